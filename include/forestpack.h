@@ -1,0 +1,229 @@
+/*
+ * forestpack -- packed decision-forest classification on AMD Instinct MI355X (gfx950).
+ *
+ * C ABI of libforestpack.so.  Plain pointers and sizes only.
+ *
+ * What is computed (Forest Packing, Browne et al., arXiv 1806.07300):
+ *   A trained forest of T decision trees (Sec. III) classifies an observation
+ *   x in R^F: in every tree the observation walks from the root to a leaf,
+ *   going to the left child when x[feature] <= threshold (fp32 compare, NaN
+ *   goes right), and the leaf's single class label (Sec. III) gets one vote.
+ *   votes[c] counts the trees voting c; the class is argmax_c votes[c] with
+ *   ties resolved to the lowest class index.  Packing (Sec. III-A) changes the
+ *   memory layout and evaluation order only, never the result (Sec. III-A,
+ *   cost model discussion), so every layout and every launch configuration
+ *   returns bit-identical int32 votes.
+ *
+ * Conventions shared by all calls:
+ *   - Every call returns an int status (FP_OK = 0 or an FP_E* code); on error
+ *     fp_last_error() returns a message (thread-local, valid until the next
+ *     call on the same thread).  No C++ exception crosses this boundary.
+ *   - Objects (fp_packed, fp_plan, fp_server) are opaque, library-owned, and
+ *     released by their *_free / *_destroy call.  They are not thread-safe,
+ *     except fp_server whose submit/poll may be called from any thread.
+ *   - Caller arrays are borrowed for the duration of the call, except where a
+ *     call says otherwise (device buffers given to fp_packed_upload and
+ *     fp_plan_create; the output buffer of fp_serve_submit).
+ *   - "device" pointers are HIP device memory of the current device (for
+ *     example torch tensors' data_ptr()); "host" pointers are CPU memory.
+ *   - `stream` is a hipStream_t passed as void* (NULL = the null stream).
+ *     Calls taking a stream are asynchronous with respect to the host and
+ *     do not synchronise the device.
+ */
+#ifndef FORESTPACK_H
+#define FORESTPACK_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ------------------------------------------------------------------------ */
+/* Status codes                                                              */
+/* ------------------------------------------------------------------------ */
+enum {
+    FP_OK = 0,
+    FP_EINVAL = 1,     /* invalid argument (null pointer, bad size, ld < n_features ...) */
+    FP_ENOMEM = 2,     /* host or device allocation failed */
+    FP_EHIP = 3,       /* a HIP runtime call failed (message names it) */
+    FP_ECORRUPT = 4,   /* malformed forest or packed buffer (range, cycle, checksum) */
+    FP_E2BIG = 5,      /* request larger than a configured limit (capacity, budget) */
+    FP_EAGAIN = 6,     /* bounded queue full: retry later */
+    FP_ENOTREADY = 7,  /* result not ready yet (poll) */
+    FP_ENODEV = 8      /* no usable gfx950 device / object not uploaded */
+};
+
+/* Message describing the last error on the calling thread ("" if none). */
+const char *fp_last_error(void);
+
+/* Library version string, "forestpack <major>.<minor> packed-format <n>". */
+const char *fp_version(void);
+
+/* ------------------------------------------------------------------------ */
+/* Trained forest (input to packing)                                          */
+/* ------------------------------------------------------------------------ */
+/*
+ * The input of packing is a trained forest of T trees (Sec. III): each
+ * internal node holds a split (feature, fp32 threshold) and two children; each
+ * leaf holds one class label (Sec. III); training cardinalities (in-bag sample
+ * counts reaching each node) drive the statistical ordering (Sec. III-A, Stat).
+ *
+ * Layout: structure of arrays, trees concatenated.  Tree t owns nodes
+ * [tree_node_offset[t], tree_node_offset[t+1]); ids inside left/right are
+ * local to the tree; local node 0 is the root.  Nodes are expected in
+ * node-creation order (breadth-first for the trainer used in the tests), but
+ * any order whose links form a tree is accepted.
+ *
+ *   feature[i]     >= 0: split feature (< n_features); < 0: leaf
+ *   threshold[i]   split threshold (fp32), ignored for leaves
+ *   left[i],right[i] local child ids of an internal node, ignored for leaves
+ *   leaf_class[i]  class of a leaf in [0, n_classes), ignored for internal nodes
+ *   cardinality[i] in-bag training count (>= 0); NULL: every leaf counts 1 and
+ *                  an internal node counts the leaves below it
+ * All arrays are host memory, borrowed during fp_pack_forest only.
+ */
+typedef struct fp_forest_view {
+    int32_t n_trees;
+    int32_t n_features;
+    int32_t n_classes;
+    int32_t reserved;
+    const int64_t *tree_node_offset; /* [n_trees + 1], [0] == 0, non-decreasing */
+    const int32_t *feature;
+    const float *threshold;
+    const int32_t *left;
+    const int32_t *right;
+    const int32_t *leaf_class;
+    const int64_t *cardinality; /* nullable */
+} fp_forest_view;
+
+/* ------------------------------------------------------------------------ */
+/* Packing                                                                    */
+/* ------------------------------------------------------------------------ */
+enum {
+    /* Baseline: every tree its own array in breadth-first order with leaves
+     * stored as nodes (the BF layout of Sec. III-A, the paper's baseline). */
+    FP_LAYOUT_NAIVE = 0,
+    /* Forest packing (Sec. III-A): leaves replaced by class references (DF-),
+     * per-tree statistical depth-first order with the more frequently taken
+     * child adjacent to its parent (Stat), trees grouped into bins whose top
+     * levels are interleaved level by level across the bin's trees (Bin). */
+    FP_LAYOUT_PACKED = 1
+};
+
+/*
+ * Packing parameters (Sec. III-A, "two parameters used when interleaving"):
+ *   bin_size          trees per bin (stripe width); <= 0 or > T: one bin of all
+ *                     trees.  Bins hold consecutive trees; the last may be short.
+ *   interleave_depth  depths 0..D of every tree in a bin are interleaved
+ *                     (D = 0: only the roots are contiguous, as in Fig. 2);
+ *                     0 <= D <= 30.
+ *   line_align        1: start each deep subtree on a 128-byte line when it
+ *                     fits in the remaining part of the current line otherwise;
+ *                     0: dense.  (Ignored by the naive layout.)
+ */
+typedef struct fp_pack_opts {
+    int32_t layout;
+    int32_t bin_size;
+    int32_t interleave_depth;
+    int32_t line_align;
+} fp_pack_opts;
+
+typedef struct fp_packed fp_packed;
+
+/* Summary of a packed forest. */
+typedef struct fp_packed_info {
+    int32_t layout, n_trees, n_features, n_classes;
+    int32_t bin_size, interleave_depth, n_bins, max_top_nodes; /* largest bin top region */
+    int64_t n_nodes;      /* stored 16-byte nodes */
+    int64_t n_internal;   /* internal nodes of the forest */
+    int64_t n_leaves;     /* leaves of the forest */
+    int64_t bytes;        /* size of the packed buffer (host and device copy) */
+    int32_t uploaded;     /* 1 once fp_packed_upload succeeded */
+    int32_t max_depth;    /* deepest leaf depth (root = 0) */
+} fp_packed_info;
+
+/*
+ * Validate and re-lay a forest (Sec. III-A).  Deterministic: equal inputs give
+ * byte-identical packed buffers.  Validation: tree offsets, feature < F,
+ * children within the tree, class < C, every node reached at most once from
+ * the root (no cycle, no shared child).  Errors: FP_EINVAL (null/size),
+ * FP_ECORRUPT (malformed forest), FP_ENOMEM.  *out is set only on FP_OK.
+ */
+int fp_pack_forest(const fp_forest_view *forest, const fp_pack_opts *opts, fp_packed **out);
+
+int fp_packed_info_get(const fp_packed *p, fp_packed_info *out);
+
+/* Host copy of the packed buffer (owned by p, valid until fp_packed_free). */
+int fp_packed_host_bytes(const fp_packed *p, const void **bytes, size_t *nbytes);
+
+/* Rebuild a packed forest from bytes written by fp_packed_host_bytes or
+ * fp_packed_save.  Verifies magic, version, sizes, checksum and every node
+ * reference; FP_ECORRUPT on any mismatch.  The bytes are copied. */
+int fp_packed_from_bytes(const void *bytes, size_t nbytes, fp_packed **out);
+
+int fp_packed_save(const fp_packed *p, const char *path);
+int fp_packed_load(const char *path, fp_packed **out);
+
+/*
+ * Copy the packed buffer to device memory `dev` (at least info.bytes bytes,
+ * 256-byte aligned, owned by the caller and kept alive while p is used) on
+ * `stream`.  p remembers dev and the current device; predictions read it.
+ * Errors: FP_EINVAL (null, misaligned), FP_E2BIG (cap too small), FP_EHIP.
+ */
+int fp_packed_upload(fp_packed *p, void *dev, size_t cap, void *stream);
+
+void fp_packed_free(fp_packed *p);
+
+/* ------------------------------------------------------------------------ */
+/* Single-forest prediction                                                   */
+/* ------------------------------------------------------------------------ */
+/*
+ * Launch parameters of the traversal kernels (the GPU form of assigning bins
+ * to workers, Sec. III, and of Bin+ round-robin evaluation, Sec. III-B).
+ *   rows_per_block  observations per workgroup (packed layout; 1..64)
+ *   cursors         trees a lane walks concurrently, round-robin (1, 2, 4, 8)
+ *   tree_groups     bins are split into this many groups, each group handled
+ *                   by its own workgroups (votes then merge with atomics);
+ *                   0: one group
+ *   block_threads   workgroup size (64..1024, multiple of 64)
+ *   lds_top_nodes   bin-top nodes staged in LDS (0: the whole top region as far
+ *                   as LDS allows; -1: none)
+ *   feature_lds     1: stage the observation tile in LDS (FP_E2BIG if it cannot
+ *                   fit); -1: read features from memory; 0: LDS when it fits
+ * Zero fields mean "library default".  Naive layout uses block_threads only.
+ */
+typedef struct fp_tune {
+    int32_t rows_per_block;
+    int32_t cursors;
+    int32_t tree_groups;
+    int32_t block_threads;
+    int32_t lds_top_nodes;
+    int32_t feature_lds;
+    int32_t reserved[2];
+} fp_tune;
+
+/* Store `tune` as the launch parameters fp_predict uses for p (NULL: defaults). */
+int fp_packed_set_tune(fp_packed *p, const fp_tune *tune);
+int fp_packed_get_tune(const fp_packed *p, fp_tune *out);
+
+/*
+ * Classify n_rows observations with the uploaded forest p.
+ *   X_dev     device fp32 [n_rows][ld], row-major; ld >= n_features
+ *   votes_dev device int32 [n_rows][n_classes], overwritten
+ *   class_dev device int32 [n_rows] (argmax, lowest index on ties) or NULL
+ * n_rows == 0 is a no-op.  Errors: FP_EINVAL (ld < F, null with n_rows > 0,
+ * n_rows > 2^31-1), FP_ENODEV (not uploaded, other device), FP_EHIP.
+ */
+int fp_predict(const fp_packed *p, const float *X_dev, int64_t n_rows, int64_t ld,
+               int32_t *votes_dev, int32_t *class_dev, void *stream);
+
+/* fp_predict with explicit launch parameters (NULL: those of p). */
+int fp_predict_tuned(const fp_packed *p, const fp_tune *tune, const float *X_dev, int64_t n_rows,
+                     int64_t ld, int32_t *votes_dev, int32_t *class_dev, void *stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* FORESTPACK_H */

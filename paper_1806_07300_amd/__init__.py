@@ -1,0 +1,290 @@
+"""forestpack: packed decision-forest classification on MI355X (gfx950).
+
+Thin ctypes binding over ``libforestpack.so`` (C ABI in include/forestpack.h).
+Every function here has the name of the C entry point it calls and only
+marshals arguments: packing runs in the library's C++ packer and every
+prediction runs in the library's HIP kernels.  PyTorch is used for device
+memory (tensors' ``data_ptr()``) and streams (``torch.cuda.current_stream()``).
+If the library is missing, importing works but every call raises: there is no
+CPU fallback.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libforestpack.so")
+
+FP_OK, FP_EINVAL, FP_ENOMEM, FP_EHIP, FP_ECORRUPT, FP_E2BIG, FP_EAGAIN, FP_ENOTREADY, FP_ENODEV = range(9)
+FP_LAYOUT_NAIVE, FP_LAYOUT_PACKED = 0, 1
+ERROR_NAMES = {0: "FP_OK", 1: "FP_EINVAL", 2: "FP_ENOMEM", 3: "FP_EHIP", 4: "FP_ECORRUPT",
+               5: "FP_E2BIG", 6: "FP_EAGAIN", 7: "FP_ENOTREADY", 8: "FP_ENODEV"}
+
+
+class FPError(RuntimeError):
+    def __init__(self, code: int, where: str, msg: str):
+        super().__init__(f"{where}: {ERROR_NAMES.get(code, code)}: {msg}")
+        self.code = code
+
+
+# ---------------------------------------------------------------------------
+# C structures (mirror include/forestpack.h)
+# ---------------------------------------------------------------------------
+_vp = ctypes.c_void_p
+_i32, _i64 = ctypes.c_int32, ctypes.c_int64
+
+
+class fp_forest_view(ctypes.Structure):
+    _fields_ = [("n_trees", _i32), ("n_features", _i32), ("n_classes", _i32), ("reserved", _i32),
+                ("tree_node_offset", _vp), ("feature", _vp), ("threshold", _vp), ("left", _vp),
+                ("right", _vp), ("leaf_class", _vp), ("cardinality", _vp)]
+
+
+class fp_pack_opts(ctypes.Structure):
+    _fields_ = [("layout", _i32), ("bin_size", _i32), ("interleave_depth", _i32), ("line_align", _i32)]
+
+
+class fp_packed_info(ctypes.Structure):
+    _fields_ = [("layout", _i32), ("n_trees", _i32), ("n_features", _i32), ("n_classes", _i32),
+                ("bin_size", _i32), ("interleave_depth", _i32), ("n_bins", _i32), ("max_top_nodes", _i32),
+                ("n_nodes", _i64), ("n_internal", _i64), ("n_leaves", _i64), ("bytes", _i64),
+                ("uploaded", _i32), ("max_depth", _i32)]
+
+
+class fp_tune(ctypes.Structure):
+    _fields_ = [("rows_per_block", _i32), ("cursors", _i32), ("tree_groups", _i32),
+                ("block_threads", _i32), ("lds_top_nodes", _i32), ("feature_lds", _i32),
+                ("reserved", _i32 * 2)]
+
+
+TUNE_FIELDS = [f for f, _ in fp_tune._fields_ if f != "reserved"]
+
+_lib = None
+
+
+def lib():
+    """The loaded library; raises if it has not been built."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise FPError(FP_ENODEV, "load", f"{LIB_PATH} is missing: run __graft_entry__.build()")
+        L = ctypes.CDLL(LIB_PATH)
+        sig = {
+            "fp_last_error": ([], ctypes.c_char_p),
+            "fp_version": ([], ctypes.c_char_p),
+            "fp_pack_forest": ([ctypes.POINTER(fp_forest_view), ctypes.POINTER(fp_pack_opts), ctypes.POINTER(_vp)], ctypes.c_int),
+            "fp_packed_info_get": ([_vp, ctypes.POINTER(fp_packed_info)], ctypes.c_int),
+            "fp_packed_host_bytes": ([_vp, ctypes.POINTER(_vp), ctypes.POINTER(ctypes.c_size_t)], ctypes.c_int),
+            "fp_packed_from_bytes": ([_vp, ctypes.c_size_t, ctypes.POINTER(_vp)], ctypes.c_int),
+            "fp_packed_save": ([_vp, ctypes.c_char_p], ctypes.c_int),
+            "fp_packed_load": ([ctypes.c_char_p, ctypes.POINTER(_vp)], ctypes.c_int),
+            "fp_packed_upload": ([_vp, _vp, ctypes.c_size_t, _vp], ctypes.c_int),
+            "fp_packed_free": ([_vp], None),
+            "fp_packed_set_tune": ([_vp, ctypes.POINTER(fp_tune)], ctypes.c_int),
+            "fp_packed_get_tune": ([_vp, ctypes.POINTER(fp_tune)], ctypes.c_int),
+            "fp_predict": ([_vp, _vp, _i64, _i64, _vp, _vp, _vp], ctypes.c_int),
+            "fp_predict_tuned": ([_vp, ctypes.POINTER(fp_tune), _vp, _i64, _i64, _vp, _vp, _vp], ctypes.c_int),
+        }
+        for name, (args, res) in sig.items():
+            fn = getattr(L, name)
+            fn.argtypes = args
+            fn.restype = res
+        _lib = L
+    return _lib
+
+
+def _check(rc: int, where: str):
+    if rc != FP_OK:
+        msg = lib().fp_last_error().decode(errors="replace")
+        raise FPError(rc, where, msg)
+
+
+def fp_last_error() -> str:
+    return lib().fp_last_error().decode()
+
+
+def fp_version() -> str:
+    return lib().fp_version().decode()
+
+
+# ---------------------------------------------------------------------------
+# packed forest handle
+# ---------------------------------------------------------------------------
+class Packed:
+    """Owns an ``fp_packed*`` and (after upload) the device tensor holding its bytes."""
+
+    def __init__(self, handle: int):
+        self.handle = _vp(handle)
+        self.device_buffer = None  # torch uint8 tensor, kept alive while uploaded
+
+    def __del__(self):
+        h = getattr(self, "handle", None)
+        if h is not None and h.value and _lib is not None:
+            _lib.fp_packed_free(h)
+            self.handle = None
+
+    @property
+    def info(self) -> dict:
+        return fp_packed_info_get(self)
+
+
+def _view_from(forest):
+    arrs = {}
+    for k, dt in (("tree_node_offset", np.int64), ("feature", np.int32), ("threshold", np.float32),
+                  ("left", np.int32), ("right", np.int32), ("leaf_class", np.int32)):
+        arrs[k] = np.ascontiguousarray(getattr(forest, k), dtype=dt)
+    card = getattr(forest, "cardinality", None)
+    if card is not None:
+        arrs["cardinality"] = np.ascontiguousarray(card, dtype=np.int64)
+    v = fp_forest_view(int(forest.n_trees), int(forest.n_features), int(forest.n_classes), 0,
+                       *(arrs[k].ctypes.data for k in ("tree_node_offset", "feature", "threshold",
+                                                        "left", "right", "leaf_class")),
+                       arrs["cardinality"].ctypes.data if card is not None else None)
+    return v, arrs
+
+
+def fp_pack_forest(forest, layout: int = FP_LAYOUT_PACKED, bin_size: int = 16,
+                   interleave_depth: int = 3, line_align: int = 0, use_cardinality: bool = True) -> Packed:
+    """Pack a trained forest (any object with the fp_forest_view arrays as attributes)."""
+    if not use_cardinality:
+        class _NoCard:
+            pass
+        f2 = _NoCard()
+        for k in ("n_trees", "n_features", "n_classes", "tree_node_offset", "feature", "threshold",
+                  "left", "right", "leaf_class"):
+            setattr(f2, k, getattr(forest, k))
+        f2.cardinality = None
+        forest = f2
+    view, keep = _view_from(forest)
+    opts = fp_pack_opts(layout, bin_size, interleave_depth, line_align)
+    out = _vp()
+    _check(lib().fp_pack_forest(ctypes.byref(view), ctypes.byref(opts), ctypes.byref(out)), "fp_pack_forest")
+    del keep
+    return Packed(out.value)
+
+
+def fp_packed_free(p: Packed) -> None:
+    """Release the packed forest now (otherwise released when garbage collected)."""
+    if p.handle is not None and p.handle.value:
+        lib().fp_packed_free(p.handle)
+    p.handle = None
+    p.device_buffer = None
+
+
+def fp_packed_info_get(p: Packed) -> dict:
+    info = fp_packed_info()
+    _check(lib().fp_packed_info_get(p.handle, ctypes.byref(info)), "fp_packed_info_get")
+    return {f: getattr(info, f) for f, _ in fp_packed_info._fields_}
+
+
+def fp_packed_host_bytes(p: Packed) -> np.ndarray:
+    ptr, n = _vp(), ctypes.c_size_t()
+    _check(lib().fp_packed_host_bytes(p.handle, ctypes.byref(ptr), ctypes.byref(n)), "fp_packed_host_bytes")
+    return np.ctypeslib.as_array(ctypes.cast(ptr, ctypes.POINTER(ctypes.c_uint8)), (n.value,)).copy()
+
+
+def fp_packed_from_bytes(buf) -> Packed:
+    b = np.ascontiguousarray(np.frombuffer(buf, np.uint8) if not isinstance(buf, np.ndarray) else buf, np.uint8)
+    out = _vp()
+    _check(lib().fp_packed_from_bytes(b.ctypes.data, b.nbytes, ctypes.byref(out)), "fp_packed_from_bytes")
+    return Packed(out.value)
+
+
+def fp_packed_save(p: Packed, path: str) -> None:
+    _check(lib().fp_packed_save(p.handle, path.encode()), "fp_packed_save")
+
+
+def fp_packed_load(path: str) -> Packed:
+    out = _vp()
+    _check(lib().fp_packed_load(path.encode(), ctypes.byref(out)), "fp_packed_load")
+    return Packed(out.value)
+
+
+def _stream_ptr(stream):
+    import torch
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return _vp(stream.cuda_stream)
+
+
+def fp_packed_upload(p: Packed, dev_tensor=None, stream=None) -> Packed:
+    """Copy the packed bytes to the GPU; allocates a torch uint8 buffer unless one is given."""
+    import torch
+    nbytes = fp_packed_info_get(p)["bytes"]
+    if dev_tensor is None:
+        dev_tensor = torch.empty(nbytes, dtype=torch.uint8, device="cuda")
+    if not dev_tensor.is_cuda or dev_tensor.dtype != torch.uint8:
+        raise FPError(FP_EINVAL, "fp_packed_upload", "device buffer must be a CUDA uint8 tensor")
+    cap = dev_tensor.numel()
+    _check(lib().fp_packed_upload(p.handle, _vp(dev_tensor.data_ptr()), cap, _stream_ptr(stream)),
+           "fp_packed_upload")
+    p.device_buffer = dev_tensor
+    return p
+
+
+def _tune_struct(tune):
+    if tune is None:
+        return None
+    if isinstance(tune, fp_tune):
+        return tune
+    t = fp_tune()
+    for k, v in dict(tune).items():
+        if k not in TUNE_FIELDS:
+            raise FPError(FP_EINVAL, "fp_tune", f"unknown field {k}")
+        setattr(t, k, int(v))
+    return t
+
+
+def fp_packed_set_tune(p: Packed, tune) -> None:
+    t = _tune_struct(tune)
+    _check(lib().fp_packed_set_tune(p.handle, ctypes.byref(t) if t is not None else None), "fp_packed_set_tune")
+
+
+def fp_packed_get_tune(p: Packed) -> dict:
+    t = fp_tune()
+    _check(lib().fp_packed_get_tune(p.handle, ctypes.byref(t)), "fp_packed_get_tune")
+    return {k: getattr(t, k) for k in TUNE_FIELDS}
+
+
+def _check_rows(X, n_features):
+    import torch
+    if not (isinstance(X, torch.Tensor) and X.is_cuda and X.dtype == torch.float32 and X.dim() == 2):
+        raise FPError(FP_EINVAL, "fp_predict", "X must be a 2-D float32 CUDA tensor")
+    if X.stride(1) != 1:
+        raise FPError(FP_EINVAL, "fp_predict", "X rows must be contiguous (stride(1) == 1)")
+    ld = X.stride(0) if X.shape[0] > 1 else max(X.shape[1], n_features)
+    return X.shape[0], ld
+
+
+def _outputs(n, C, votes, cls, want_cls):
+    import torch
+    if votes is None:
+        votes = torch.empty((n, C), dtype=torch.int32, device="cuda")
+    if cls is None and want_cls:
+        cls = torch.empty((n,), dtype=torch.int32, device="cuda")
+    return votes, cls
+
+
+def fp_predict(p: Packed, X, votes=None, cls=None, stream=None, want_cls: bool = True):
+    """votes int32 [n, C] and argmax class int32 [n] (CUDA tensors) for rows X (CUDA fp32 [n, >=F])."""
+    info = fp_packed_info_get(p)
+    n, ld = _check_rows(X, info["n_features"])
+    votes, cls = _outputs(n, info["n_classes"], votes, cls, want_cls)
+    _check(lib().fp_predict(p.handle, _vp(X.data_ptr()), n, ld, _vp(votes.data_ptr()),
+                            _vp(cls.data_ptr()) if cls is not None else None, _stream_ptr(stream)), "fp_predict")
+    return votes, cls
+
+
+def fp_predict_tuned(p: Packed, tune, X, votes=None, cls=None, stream=None, want_cls: bool = True):
+    """fp_predict with explicit launch parameters (dict with fp_tune fields)."""
+    info = fp_packed_info_get(p)
+    n, ld = _check_rows(X, info["n_features"])
+    votes, cls = _outputs(n, info["n_classes"], votes, cls, want_cls)
+    t = _tune_struct(tune)
+    _check(lib().fp_predict_tuned(p.handle, ctypes.byref(t) if t is not None else None, _vp(X.data_ptr()), n, ld,
+                                  _vp(votes.data_ptr()), _vp(cls.data_ptr()) if cls is not None else None,
+                                  _stream_ptr(stream)), "fp_predict_tuned")
+    return votes, cls

@@ -1,0 +1,613 @@
+// Host packer: validates a trained forest and re-lays it (Sec. III-A).
+//
+//   NAIVE  : per-tree breadth-first arrays with leaves stored as nodes, the
+//            BF baseline layout that the paper measures everything against.
+//   PACKED : DF-  -- leaves are not stored; a child that is a leaf becomes the
+//                    reference "class c" (-c-1), one shared class node per class
+//                    as in DF- but needing no storage at all;
+//            Stat -- below the interleaved levels, each tree is laid out depth
+//                    first with the child reached by more training samples
+//                    placed right after its parent (an internal child always
+//                    wins over a leaf sibling, which is folded away);
+//            Bin  -- trees are grouped into bins of B consecutive trees; depths
+//                    0..D of all trees of a bin are interleaved level-major
+//                    (all depth-0 nodes of the bin's trees, then all depth-1
+//                    nodes, ...), each tree's nodes of one depth in
+//                    breadth-first order, so the most used nodes of many trees
+//                    share lines.  The kernels stage this top region in LDS.
+//
+// Every internal node index in a bin is larger than its parent's: children
+// always come later (level-major top, pre-order deep region), which the
+// verifier checks, so every walk terminates.
+#include <hip/hip_runtime_api.h>
+
+#include <algorithm>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <deque>
+#include <memory>
+#include <new>
+
+#include "fp_internal.h"
+
+using fp::BinEntry;
+using fp::Header;
+using fp::Node16;
+
+// ---------------------------------------------------------------------------
+// errors
+// ---------------------------------------------------------------------------
+static thread_local std::string g_last_error;
+
+int fp_set_error(int code, const char* fmt, ...) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_last_error = buf;
+    return code;
+}
+void fp_clear_error() { g_last_error.clear(); }
+
+extern "C" const char* fp_last_error(void) { return g_last_error.c_str(); }
+extern "C" const char* fp_version(void) { return "forestpack 0.1 packed-format 1"; }
+
+namespace fp {
+
+uint64_t fnv1a64(const uint8_t* p, size_t n) {
+    // FNV-1a over little-endian 64-bit words (n is a multiple of 8 here).
+    uint64_t h = 0xcbf29ce484222325ull;
+    size_t w = n / 8;
+    const uint64_t prime = 0x100000001b3ull;
+    for (size_t i = 0; i < w; i++) {
+        uint64_t v;
+        memcpy(&v, p + 8 * i, 8);
+        h = (h ^ v) * prime;
+    }
+    for (size_t i = 8 * w; i < n; i++) h = (h ^ p[i]) * prime;
+    return h;
+}
+
+static size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
+
+namespace {
+
+// Per-tree structure recovered from the view.
+struct TreeShape {
+    int64_t base = 0, size = 0;
+    std::vector<int32_t> bfs;     // reachable nodes, breadth-first, left before right
+    std::vector<int32_t> depth;   // per local node (-1 unreachable)
+    std::vector<int64_t> card;    // subtree cardinality per local node
+    int64_t n_internal = 0, n_leaves = 0;
+    int32_t max_depth = 0;
+};
+
+bool is_internal(const fp_forest_view* v, const TreeShape& t, int32_t n) {
+    return v->feature[t.base + n] >= 0;
+}
+
+int validate_tree(const fp_forest_view* v, int32_t ti, TreeShape* t) {
+    const int64_t base = v->tree_node_offset[ti];
+    const int64_t size = v->tree_node_offset[ti + 1] - base;
+    if (size < 1)
+        return fp_set_error(FP_ECORRUPT, "tree %d has no nodes", ti);
+    if (size > INT32_MAX / 2)
+        return fp_set_error(FP_E2BIG, "tree %d has %lld nodes (limit %d)", ti, (long long)size,
+                            INT32_MAX / 2);
+    t->base = base;
+    t->size = size;
+    t->depth.assign(size, -1);
+    t->bfs.clear();
+    t->bfs.reserve(size);
+    std::deque<int32_t> q;
+    q.push_back(0);
+    t->depth[0] = 0;
+    while (!q.empty()) {
+        int32_t n = q.front();
+        q.pop_front();
+        t->bfs.push_back(n);
+        const int64_t g = base + n;
+        const int32_t f = v->feature[g];
+        if (f >= 0) {
+            if (f >= v->n_features)
+                return fp_set_error(FP_ECORRUPT, "tree %d node %d: feature %d >= n_features %d", ti,
+                                    n, f, v->n_features);
+            const int32_t ch[2] = {v->left[g], v->right[g]};
+            for (int k = 0; k < 2; k++) {
+                if (ch[k] < 0 || ch[k] >= size)
+                    return fp_set_error(FP_ECORRUPT, "tree %d node %d: child %d out of range [0,%lld)",
+                                        ti, n, ch[k], (long long)size);
+                if (t->depth[ch[k]] >= 0)
+                    return fp_set_error(FP_ECORRUPT,
+                                        "tree %d node %d: child %d reached twice (cycle or shared node)",
+                                        ti, n, ch[k]);
+                t->depth[ch[k]] = t->depth[n] + 1;
+                q.push_back(ch[k]);
+            }
+            t->n_internal++;
+        } else {
+            const int32_t c = v->leaf_class[g];
+            if (c < 0 || c >= v->n_classes)
+                return fp_set_error(FP_ECORRUPT, "tree %d leaf %d: class %d outside [0,%d)", ti, n, c,
+                                    v->n_classes);
+            t->n_leaves++;
+            t->max_depth = std::max(t->max_depth, t->depth[n]);
+        }
+    }
+    // subtree cardinalities, children before parents (reverse breadth-first)
+    t->card.assign(size, 0);
+    for (auto it = t->bfs.rbegin(); it != t->bfs.rend(); ++it) {
+        const int32_t n = *it;
+        const int64_t g = base + n;
+        if (v->feature[g] >= 0) {
+            t->card[n] = v->cardinality ? v->cardinality[g]
+                                        : t->card[v->left[g]] + t->card[v->right[g]];
+        } else {
+            t->card[n] = v->cardinality ? v->cardinality[g] : 1;
+        }
+        if (t->card[n] < 0)
+            return fp_set_error(FP_ECORRUPT, "tree %d node %d: negative cardinality", ti, n);
+    }
+    return FP_OK;
+}
+
+int validate_view(const fp_forest_view* v, std::vector<TreeShape>* shapes) {
+    if (!v) return fp_set_error(FP_EINVAL, "forest view is NULL");
+    if (v->n_trees < 1 || v->n_features < 1 || v->n_classes < 1)
+        return fp_set_error(FP_EINVAL, "need n_trees, n_features, n_classes >= 1 (got %d, %d, %d)",
+                            v->n_trees, v->n_features, v->n_classes);
+    if (v->n_classes > kMaxClasses)
+        return fp_set_error(FP_E2BIG, "n_classes %d exceeds %d", v->n_classes, kMaxClasses);
+    if (!v->tree_node_offset || !v->feature || !v->threshold || !v->left || !v->right ||
+        !v->leaf_class)
+        return fp_set_error(FP_EINVAL, "forest view has a NULL array");
+    if (v->tree_node_offset[0] != 0)
+        return fp_set_error(FP_ECORRUPT, "tree_node_offset[0] must be 0");
+    for (int32_t t = 0; t < v->n_trees; t++)
+        if (v->tree_node_offset[t + 1] < v->tree_node_offset[t])
+            return fp_set_error(FP_ECORRUPT, "tree_node_offset decreases at tree %d", t);
+    shapes->resize(v->n_trees);
+    for (int32_t t = 0; t < v->n_trees; t++) {
+        int rc = validate_tree(v, t, &(*shapes)[t]);
+        if (rc) return rc;
+    }
+    return FP_OK;
+}
+
+void fill_header_common(Header* h, const fp_forest_view* v, const std::vector<TreeShape>& s,
+                        int32_t layout) {
+    memset(h, 0, sizeof *h);
+    h->magic = kMagic;
+    h->version = kFormatVersion;
+    h->layout = layout;
+    h->n_trees = v->n_trees;
+    h->n_features = v->n_features;
+    h->n_classes = v->n_classes;
+    for (const auto& t : s) {
+        h->n_internal += t.n_internal;
+        h->n_leaves += t.n_leaves;
+        h->max_depth = std::max(h->max_depth, t.max_depth);
+    }
+}
+
+void finish(std::vector<uint8_t>* bytes, Header* h) {
+    h->total_bytes = (int64_t)bytes->size();
+    h->checksum = fnv1a64(bytes->data() + sizeof(Header), bytes->size() - sizeof(Header));
+    memcpy(bytes->data(), h, sizeof *h);
+}
+
+int pack_naive(const fp_forest_view* v, const std::vector<TreeShape>& s, std::vector<uint8_t>* out,
+               Header* h) {
+    fill_header_common(h, v, s, FP_LAYOUT_NAIVE);
+    int64_t n_nodes = 0;
+    for (const auto& t : s) n_nodes += (int64_t)t.bfs.size();
+    const size_t table_off = sizeof(Header);
+    const size_t nodes_off = align_up(table_off + sizeof(int64_t) * (v->n_trees + 1), kSectionAlign);
+    const size_t total = align_up(nodes_off + sizeof(Node16) * (size_t)n_nodes, kSectionAlign);
+    out->assign(total, 0);
+    int64_t* offs = reinterpret_cast<int64_t*>(out->data() + table_off);
+    Node16* nodes = reinterpret_cast<Node16*>(out->data() + nodes_off);
+    int64_t o = 0;
+    std::vector<int32_t> pos;
+    for (int32_t ti = 0; ti < v->n_trees; ti++) {
+        const TreeShape& t = s[ti];
+        offs[ti] = o;
+        pos.assign(t.size, -1);
+        for (size_t k = 0; k < t.bfs.size(); k++) pos[t.bfs[k]] = (int32_t)k;
+        for (size_t k = 0; k < t.bfs.size(); k++) {
+            const int64_t g = t.base + t.bfs[k];
+            Node16& nd = nodes[o + (int64_t)k];
+            if (v->feature[g] >= 0) {
+                nd.thr = v->threshold[g];
+                nd.feat = v->feature[g];
+                nd.left = pos[v->left[g]];
+                nd.right = pos[v->right[g]];
+            } else {
+                nd.thr = 0.0f;
+                nd.feat = -1;
+                nd.left = v->leaf_class[g];
+                nd.right = v->leaf_class[g];
+            }
+        }
+        o += (int64_t)t.bfs.size();
+    }
+    offs[v->n_trees] = o;
+    h->bin_size = 1;
+    h->interleave_depth = 0;
+    h->n_bins = v->n_trees;
+    h->table_offset = (int64_t)table_off;
+    h->roots_offset = 0;
+    h->nodes_offset = (int64_t)nodes_off;
+    h->n_nodes = n_nodes;
+    finish(out, h);
+    return FP_OK;
+}
+
+int pack_packed(const fp_forest_view* v, const std::vector<TreeShape>& s, const fp_pack_opts* o,
+                std::vector<uint8_t>* out, Header* h) {
+    const int32_t T = v->n_trees;
+    const int32_t B = (o->bin_size <= 0 || o->bin_size > T) ? T : o->bin_size;
+    const int32_t D = o->interleave_depth;
+    const bool align_lines = o->line_align != 0;
+    const int32_t n_bins = (T + B - 1) / B;
+    fill_header_common(h, v, s, FP_LAYOUT_PACKED);
+
+    // 1) positions of every internal node, bin by bin
+    std::vector<std::vector<int32_t>> pos(T);
+    std::vector<BinEntry> bins(n_bins);
+    int64_t node_cursor = 0;
+    int32_t max_top = 0;
+    std::vector<int32_t> stack;
+    for (int32_t b = 0; b < n_bins; b++) {
+        BinEntry& be = bins[b];
+        be.first_tree = b * B;
+        be.n_trees = std::min(B, T - b * B);
+        be.root_base = be.first_tree;
+        node_cursor = (int64_t)align_up((size_t)node_cursor, 8);  // bins start on a 128 B line
+        be.node_base = node_cursor;
+        int64_t next = 0;
+        for (int32_t j = 0; j < be.n_trees; j++) pos[be.first_tree + j].assign(s[be.first_tree + j].size, -1);
+        // top region: level-major, tree-minor, breadth-first inside a (depth, tree)
+        for (int32_t d = 0; d <= D; d++)
+            for (int32_t j = 0; j < be.n_trees; j++) {
+                const int32_t ti = be.first_tree + j;
+                const TreeShape& t = s[ti];
+                for (int32_t n : t.bfs) {
+                    if (t.depth[n] > d) break;  // bfs is sorted by depth
+                    if (t.depth[n] == d && is_internal(v, t, n)) pos[ti][n] = (int32_t)next++;
+                }
+            }
+        be.top_len = (int32_t)next;
+        max_top = std::max(max_top, be.top_len);
+        // deep region: per tree, each subtree hanging below depth D in Stat order
+        for (int32_t j = 0; j < be.n_trees; j++) {
+            const int32_t ti = be.first_tree + j;
+            const TreeShape& t = s[ti];
+            auto emit_subtree = [&](int32_t root) {
+                if (align_lines) next = (int64_t)align_up((size_t)next, 8);
+                stack.clear();
+                stack.push_back(root);
+                while (!stack.empty()) {
+                    const int32_t n = stack.back();
+                    stack.pop_back();
+                    pos[ti][n] = (int32_t)next++;
+                    const int64_t g = t.base + n;
+                    const int32_t l = v->left[g], r = v->right[g];
+                    const bool li = is_internal(v, t, l), ri = is_internal(v, t, r);
+                    if (li && ri) {
+                        // hot child (more training samples; ties -> left) goes right after n
+                        const bool left_hot = t.card[l] >= t.card[r];
+                        stack.push_back(left_hot ? r : l);
+                        stack.push_back(left_hot ? l : r);
+                    } else if (li) {
+                        stack.push_back(l);
+                    } else if (ri) {
+                        stack.push_back(r);
+                    }
+                }
+            };
+            for (int32_t n : t.bfs) {
+                if (t.depth[n] > D) break;
+                if (t.depth[n] != D || !is_internal(v, t, n)) continue;
+                const int64_t g = t.base + n;
+                if (is_internal(v, t, v->left[g])) emit_subtree(v->left[g]);
+                if (is_internal(v, t, v->right[g])) emit_subtree(v->right[g]);
+            }
+        }
+        if (next > INT32_MAX)
+            return fp_set_error(FP_E2BIG, "bin %d holds %lld nodes (limit %d)", b, (long long)next,
+                                INT32_MAX);
+        be.deep_len = (int32_t)(next - be.top_len);
+        node_cursor += next;
+    }
+    const int64_t n_nodes = node_cursor;
+
+    // 2) buffer
+    const size_t table_off = sizeof(Header);
+    const size_t roots_off = align_up(table_off + sizeof(BinEntry) * (size_t)n_bins, kSectionAlign);
+    const size_t nodes_off = align_up(roots_off + sizeof(int32_t) * (size_t)T, kSectionAlign);
+    const size_t total = align_up(nodes_off + sizeof(Node16) * (size_t)n_nodes, kSectionAlign);
+    try {
+        out->assign(total, 0);
+    } catch (const std::bad_alloc&) {
+        return fp_set_error(FP_ENOMEM, "cannot allocate %zu bytes for the packed forest", total);
+    }
+    memcpy(out->data() + table_off, bins.data(), sizeof(BinEntry) * (size_t)n_bins);
+    int32_t* roots = reinterpret_cast<int32_t*>(out->data() + roots_off);
+    Node16* nodes = reinterpret_cast<Node16*>(out->data() + nodes_off);
+    for (int32_t b = 0; b < n_bins; b++) {
+        const BinEntry& be = bins[b];
+        Node16* bn = nodes + be.node_base;
+        for (int32_t j = 0; j < be.n_trees; j++) {
+            const int32_t ti = be.first_tree + j;
+            const TreeShape& t = s[ti];
+            const std::vector<int32_t>& p = pos[ti];
+            auto ref = [&](int32_t child) -> int32_t {
+                const int64_t g = t.base + child;
+                return v->feature[g] >= 0 ? p[child] : -v->leaf_class[g] - 1;
+            };
+            roots[ti] = ref(0);
+            for (int32_t n : t.bfs) {
+                if (!is_internal(v, t, n)) continue;
+                const int64_t g = t.base + n;
+                Node16& nd = bn[p[n]];
+                nd.thr = v->threshold[g];
+                nd.feat = v->feature[g];
+                nd.left = ref(v->left[g]);
+                nd.right = ref(v->right[g]);
+            }
+        }
+    }
+    h->bin_size = B;
+    h->interleave_depth = D;
+    h->n_bins = n_bins;
+    h->max_top_len = max_top;
+    h->max_bin_trees = B;
+    h->line_align = align_lines ? 1 : 0;
+    h->table_offset = (int64_t)table_off;
+    h->roots_offset = (int64_t)roots_off;
+    h->nodes_offset = (int64_t)nodes_off;
+    h->n_nodes = n_nodes;
+    finish(out, h);
+    return FP_OK;
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// verification of a packed buffer (used on every buffer built from bytes)
+// ---------------------------------------------------------------------------
+int verify_buffer(const uint8_t* bytes, size_t n, std::string* why) {
+    char buf[256];
+#define bad(...) (snprintf(buf, sizeof buf, __VA_ARGS__), *why = buf, FP_ECORRUPT)
+    if (n < sizeof(Header)) return bad("buffer of %zu bytes is shorter than the header", n);
+    Header h;
+    memcpy(&h, bytes, sizeof h);
+    if (h.magic != kMagic) return bad("bad magic");
+    if (h.version != kFormatVersion) return bad("format version %u, expected %u", h.version, kFormatVersion);
+    if (h.total_bytes != (int64_t)n) return bad("size %zu != header size %lld", n, (long long)h.total_bytes);
+    if (h.n_trees < 1 || h.n_features < 1 || h.n_classes < 1 || h.n_classes > kMaxClasses)
+        return bad("bad forest dimensions");
+    if (fnv1a64(bytes + sizeof(Header), n - sizeof(Header)) != h.checksum) return bad("checksum mismatch");
+    const int64_t N = h.n_nodes;
+    if (N < 0 || h.nodes_offset < (int64_t)sizeof(Header) || h.nodes_offset % 256 ||
+        h.nodes_offset + N * (int64_t)sizeof(Node16) > (int64_t)n)
+        return bad("node section out of bounds");
+    const Node16* nodes = reinterpret_cast<const Node16*>(bytes + h.nodes_offset);
+    const int32_t C = h.n_classes, F = h.n_features;
+    if (h.layout == FP_LAYOUT_NAIVE) {
+        if (h.table_offset + (int64_t)sizeof(int64_t) * (h.n_trees + 1) > h.nodes_offset)
+            return bad("tree table out of bounds");
+        const int64_t* offs = reinterpret_cast<const int64_t*>(bytes + h.table_offset);
+        if (offs[0] != 0 || offs[h.n_trees] != N) return bad("tree table endpoints");
+        for (int32_t t = 0; t < h.n_trees; t++) {
+            const int64_t lo = offs[t], hi = offs[t + 1];
+            if (hi <= lo) return bad("tree %d empty or reversed", t);
+            for (int64_t i = lo; i < hi; i++) {
+                const Node16& nd = nodes[i];
+                const int64_t self = i - lo;
+                if (nd.feat < 0) {
+                    if (nd.left < 0 || nd.left >= C) return bad("tree %d leaf %lld class", t, (long long)self);
+                } else {
+                    if (nd.feat >= F) return bad("tree %d node %lld feature", t, (long long)self);
+                    if (nd.left <= self || nd.left >= hi - lo || nd.right <= self || nd.right >= hi - lo)
+                        return bad("tree %d node %lld child not after it", t, (long long)self);
+                }
+            }
+        }
+        return FP_OK;
+    }
+    if (h.layout != FP_LAYOUT_PACKED) return bad("unknown layout %d", h.layout);
+    if (h.n_bins < 1 || h.table_offset + (int64_t)sizeof(BinEntry) * h.n_bins > h.roots_offset ||
+        h.roots_offset + (int64_t)sizeof(int32_t) * h.n_trees > h.nodes_offset)
+        return bad("bin/root tables out of bounds");
+    const BinEntry* bins = reinterpret_cast<const BinEntry*>(bytes + h.table_offset);
+    const int32_t* roots = reinterpret_cast<const int32_t*>(bytes + h.roots_offset);
+    int32_t tree_cursor = 0;
+    int32_t max_top = 0, max_trees = 0;
+    for (int32_t b = 0; b < h.n_bins; b++) {
+        const BinEntry& be = bins[b];
+        if (be.first_tree != tree_cursor || be.n_trees < 1 || be.root_base != be.first_tree)
+            return bad("bin %d tree range", b);
+        tree_cursor += be.n_trees;
+        if (be.top_len < 0 || be.deep_len < 0 || be.node_base < 0 || be.node_base % 8 ||
+            be.node_base + (int64_t)be.top_len + be.deep_len > N)
+            return bad("bin %d node range", b);
+        const int64_t len = (int64_t)be.top_len + be.deep_len;
+        max_top = std::max(max_top, be.top_len);
+        max_trees = std::max(max_trees, be.n_trees);
+        auto ref_ok = [&](int32_t r, int64_t self) { return r < 0 ? (-(int64_t)r - 1) < C : (r > self && r < len); };
+        for (int32_t j = 0; j < be.n_trees; j++)
+            if (!ref_ok(roots[be.first_tree + j], -1)) return bad("bin %d root %d", b, j);
+        const Node16* bn = nodes + be.node_base;
+        for (int64_t i = 0; i < len; i++) {
+            const Node16& nd = bn[i];
+            if (nd.feat < 0 || nd.feat >= F) {
+                // padding slots between aligned subtrees are all-zero and unreferenced;
+                // a real node must have a valid feature
+                if (!(nd.feat == 0 && nd.left == 0 && nd.right == 0)) return bad("bin %d node %lld feature", b, (long long)i);
+                continue;
+            }
+            if (!(nd.feat == 0 && nd.left == 0 && nd.right == 0) && (!ref_ok(nd.left, i) || !ref_ok(nd.right, i)))
+                return bad("bin %d node %lld reference", b, (long long)i);
+        }
+    }
+    if (tree_cursor != h.n_trees) return bad("bins cover %d of %d trees", tree_cursor, h.n_trees);
+    if (max_top != h.max_top_len || max_trees > h.max_bin_trees) return bad("bin maxima");
+    return FP_OK;
+#undef bad
+}
+
+}  // namespace fp
+
+// ---------------------------------------------------------------------------
+// C ABI
+// ---------------------------------------------------------------------------
+extern "C" int fp_pack_forest(const fp_forest_view* forest, const fp_pack_opts* opts, fp_packed** out) {
+    fp_clear_error();
+    if (!out) return fp_set_error(FP_EINVAL, "out is NULL");
+    *out = nullptr;
+    if (!opts) return fp_set_error(FP_EINVAL, "opts is NULL");
+    if (opts->layout != FP_LAYOUT_NAIVE && opts->layout != FP_LAYOUT_PACKED)
+        return fp_set_error(FP_EINVAL, "unknown layout %d", opts->layout);
+    if (opts->layout == FP_LAYOUT_PACKED && (opts->interleave_depth < 0 || opts->interleave_depth > 30))
+        return fp_set_error(FP_EINVAL, "interleave_depth %d outside [0, 30]", opts->interleave_depth);
+    try {
+        std::vector<fp::TreeShape> shapes;
+        int rc = fp::validate_view(forest, &shapes);
+        if (rc) return rc;
+        std::unique_ptr<fp_packed> p(new fp_packed());
+        rc = opts->layout == FP_LAYOUT_NAIVE ? fp::pack_naive(forest, shapes, &p->bytes, &p->hdr)
+                                             : fp::pack_packed(forest, shapes, opts, &p->bytes, &p->hdr);
+        if (rc) return rc;
+        *out = p.release();
+        return FP_OK;
+    } catch (const std::bad_alloc&) {
+        return fp_set_error(FP_ENOMEM, "out of host memory while packing");
+    }
+}
+
+extern "C" int fp_packed_info_get(const fp_packed* p, fp_packed_info* out) {
+    fp_clear_error();
+    if (!p || !out) return fp_set_error(FP_EINVAL, "NULL argument");
+    const fp::Header& h = p->hdr;
+    memset(out, 0, sizeof *out);
+    out->layout = h.layout;
+    out->n_trees = h.n_trees;
+    out->n_features = h.n_features;
+    out->n_classes = h.n_classes;
+    out->bin_size = h.bin_size;
+    out->interleave_depth = h.interleave_depth;
+    out->n_bins = h.n_bins;
+    out->max_top_nodes = h.max_top_len;
+    out->n_nodes = h.n_nodes;
+    out->n_internal = h.n_internal;
+    out->n_leaves = h.n_leaves;
+    out->bytes = h.total_bytes;
+    out->uploaded = p->dev != nullptr;
+    out->max_depth = h.max_depth;
+    return FP_OK;
+}
+
+extern "C" int fp_packed_host_bytes(const fp_packed* p, const void** bytes, size_t* nbytes) {
+    fp_clear_error();
+    if (!p || !bytes || !nbytes) return fp_set_error(FP_EINVAL, "NULL argument");
+    *bytes = p->bytes.data();
+    *nbytes = p->bytes.size();
+    return FP_OK;
+}
+
+extern "C" int fp_packed_from_bytes(const void* bytes, size_t nbytes, fp_packed** out) {
+    fp_clear_error();
+    if (!out) return fp_set_error(FP_EINVAL, "out is NULL");
+    *out = nullptr;
+    if (!bytes) return fp_set_error(FP_EINVAL, "bytes is NULL");
+    std::string why;
+    const uint8_t* b = static_cast<const uint8_t*>(bytes);
+    if (fp::verify_buffer(b, nbytes, &why)) return fp_set_error(FP_ECORRUPT, "packed buffer: %s", why.c_str());
+    try {
+        std::unique_ptr<fp_packed> p(new fp_packed());
+        p->bytes.assign(b, b + nbytes);
+        memcpy(&p->hdr, b, sizeof(fp::Header));
+        *out = p.release();
+    } catch (const std::bad_alloc&) {
+        return fp_set_error(FP_ENOMEM, "out of host memory");
+    }
+    return FP_OK;
+}
+
+extern "C" int fp_packed_save(const fp_packed* p, const char* path) {
+    fp_clear_error();
+    if (!p || !path) return fp_set_error(FP_EINVAL, "NULL argument");
+    FILE* f = fopen(path, "wb");
+    if (!f) return fp_set_error(FP_EINVAL, "cannot open %s for writing", path);
+    size_t w = fwrite(p->bytes.data(), 1, p->bytes.size(), f);
+    int rc = fclose(f);
+    if (w != p->bytes.size() || rc != 0) return fp_set_error(FP_EINVAL, "short write to %s", path);
+    return FP_OK;
+}
+
+extern "C" int fp_packed_load(const char* path, fp_packed** out) {
+    fp_clear_error();
+    if (!path || !out) return fp_set_error(FP_EINVAL, "NULL argument");
+    *out = nullptr;
+    FILE* f = fopen(path, "rb");
+    if (!f) return fp_set_error(FP_EINVAL, "cannot open %s", path);
+    std::vector<uint8_t> buf;
+    if (fseek(f, 0, SEEK_END) == 0) {
+        long n = ftell(f);
+        if (n > 0) {
+            buf.resize((size_t)n);
+            fseek(f, 0, SEEK_SET);
+            if (fread(buf.data(), 1, buf.size(), f) != buf.size()) buf.clear();
+        }
+    }
+    fclose(f);
+    if (buf.empty()) return fp_set_error(FP_ECORRUPT, "%s is empty or unreadable", path);
+    return fp_packed_from_bytes(buf.data(), buf.size(), out);
+}
+
+extern "C" int fp_packed_upload(fp_packed* p, void* dev, size_t cap, void* stream) {
+    fp_clear_error();
+    if (!p || !dev) return fp_set_error(FP_EINVAL, "NULL argument");
+    if (reinterpret_cast<uintptr_t>(dev) % 256) return fp_set_error(FP_EINVAL, "device buffer not 256-byte aligned");
+    if (cap < p->bytes.size())
+        return fp_set_error(FP_E2BIG, "device buffer of %zu bytes < packed size %zu", cap, p->bytes.size());
+    int dev_id = -1;
+    hipError_t e = hipGetDevice(&dev_id);
+    if (e != hipSuccess) return fp_set_error(FP_EHIP, "hipGetDevice: %s", hipGetErrorString(e));
+    e = hipMemcpyAsync(dev, p->bytes.data(), p->bytes.size(), hipMemcpyHostToDevice,
+                       static_cast<hipStream_t>(stream));
+    if (e != hipSuccess) return fp_set_error(FP_EHIP, "hipMemcpyAsync: %s", hipGetErrorString(e));
+    // the host vector must outlive the copy: wait for it
+    e = hipStreamSynchronize(static_cast<hipStream_t>(stream));
+    if (e != hipSuccess) return fp_set_error(FP_EHIP, "hipStreamSynchronize: %s", hipGetErrorString(e));
+    p->dev = dev;
+    p->dev_cap = cap;
+    p->dev_id = dev_id;
+    return FP_OK;
+}
+
+extern "C" void fp_packed_free(fp_packed* p) { delete p; }
+
+extern "C" int fp_packed_set_tune(fp_packed* p, const fp_tune* tune) {
+    fp_clear_error();
+    if (!p) return fp_set_error(FP_EINVAL, "NULL packed forest");
+    if (tune) {
+        p->tune = *tune;
+        p->has_tune = true;
+    } else {
+        p->tune = fp_tune{};
+        p->has_tune = false;
+    }
+    return FP_OK;
+}
+
+extern "C" int fp_packed_get_tune(const fp_packed* p, fp_tune* out) {
+    fp_clear_error();
+    if (!p || !out) return fp_set_error(FP_EINVAL, "NULL argument");
+    *out = p->tune;
+    return FP_OK;
+}

@@ -1,0 +1,190 @@
+"""GPU parity: every layout and launch configuration returns exactly the CPU
+checker's int32 votes and classes (bit-exact), through the C ABI.
+
+Sizes: the checker finishes each case in well under a second; cases span many
+row tiles and bins with ragged tails.  The full image-shaped workload (1M rows,
+128 trees) is checked on sampled rows in the launch configuration the
+benchmark times.
+"""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import paper_1806_07300_amd as fp
+from paper_1806_07300_amd import presets
+import synth
+
+pytestmark = pytest.mark.gpu
+
+
+def run(p, X, tune=None, ld_pad=0):
+    n, F = X.shape
+    if ld_pad:
+        Xp = np.full((n, F + ld_pad), np.nan, np.float32)
+        Xp[:, :F] = X
+        Xd = torch.from_numpy(Xp).cuda()
+    else:
+        Xd = torch.from_numpy(np.ascontiguousarray(X)).cuda()
+    if tune is None:
+        v, c = fp.fp_predict(p, Xd)
+    else:
+        v, c = fp.fp_predict_tuned(p, tune, Xd)
+    torch.cuda.synchronize()
+    return v.cpu().numpy(), c.cpu().numpy()
+
+
+def upload(forest, **kw):
+    p = fp.fp_pack_forest(forest, **kw)
+    fp.fp_packed_upload(p)
+    return p
+
+
+def assert_same(got, want, what=""):
+    gv, gc = got
+    wv, wc = want
+    if not np.array_equal(gv, wv):
+        bad = np.nonzero((gv != wv).any(1))[0]
+        raise AssertionError(f"{what}: {len(bad)} rows differ, first {bad[:5]}: {gv[bad[0]]} vs {wv[bad[0]]}")
+    assert np.array_equal(gc, wc), f"{what}: classes differ"
+
+
+@pytest.fixture(scope="module")
+def small():
+    w = synth.small()
+    f = w.forest()
+    X, _ = w.predict_rows()
+    return f, X, oracle.predict(f, X)
+
+
+def test_naive_small(small):
+    f, X, want = small
+    p = upload(f, layout=fp.FP_LAYOUT_NAIVE)
+    for threads in (64, 256, 1024):
+        assert_same(run(p, X, {"block_threads": threads}), want, f"naive threads={threads}")
+
+
+@pytest.mark.parametrize("B", [1, 2, 16, 32])
+@pytest.mark.parametrize("D", [0, 1, 3, 6])
+def test_packed_layout_grid(small, B, D):
+    f, X, want = small
+    p = upload(f, bin_size=B, interleave_depth=D, line_align=int(B % 2 == 0))
+    assert_same(run(p, X), want, f"B={B} D={D}")
+
+
+TUNES = [
+    {"rows_per_block": 1, "cursors": 1, "block_threads": 64},
+    {"rows_per_block": 4, "cursors": 8, "block_threads": 256},
+    {"rows_per_block": 16, "cursors": 2, "tree_groups": 2},
+    {"rows_per_block": 64, "cursors": 4, "tree_groups": 4, "block_threads": 1024},
+    {"rows_per_block": 16, "cursors": 4, "feature_lds": -1},
+    {"rows_per_block": 32, "cursors": 2, "lds_top_nodes": -1},
+    {"rows_per_block": 8, "cursors": 1, "lds_top_nodes": 5, "tree_groups": 3},
+    {"rows_per_block": 16, "cursors": 8, "feature_lds": 1, "block_threads": 512},
+]
+
+
+@pytest.mark.parametrize("tune", TUNES, ids=lambda t: "-".join(f"{k[:4]}{v}" for k, v in t.items()))
+def test_packed_launch_grid(small, tune):
+    f, X, want = small
+    p = upload(f, bin_size=8, interleave_depth=3)
+    assert_same(run(p, X, tune), want, str(tune))
+
+
+@pytest.mark.parametrize("n", [0, 1, 15, 17, 257, 4099])
+def test_ragged_and_empty(small, n):
+    f, X, _ = small
+    Xn = X[:n]
+    want = oracle.predict(f, Xn)
+    for kw in ({"layout": fp.FP_LAYOUT_NAIVE}, {"bin_size": 16, "interleave_depth": 2}):
+        p = upload(f, **kw)
+        got = run(p, Xn, {"rows_per_block": 16, "cursors": 2})
+        assert got[0].shape == (n, 2)
+        assert_same(got, want, f"n={n} {kw}")
+
+
+def test_strided_rows_and_special_values(small):
+    f, X, _ = small
+    X = X[:3000].copy()
+    rng = np.random.default_rng(0)
+    thr = f.threshold[f.feature >= 0]
+    m = rng.random(X.shape)
+    X[m < 0.05] = np.nan
+    X[(m >= 0.05) & (m < 0.08)] = np.inf
+    X[(m >= 0.08) & (m < 0.11)] = -np.inf
+    X[(m >= 0.11) & (m < 0.13)] = np.float32(1e-44)   # denormal
+    X[(m >= 0.13) & (m < 0.15)] = np.float32(-1e-44)
+    X[(m >= 0.15) & (m < 0.17)] = -0.0
+    # values exactly on thresholds and one ulp either side
+    sel = (m >= 0.17) & (m < 0.40)
+    pick = rng.choice(thr, size=sel.sum())
+    bump = rng.integers(-1, 2, size=sel.sum())
+    pick = np.where(bump > 0, np.nextafter(pick, np.float32(np.inf)),
+                    np.where(bump < 0, np.nextafter(pick, np.float32(-np.inf)), pick))
+    X[sel] = pick
+    want = oracle.predict(f, X)
+    for kw in ({"layout": fp.FP_LAYOUT_NAIVE}, {"bin_size": 4, "interleave_depth": 5}):
+        p = upload(f, **kw)
+        assert_same(run(p, X, ld_pad=13), want, f"padded ld {kw}")
+        assert_same(run(p, X, {"feature_lds": -1, "rows_per_block": 16}), want, f"global features {kw}")
+
+
+def test_degenerate_forests():
+    rng = np.random.default_rng(4)
+    X = rng.standard_normal((5000, 3)).astype(np.float32)
+    y = (X[:, 0] > 0).astype(np.int32)
+    y[:50] = 2
+    f = synth.train_forest(X, y, n_trees=9, n_classes=3, mtry=1, max_depth=3, seed=2)
+    g = f.subset(range(9))
+    g.feature[g.tree_node_offset[4]] = -1  # tree 4: the root is a leaf
+    g.leaf_class[g.tree_node_offset[4]] = 2
+    for forest in (g, g.subset([4]), g.subset([0])):
+        want = oracle.predict(forest, X)
+        for kw in ({"layout": fp.FP_LAYOUT_NAIVE}, {"bin_size": 4, "interleave_depth": 0},
+                   {"bin_size": 1, "interleave_depth": 3}):
+            assert_same(run(upload(forest, **kw), X, {"rows_per_block": 8, "cursors": 4}), want,
+                        f"T={forest.n_trees} {kw}")
+
+
+def test_image_lite():
+    w = synth.image(n_train=6000, n_trees=16)
+    f = w.forest()
+    X, _ = w.predict_rows(20_000)
+    want = oracle.predict(f, X)
+    assert_same(run(upload(f, layout=fp.FP_LAYOUT_NAIVE), X), want, "naive")
+    for B, D, tune in ((16, 4, None), (4, 6, {"rows_per_block": 8, "cursors": 4, "tree_groups": 4}),
+                       (8, 2, {"feature_lds": -1, "rows_per_block": 32})):
+        assert_same(run(upload(f, bin_size=B, interleave_depth=D, line_align=1), X, tune), want, f"B={B} D={D}")
+
+
+def test_tabular_lite():
+    w = synth.tabular(n_train=30_000, n_trees=32)
+    f = w.forest()
+    X, _ = w.predict_rows(50_000)
+    want = oracle.predict(f, X)
+    assert_same(run(upload(f, layout=fp.FP_LAYOUT_NAIVE), X), want, "naive")
+    for B, D in ((16, 3), (32, 6)):
+        assert_same(run(upload(f, bin_size=B, interleave_depth=D)), want, f"B={B} D={D}")
+
+
+def test_image_full_size_sampled():
+    """1M rows x 128 trees in the benchmark's launch configuration; the checker
+    recomputes 20,000 sampled rows; every row's votes sum to T."""
+    w = synth.image()
+    f = w.forest()
+    X, _ = w.predict_rows()
+    cfg = presets.IMAGE
+    p = upload(f, **cfg["pack"])
+    Xd = torch.from_numpy(X).cuda()
+    v, c = fp.fp_predict_tuned(p, cfg["tune"], Xd)
+    pn = upload(f, layout=fp.FP_LAYOUT_NAIVE)
+    vn, cn = fp.fp_predict_tuned(pn, cfg["naive_tune"], Xd)
+    torch.cuda.synchronize()
+    v, c, vn, cn = v.cpu().numpy(), c.cpu().numpy(), vn.cpu().numpy(), cn.cpu().numpy()
+    assert (v.sum(1) == f.n_trees).all()
+    rows = np.sort(np.random.default_rng(7).choice(len(X), size=20_000, replace=False))
+    rows = np.concatenate([rows, [0, len(X) - 1]])
+    want_v, want_c = oracle.predict(f, X[rows])
+    assert np.array_equal(v[rows], want_v) and np.array_equal(c[rows], want_c)
+    assert np.array_equal(vn[rows], want_v) and np.array_equal(cn[rows], want_c)
+    assert np.array_equal(v, vn) and np.array_equal(c, cn)

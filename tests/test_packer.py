@@ -1,0 +1,232 @@
+"""Host packer (no GPU): layout invariants of Sec. III-A and packed == unpacked.
+
+Invariants checked on the decoded bytes:
+  * DF-  : no leaf is stored; leaves are class references; every internal node
+           of the forest is stored exactly once;
+  * Bin  : bins hold consecutive trees (last one short); the top region holds
+           exactly the internal nodes of depth <= D, level-major and tree-minor,
+           so depth 0 (the roots) is contiguous (Fig. 2 caption);
+  * Stat : below depth D, the child with more training samples (left on ties,
+           an internal child over a leaf) sits right after its parent;
+  * every reference points forward inside its bin (walks terminate);
+  * walking the packed bytes gives exactly the checker's votes, for a grid of
+    bin sizes and interleave depths (layout never changes predictions).
+"""
+import os
+
+import numpy as np
+import pytest
+
+import oracle
+import paper_1806_07300_amd as fp
+import synth
+
+from packed_format import decode, walk
+
+
+@pytest.fixture(scope="module")
+def small_forest():
+    return synth.small().forest()
+
+
+@pytest.fixture(scope="module")
+def small_rows():
+    X, _ = synth.small().predict_rows(2000)
+    return X
+
+
+def node_map(forest, dec, be, j):
+    """Map packed node index -> (original local id, depth) for tree j of bin be."""
+    t = be["first_tree"] + j
+    off = forest.tree_node_offset[t]
+    bn = dec["nodes"][be["node_base"]:be["node_base"] + be["top_len"] + be["deep_len"]]
+    root = dec["roots"][be["root_base"] + j]
+    out = {}
+    stack = [(root, 0, 0)]
+    while stack:
+        ref, orig, d = stack.pop()
+        if ref < 0:
+            assert forest.feature[off + orig] < 0
+            assert -ref - 1 == forest.leaf_class[off + orig]
+            continue
+        assert forest.feature[off + orig] >= 0
+        assert ref not in out
+        out[ref] = (orig, d)
+        nd = bn[ref]
+        assert nd["feat"] == forest.feature[off + orig]
+        assert nd["thr"] == forest.threshold[off + orig]
+        stack.append((nd["left"], forest.left[off + orig], d + 1))
+        stack.append((nd["right"], forest.right[off + orig], d + 1))
+    return out
+
+
+@pytest.mark.parametrize("B", [1, 2, 7, 16, 32])
+@pytest.mark.parametrize("D", [0, 1, 3, 6])
+def test_packed_equals_unpacked(small_forest, small_rows, B, D):
+    p = fp.fp_pack_forest(small_forest, bin_size=B, interleave_depth=D)
+    dec = decode(fp.fp_packed_host_bytes(p))
+    votes, _ = oracle.predict(small_forest, small_rows)
+    assert (walk(dec, small_rows) == votes).all()
+
+
+@pytest.mark.parametrize("B,D,align", [(16, 3, 0), (5, 2, 1), (32, 0, 0), (1, 4, 1)])
+def test_layout_invariants(small_forest, B, D, align):
+    f = small_forest
+    p = fp.fp_pack_forest(f, bin_size=B, interleave_depth=D, line_align=align)
+    info = fp.fp_packed_info_get(p)
+    dec = decode(fp.fp_packed_host_bytes(p))
+    h = dec["h"]
+    assert info["n_internal"] == f.n_internal() and info["n_leaves"] == f.n_nodes - f.n_internal()
+    bins = dec["bins"]
+    assert len(bins) == -(-f.n_trees // B)
+    assert [int(b["first_tree"]) for b in bins] == list(range(0, f.n_trees, B))
+    assert all(b["n_trees"] == B for b in bins[:-1]) and 1 <= bins[-1]["n_trees"] <= B
+    stored = 0
+    for be in bins:
+        assert be["node_base"] % 8 == 0  # every bin starts on a 128-byte line
+        bn = dec["nodes"][be["node_base"]:be["node_base"] + be["top_len"] + be["deep_len"]]
+        real = ~((bn["feat"] == 0) & (bn["left"] == 0) & (bn["right"] == 0))
+        stored += int(real.sum())
+        seen = {}
+        tree_of = {}
+        for j in range(be["n_trees"]):
+            m = node_map(f, dec, be, j)
+            for ref, (orig, d) in m.items():
+                seen[ref] = (orig, d, j)
+        assert set(seen) == set(np.nonzero(real)[0].tolist())
+        top = [seen[i] for i in range(be["top_len"])]
+        # top region = exactly the internal nodes of depth <= D, level-major, tree-minor
+        assert all(d <= D for _, d, _ in top)
+        assert all(d > D for i, (_, d, _) in seen.items() if i >= be["top_len"])
+        keys = [(d, j) for _, d, j in top]
+        assert keys == sorted(keys)
+        # roots contiguous at the start
+        n_int_roots = sum(1 for _, d, _ in top if d == 0)
+        roots = dec["roots"][be["root_base"]:be["root_base"] + be["n_trees"]]
+        assert sorted(int(r) for r in roots if r >= 0) == list(range(n_int_roots))
+        # references point forward
+        for i in np.nonzero(real)[0]:
+            for c in (bn[i]["left"], bn[i]["right"]):
+                assert c < 0 or c > i
+        # Stat: hot child adjacent below depth D
+        for i, (orig, d, j) in seen.items():
+            if i < be["top_len"]:
+                continue
+            t = be["first_tree"] + j
+            off = f.tree_node_offset[t]
+            l, r = f.left[off + orig], f.right[off + orig]
+            li, ri = f.feature[off + l] >= 0, f.feature[off + r] >= 0
+            if li and ri:
+                hot = l if f.cardinality[off + l] >= f.cardinality[off + r] else r
+            elif li:
+                hot = l
+            elif ri:
+                hot = r
+            else:
+                continue
+            nxt = seen.get(i + 1)
+            assert nxt is not None and nxt[0] == hot and nxt[2] == j, (i, orig, hot)
+    assert stored == f.n_internal()
+    assert h["max_top_len"] == max(int(b["top_len"]) for b in bins)
+
+
+def test_deterministic_bytes_and_roundtrip(small_forest, tmp_path):
+    a = fp.fp_packed_host_bytes(fp.fp_pack_forest(small_forest, bin_size=8, interleave_depth=2))
+    b = fp.fp_packed_host_bytes(fp.fp_pack_forest(small_forest, bin_size=8, interleave_depth=2))
+    assert np.array_equal(a, b)
+    p = fp.fp_packed_from_bytes(a)
+    assert np.array_equal(fp.fp_packed_host_bytes(p), a)
+    path = str(tmp_path / "f.fpk")
+    fp.fp_packed_save(p, path)
+    q = fp.fp_packed_load(path)
+    assert np.array_equal(fp.fp_packed_host_bytes(q), a)
+    # one flipped byte in the node section, a truncation, a bad magic
+    bad = a.copy()
+    bad[len(bad) // 2] ^= 0x40
+    for corrupt in (bad, a[:-256], np.concatenate([np.zeros(8, np.uint8), a[8:]])):
+        with pytest.raises(fp.FPError) as e:
+            fp.fp_packed_from_bytes(corrupt)
+        assert e.value.code == fp.FP_ECORRUPT
+    with open(path, "r+b") as fh:
+        fh.truncate(1000)
+    with pytest.raises(fp.FPError) as e:
+        fp.fp_packed_load(path)
+    assert e.value.code == fp.FP_ECORRUPT
+
+
+def test_naive_layout(small_forest, small_rows):
+    p = fp.fp_pack_forest(small_forest, layout=fp.FP_LAYOUT_NAIVE)
+    info = fp.fp_packed_info_get(p)
+    assert info["n_nodes"] == small_forest.n_nodes  # leaves are stored
+    dec = decode(fp.fp_packed_host_bytes(p))
+    votes, _ = oracle.predict(small_forest, small_rows)
+    assert (walk(dec, small_rows) == votes).all()
+    assert np.array_equal(fp.fp_packed_host_bytes(fp.fp_packed_from_bytes(fp.fp_packed_host_bytes(p))),
+                          fp.fp_packed_host_bytes(p))
+
+
+def test_no_cardinality_and_single_node_trees():
+    rng = np.random.default_rng(4)
+    X = rng.standard_normal((300, 3)).astype(np.float32)
+    y = (X[:, 0] > 0).astype(np.int32)
+    y[:5] = 2
+    f = synth.train_forest(X, y, n_trees=9, n_classes=3, mtry=1, max_depth=3, seed=2)
+    # make tree 4 a lone leaf (root is a leaf)
+    g = f.subset(range(9))
+    off = g.tree_node_offset
+    g.feature[off[4]] = -1
+    g.leaf_class[off[4]] = 2
+    for use_card in (True, False):
+        for B, D in ((4, 0), (9, 2), (1, 1)):
+            p = fp.fp_pack_forest(g, bin_size=B, interleave_depth=D, use_cardinality=use_card)
+            votes, _ = oracle.predict(g, X)
+            assert (walk(decode(fp.fp_packed_host_bytes(p)), X) == votes).all()
+
+
+def _forest_copy(f):
+    return f.subset(range(f.n_trees))
+
+
+@pytest.mark.parametrize("mutation", ["feature", "child_range", "cycle", "shared", "class", "offsets"])
+def test_malformed_forest_rejected(small_forest, mutation):
+    g = _forest_copy(small_forest)
+    off = g.tree_node_offset
+    t0 = off[3]
+    internal = np.nonzero(g.feature[off[3]:off[4]] >= 0)[0]
+    leaf = np.nonzero(g.feature[off[3]:off[4]] < 0)[0]
+    i = int(internal[2])
+    if mutation == "feature":
+        g.feature[t0 + i] = g.n_features
+    elif mutation == "child_range":
+        g.right[t0 + i] = int(off[4] - off[3])
+    elif mutation == "cycle":
+        g.left[t0 + i] = 0
+    elif mutation == "shared":
+        g.right[t0 + i] = g.left[t0 + i]
+    elif mutation == "class":
+        g.leaf_class[t0 + int(leaf[0])] = g.n_classes
+    elif mutation == "offsets":
+        g.tree_node_offset = off.copy()
+        g.tree_node_offset[5] = g.tree_node_offset[4] - 1
+    with pytest.raises(fp.FPError) as e:
+        fp.fp_pack_forest(g, bin_size=4, interleave_depth=2)
+    assert e.value.code == fp.FP_ECORRUPT
+
+
+def test_bad_options(small_forest):
+    with pytest.raises(fp.FPError) as e:
+        fp.fp_pack_forest(small_forest, layout=7)
+    assert e.value.code == fp.FP_EINVAL
+    with pytest.raises(fp.FPError) as e:
+        fp.fp_pack_forest(small_forest, interleave_depth=-1)
+    assert e.value.code == fp.FP_EINVAL
+
+
+def test_image_forest_packs(tmp_path):
+    w = synth.image(n_train=6000, n_trees=8)
+    f = w.forest()
+    X, _ = w.predict_rows(500)
+    votes, _ = oracle.predict(f, X)
+    for B, D in ((8, 4), (3, 6)):
+        p = fp.fp_pack_forest(f, bin_size=B, interleave_depth=D, line_align=1)
+        assert (walk(decode(fp.fp_packed_host_bytes(p)), X) == votes).all()
