@@ -1,0 +1,235 @@
+#!/usr/bin/env python3
+"""Benchmark: forest classification throughput, packed vs naive layout, one MI355X.
+
+A step is one pass of the whole hot path over one batch: every one of the
+batch's observations walks every tree of the resident packed forest and its
+votes and class are written (fp_predict on 1,000,000 rows of the image-shaped
+workload: 784 fp32 features, 10 classes, 128 trees grown to purity on 60,000
+rows).  Inputs are resident in HBM before timing starts.  Prints one JSON line.
+
+  python bench.py [--gpus 1] [--steps K] [--warmup W]
+
+Extra modes used for profiling (rocprofv3 runs):
+  --only packed|naive|copy   run only that kernel, --steps times, no JSON
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+METRIC = "observations/sec packed vs naive layout on 1 MI355X (bit-exact); p99 serve ms"
+HBM_PEAK_GBS = 8000.0
+KERNEL_SRC = os.path.join(ROOT, "paper_1806_07300_amd", "csrc", "predict.hip")
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "packed_kernel_image_traffic.txt")
+
+
+def log(*a):
+    print("[bench]", *a, file=sys.stderr, flush=True)
+
+
+def kernel_source_hash() -> str:
+    with open(KERNEL_SRC, "rb") as fh:
+        return hashlib.sha256(fh.read()).hexdigest()[:16]
+
+
+def read_traffic():
+    """HBM bytes per launch of the packed kernel measured by rocprofv3 --pmc
+    (FETCH_SIZE, WRITE_SIZE, scaled by a copy-kernel calibration); None when
+    missing or taken on a different kernel source."""
+    if not os.path.exists(TRAFFIC_FILE):
+        return None
+    vals = {}
+    for line in open(TRAFFIC_FILE):
+        if ":" in line:
+            k, v = line.split(":", 1)
+            vals[k.strip()] = v.strip()
+    if vals.get("kernel_source_sha256") != kernel_source_hash():
+        return None
+    try:
+        return float(vals["fetch_bytes_per_launch"]) + float(vals["write_bytes_per_launch"])
+    except (KeyError, ValueError):
+        return None
+
+
+def time_steps(fn, steps, warmup, torch):
+    for _ in range(warmup):
+        fn()
+    torch.cuda.synchronize()
+    stream = torch.cuda.current_stream()
+    start, end = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    t0 = time.perf_counter()
+    start.record(stream)
+    for _ in range(steps):
+        fn()
+    end.record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    return start.elapsed_time(end) / steps, wall
+
+
+def cpu_baseline(forest, X, target_s=10.0):
+    """The CPU checker, as it stands, on a bounded sample of the same batch."""
+    import oracle
+    n_threads = os.cpu_count() or 1
+    n = min(len(X), 20_000)
+    t0 = time.perf_counter()
+    _, _, visits = oracle.predict(forest, X[:n], n_threads=n_threads, return_visits=True)
+    dt = time.perf_counter() - t0
+    m = min(len(X), max(n, int(n * target_s / max(dt, 1e-3))))
+    if m > n:
+        t0 = time.perf_counter()
+        _, _, visits = oracle.predict(forest, X[:m], n_threads=n_threads, return_visits=True)
+        dt = time.perf_counter() - t0
+        n = m
+    return {"value": n / dt, "unit": "observations/s", "cores": n_threads, "kind": "oracle",
+            "sample": f"first {n} rows of the batch, all {n_threads} host threads, {dt:.1f} s"}, visits / n
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--rows", type=int, default=1_000_000)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--only", choices=["packed", "naive", "copy"], default=None)
+    ap.add_argument("--cache", default=os.environ.get("FP_BENCH_CACHE", "/tmp/forestpack_cache"))
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print(f"bench.py measures one GPU only (asked for {args.gpus}); the multi-GPU design is "
+              "described in DESIGN.md and not run here.", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+    import paper_1806_07300_amd as fp
+    from paper_1806_07300_amd import presets
+    import synth
+
+    if not torch.cuda.is_available():
+        print("bench.py needs a GPU", file=sys.stderr)
+        sys.exit(1)
+    torch.cuda.set_device(0)
+
+    if args.only == "copy":
+        # calibration kernel of known size for the HBM byte counters: 1 GiB copy
+        a = torch.empty(1 << 28, dtype=torch.float32, device="cuda").fill_(1.0)
+        b = torch.empty_like(a)
+        for _ in range(args.steps):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        print("copy done: bytes read per launch", a.numel() * 4, "written", b.numel() * 4, flush=True)
+        return
+
+    t0 = time.perf_counter()
+    w = synth.image(n_predict=args.rows)
+    forest = w.forest(cache_dir=args.cache)
+    log(f"forest: {forest.n_trees} trees, {forest.n_internal() / forest.n_trees:.0f} internal nodes/tree, "
+        f"max depth {int(forest.depth.max())} ({time.perf_counter() - t0:.1f} s)")
+    t0 = time.perf_counter()
+    X, _ = w.predict_rows()
+    n, F = X.shape
+    C = forest.n_classes
+    log(f"rows: {n} x {F} ({time.perf_counter() - t0:.1f} s)")
+    Xd = torch.from_numpy(X).cuda()
+    votes = torch.empty((n, C), dtype=torch.int32, device="cuda")
+    cls = torch.empty((n,), dtype=torch.int32, device="cuda")
+    cfg = presets.IMAGE
+
+    t0 = time.perf_counter()
+    packed = fp.fp_pack_forest(forest, **cfg["pack"])
+    pack_s = time.perf_counter() - t0
+    fp.fp_packed_upload(packed)
+    naive = fp.fp_pack_forest(forest, layout=fp.FP_LAYOUT_NAIVE)
+    fp.fp_packed_upload(naive)
+    info = fp.fp_packed_info_get(packed)
+    log(f"packed: {info['bytes'] / 2**20:.1f} MiB, {info['n_bins']} bins, top {info['max_top_nodes']} nodes "
+        f"({pack_s:.2f} s); naive {fp.fp_packed_info_get(naive)['bytes'] / 2**20:.1f} MiB")
+
+    run_packed = lambda: fp.fp_predict_tuned(packed, cfg["tune"], Xd, votes, cls)
+    run_naive = lambda: fp.fp_predict_tuned(naive, cfg["naive_tune"], Xd, votes, cls)
+    if args.only:
+        fn = run_packed if args.only == "packed" else run_naive
+        for i in range(args.steps):
+            fn()
+            torch.cuda.synchronize()
+            log(f"{args.only} launch {i + 1}/{args.steps} done")
+        return
+
+    # the two layouts must agree bit for bit on the whole batch before timing
+    run_naive()
+    v_naive, c_naive = votes.clone(), cls.clone()
+    run_packed()
+    torch.cuda.synchronize()
+    if not (torch.equal(votes, v_naive) and torch.equal(cls, c_naive)):
+        print("packed and naive votes differ", file=sys.stderr)
+        sys.exit(3)
+    del v_naive, c_naive
+
+    ms_packed, wall_packed = time_steps(run_packed, args.steps, args.warmup, torch)
+    log(f"packed: {ms_packed:.3f} ms/step")
+    ms_naive, _ = time_steps(run_naive, max(3, args.steps // 2), 1, torch)
+    log(f"naive : {ms_naive:.3f} ms/step")
+
+    cpu = None
+    visits_per_row = None
+    if not args.no_cpu_baseline:
+        cpu, visits_per_row = cpu_baseline(forest, X)
+        log(f"cpu baseline: {cpu['value']:.0f} obs/s ({cpu['sample']})")
+
+    value = n / (ms_packed / 1e3)
+    # compulsory HBM bytes per launch: observations in, votes and classes out, the packed forest once
+    algo_bytes = n * (F * 4 + C * 4 + 4) + info["bytes"]
+    achieved = algo_bytes / (ms_packed / 1e3) / 1e9
+    traffic = read_traffic()
+    out = {
+        "metric": METRIC,
+        "value": value,
+        "unit": "observations/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_packed,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {
+            "workload": "image-shaped: 784 fp32 features (0-255, 80% zeros), 10 classes, 128 trees grown to "
+                        "purity on 60,000 rows, 1,000,000 rows per step",
+            "n_rows": n, "n_trees": forest.n_trees, "n_features": F, "n_classes": C,
+            "internal_nodes": info["n_internal"], "layout": "packed",
+            "bin_size": info["bin_size"], "interleave_depth": info["interleave_depth"], "tune": cfg["tune"],
+        },
+        "naive": {"value": n / (ms_naive / 1e3), "ms_per_step": ms_naive},
+        "speedup_vs_naive": ms_naive / ms_packed,
+        "roofline": {
+            "bound": "hbm",
+            "achieved": achieved,
+            "peak": HBM_PEAK_GBS,
+            "unit": "GB/s",
+            "frac": achieved / HBM_PEAK_GBS,
+            "traffic": traffic,
+        },
+        "wall_s_timed": wall_packed,
+        "pack_s": pack_s,
+    }
+    if visits_per_row is not None:
+        out["node_visits_per_row"] = visits_per_row
+        out["node_visits_per_s"] = visits_per_row * value
+    if cpu is not None:
+        out["cpu_baseline"] = cpu
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

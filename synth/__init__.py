@@ -162,18 +162,29 @@ def _chunk_rng(seed: int, chunk: int) -> np.random.Generator:
 
 
 def _rows(gen_chunk, n: int, start: int, F: int, seed: int):
-    """Assemble rows [start, start+n) from independently seeded chunks."""
+    """Assemble rows [start, start+n) from independently seeded chunks
+    (chunks are generated on a thread pool; each has its own stream, so the
+    result does not depend on scheduling)."""
     X = np.empty((n, F), np.float32)
     y = np.empty(n, np.int32)
     if n == 0:
         return X, y
     c0, c1 = start // CHUNK, (start + n - 1) // CHUNK
-    for c in range(c0, c1 + 1):
+
+    def one(c):
         Xc, yc = gen_chunk(_chunk_rng(seed, c), CHUNK)
         lo = max(start, c * CHUNK)
         hi = min(start + n, (c + 1) * CHUNK)
         X[lo - start:hi - start] = Xc[lo - c * CHUNK:hi - c * CHUNK]
         y[lo - start:hi - start] = yc[lo - c * CHUNK:hi - c * CHUNK]
+
+    chunks = range(c0, c1 + 1)
+    if len(chunks) == 1:
+        one(c0)
+    else:
+        from concurrent.futures import ThreadPoolExecutor
+        with ThreadPoolExecutor(max_workers=min(len(chunks), os.cpu_count() or 1, 16)) as ex:
+            list(ex.map(one, chunks))
     return X, y
 
 

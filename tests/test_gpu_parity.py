@@ -164,7 +164,7 @@ def test_tabular_lite():
     want = oracle.predict(f, X)
     assert_same(run(upload(f, layout=fp.FP_LAYOUT_NAIVE), X), want, "naive")
     for B, D in ((16, 3), (32, 6)):
-        assert_same(run(upload(f, bin_size=B, interleave_depth=D)), want, f"B={B} D={D}")
+        assert_same(run(upload(f, bin_size=B, interleave_depth=D), X), want, f"B={B} D={D}")
 
 
 def test_image_full_size_sampled():
