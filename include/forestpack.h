@@ -142,6 +142,8 @@ typedef struct fp_packed_info {
     int64_t bytes;        /* size of the packed buffer (host and device copy) */
     int32_t uploaded;     /* 1 once fp_packed_upload succeeded */
     int32_t max_depth;    /* deepest leaf depth (root = 0) */
+    int32_t n_used_features; /* observation columns some split tests */
+    int32_t reserved;
 } fp_packed_info;
 
 /*

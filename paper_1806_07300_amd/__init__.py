@@ -51,7 +51,7 @@ class fp_packed_info(ctypes.Structure):
     _fields_ = [("layout", _i32), ("n_trees", _i32), ("n_features", _i32), ("n_classes", _i32),
                 ("bin_size", _i32), ("interleave_depth", _i32), ("n_bins", _i32), ("max_top_nodes", _i32),
                 ("n_nodes", _i64), ("n_internal", _i64), ("n_leaves", _i64), ("bytes", _i64),
-                ("uploaded", _i32), ("max_depth", _i32)]
+                ("uploaded", _i32), ("max_depth", _i32), ("n_used_features", _i32), ("reserved", _i32)]
 
 
 class fp_tune(ctypes.Structure):

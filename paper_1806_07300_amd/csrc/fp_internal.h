@@ -16,17 +16,21 @@ namespace fp {
 // 256-byte boundary so that the device copy keeps 128-byte line alignment.
 //
 //   [Header 256 B]
-//   PACKED: [BinEntry x n_bins] [root refs int32 x n_trees] [Node16 x n_nodes]
+//   PACKED: [BinEntry x n_bins] [root refs int32 x n_trees]
+//           [feature map int32 x n_used_features] [Node16 x n_nodes]
 //   NAIVE : [tree offsets int64 x (n_trees+1)]             [Node16 x n_nodes]
 //
 // PACKED node references (left/right, roots) are bin-relative: r >= 0 is the
 // r-th node of the bin (top region first, then the deep region); r < 0 is
 // "class -r-1" (a leaf folded into its class, DF- of Sec. III-A).
+// PACKED node features are compacted: a node tests observation column
+// feature_map[feat]; the map lists, in increasing order, the columns that at
+// least one split uses, so a kernel only stages those columns.
 // NAIVE nodes keep leaves: feature < 0 marks a leaf whose class is `left`;
 // internal children are tree-local ids.
 // ---------------------------------------------------------------------------
 constexpr uint64_t kMagic = 0x314B4341504D5046ull;  // "FPMPACK1"
-constexpr uint32_t kFormatVersion = 1;
+constexpr uint32_t kFormatVersion = 2;
 constexpr size_t kSectionAlign = 256;
 
 struct alignas(16) Node16 {
@@ -61,8 +65,10 @@ struct Header {
     int64_t n_nodes;
     int64_t n_internal, n_leaves;
     int32_t max_depth, line_align;
-    uint64_t checksum;      // FNV-1a 64 of bytes [256, total_bytes)
-    uint8_t pad[256 - 120];
+    uint64_t checksum;      // FNV-1a over 64-bit words of bytes [256, total_bytes)
+    int32_t n_used_features, pad0;
+    int64_t fmap_offset;    // feature map (packed), 0 for naive
+    uint8_t pad[256 - 136];
 };
 static_assert(sizeof(Header) == 256, "header is 256 bytes");
 

@@ -237,6 +237,8 @@ int pack_naive(const fp_forest_view* v, const std::vector<TreeShape>& s, std::ve
     h->bin_size = 1;
     h->interleave_depth = 0;
     h->n_bins = v->n_trees;
+    h->n_used_features = v->n_features;
+    h->fmap_offset = 0;
     h->table_offset = (int64_t)table_off;
     h->roots_offset = 0;
     h->nodes_offset = (int64_t)nodes_off;
@@ -324,10 +326,23 @@ int pack_packed(const fp_forest_view* v, const std::vector<TreeShape>& s, const 
     }
     const int64_t n_nodes = node_cursor;
 
-    // 2) buffer
+    // 2) compacted feature numbering: the columns some split tests, in increasing order
+    std::vector<int32_t> remap(v->n_features, -1), fmap;
+    for (int32_t ti = 0; ti < T; ti++)
+        for (int32_t n : s[ti].bfs)
+            if (is_internal(v, s[ti], n)) remap[v->feature[s[ti].base + n]] = 0;
+    for (int32_t f = 0; f < v->n_features; f++)
+        if (remap[f] == 0) {
+            remap[f] = (int32_t)fmap.size();
+            fmap.push_back(f);
+        }
+    if (fmap.empty()) fmap.push_back(0);  // forest of lone leaves: keep one column
+
+    // 3) buffer
     const size_t table_off = sizeof(Header);
     const size_t roots_off = align_up(table_off + sizeof(BinEntry) * (size_t)n_bins, kSectionAlign);
-    const size_t nodes_off = align_up(roots_off + sizeof(int32_t) * (size_t)T, kSectionAlign);
+    const size_t fmap_off = align_up(roots_off + sizeof(int32_t) * (size_t)T, kSectionAlign);
+    const size_t nodes_off = align_up(fmap_off + sizeof(int32_t) * fmap.size(), kSectionAlign);
     const size_t total = align_up(nodes_off + sizeof(Node16) * (size_t)n_nodes, kSectionAlign);
     try {
         out->assign(total, 0);
@@ -335,6 +350,7 @@ int pack_packed(const fp_forest_view* v, const std::vector<TreeShape>& s, const 
         return fp_set_error(FP_ENOMEM, "cannot allocate %zu bytes for the packed forest", total);
     }
     memcpy(out->data() + table_off, bins.data(), sizeof(BinEntry) * (size_t)n_bins);
+    memcpy(out->data() + fmap_off, fmap.data(), sizeof(int32_t) * fmap.size());
     int32_t* roots = reinterpret_cast<int32_t*>(out->data() + roots_off);
     Node16* nodes = reinterpret_cast<Node16*>(out->data() + nodes_off);
     for (int32_t b = 0; b < n_bins; b++) {
@@ -354,7 +370,7 @@ int pack_packed(const fp_forest_view* v, const std::vector<TreeShape>& s, const 
                 const int64_t g = t.base + n;
                 Node16& nd = bn[p[n]];
                 nd.thr = v->threshold[g];
-                nd.feat = v->feature[g];
+                nd.feat = remap[v->feature[g]];
                 nd.left = ref(v->left[g]);
                 nd.right = ref(v->right[g]);
             }
@@ -366,6 +382,8 @@ int pack_packed(const fp_forest_view* v, const std::vector<TreeShape>& s, const 
     h->max_top_len = max_top;
     h->max_bin_trees = B;
     h->line_align = align_lines ? 1 : 0;
+    h->n_used_features = (int32_t)fmap.size();
+    h->fmap_offset = (int64_t)fmap_off;
     h->table_offset = (int64_t)table_off;
     h->roots_offset = (int64_t)roots_off;
     h->nodes_offset = (int64_t)nodes_off;
@@ -396,7 +414,8 @@ int verify_buffer(const uint8_t* bytes, size_t n, std::string* why) {
         h.nodes_offset + N * (int64_t)sizeof(Node16) > (int64_t)n)
         return bad("node section out of bounds");
     const Node16* nodes = reinterpret_cast<const Node16*>(bytes + h.nodes_offset);
-    const int32_t C = h.n_classes, F = h.n_features;
+    const int32_t C = h.n_classes;
+    int32_t F = h.n_features;
     if (h.layout == FP_LAYOUT_NAIVE) {
         if (h.table_offset + (int64_t)sizeof(int64_t) * (h.n_trees + 1) > h.nodes_offset)
             return bad("tree table out of bounds");
@@ -421,8 +440,15 @@ int verify_buffer(const uint8_t* bytes, size_t n, std::string* why) {
     }
     if (h.layout != FP_LAYOUT_PACKED) return bad("unknown layout %d", h.layout);
     if (h.n_bins < 1 || h.table_offset + (int64_t)sizeof(BinEntry) * h.n_bins > h.roots_offset ||
-        h.roots_offset + (int64_t)sizeof(int32_t) * h.n_trees > h.nodes_offset)
-        return bad("bin/root tables out of bounds");
+        h.roots_offset + (int64_t)sizeof(int32_t) * h.n_trees > h.fmap_offset ||
+        h.n_used_features < 1 || h.n_used_features > h.n_features ||
+        h.fmap_offset + (int64_t)sizeof(int32_t) * h.n_used_features > h.nodes_offset)
+        return bad("bin/root/feature tables out of bounds");
+    const int32_t* fmap = reinterpret_cast<const int32_t*>(bytes + h.fmap_offset);
+    for (int32_t j = 0; j < h.n_used_features; j++)
+        if (fmap[j] < 0 || fmap[j] >= h.n_features || (j && fmap[j] <= fmap[j - 1]))
+            return bad("feature map entry %d", j);
+    F = h.n_used_features;  // packed nodes index the compacted feature map
     const BinEntry* bins = reinterpret_cast<const BinEntry*>(bytes + h.table_offset);
     const int32_t* roots = reinterpret_cast<const int32_t*>(bytes + h.roots_offset);
     int32_t tree_cursor = 0;
@@ -508,6 +534,7 @@ extern "C" int fp_packed_info_get(const fp_packed* p, fp_packed_info* out) {
     out->bytes = h.total_bytes;
     out->uploaded = p->dev != nullptr;
     out->max_depth = h.max_depth;
+    out->n_used_features = h.n_used_features;
     return FP_OK;
 }
 

@@ -44,6 +44,7 @@ constexpr int32_t kDone = INT32_MIN;
 struct DeviceProps {
     int cus = 0;
     size_t lds_per_block = 0;
+    size_t lds_per_cu = 0;
     bool ok = false;
 };
 
@@ -59,6 +60,7 @@ int device_props(int dev, DeviceProps* out) {
         if (e != hipSuccess) return fp_set_error(FP_EHIP, "hipGetDeviceProperties: %s", hipGetErrorString(e));
         g_props[dev].cus = pr.multiProcessorCount;
         g_props[dev].lds_per_block = pr.sharedMemPerBlock;
+        g_props[dev].lds_per_cu = pr.maxSharedMemoryPerMultiProcessor;
         g_props[dev].ok = true;
     }
     *out = g_props[dev];
@@ -118,124 +120,167 @@ __global__ __launch_bounds__(1024) void naive_kernel(NaiveArgs a) {
 
 // ---------------------------------------------------------------------------
 // packed kernel
+//
+// Work unit = one (observation, tree) walk.  A workgroup owns a tile of R
+// observations (compacted feature columns staged in LDS) and the trees of
+// one tree group; the tile's R x trees units form a pool in LDS.  Every lane
+// keeps K walks in flight (Bin+ round-robin, Sec. III-B): per step it issues
+// the K node loads, then the K compares.  When walks end, the wavefront
+// refills all its empty cursors at once: one lane reserves as many units as
+// there are empty cursors with a single LDS atomic, and each empty cursor
+// takes base + (number of empty cursors on lower lanes) -- a ballot/mbcnt
+// prefix, no per-lane atomics.  Lanes therefore never idle behind a long
+// walk while units remain, which is the GPU answer to the longest-path skew
+// of Sec. IV-D.  The interleaved top levels of every bin of the group stay in
+// LDS for the whole kernel (persistent workgroups).
 // ---------------------------------------------------------------------------
 struct PackedArgs {
     const BinEntry* bins;
     const int32_t* roots;
+    const int32_t* fmap;
     const Node16* nodes;
     const float* X;
     int64_t ld;
     int64_t n_rows;
     int32_t* votes;
     int32_t* cls;
-    int32_t F, C, Fp;       // features, classes, LDS row stride (floats)
-    int32_t n_bins;
-    int32_t R, S;           // rows per block, tree slots per block (R * S == blockDim)
-    int32_t G, bins_per_group;
-    int32_t top_cap;        // bin-top nodes staged in LDS
+    int32_t Fc, Fcp, C;      // used features, LDS row stride (floats), classes
+    int32_t n_bins, bin_size;
+    int32_t R;               // observations per tile
+    int32_t G, bins_per_group, trees_per_group;
+    int32_t cap;             // LDS nodes reserved per bin of the group
     int32_t n_tiles;
-    int32_t atomic_votes;   // 1: add into global votes (several groups)
+    int32_t atomic_votes;    // 1: add into global votes (several groups)
 };
 
-__device__ __forceinline__ Node16 load_node(const Node16* p) {
-    return *p;  // 16-byte aligned: one dwordx4 load
+struct PackedLds {
+    size_t top, ttab, fmap, xs, votes, pool, total;
+};
+
+__host__ __device__ inline PackedLds packed_lds_layout(int cap, int bins_per_group, int trees_per_group, int Fc, int Fcp,
+                                                       int R, int C, bool feat_lds) {
+    PackedLds L;
+    size_t o = 0;
+    L.top = o;   o += (size_t)cap * bins_per_group * sizeof(Node16);
+    L.ttab = o;  o += (size_t)trees_per_group * 16;
+    L.fmap = o;  o += feat_lds ? 0 : ((size_t)Fc * 4 + 15) / 16 * 16;
+    L.xs = o;    o += feat_lds ? ((size_t)R * Fcp * 4 + 15) / 16 * 16 : 0;
+    L.votes = o; o += ((size_t)R * C * 4 + 15) / 16 * 16;
+    L.pool = o;  o += 16;
+    L.total = o;
+    return L;
+}
+
+__device__ __forceinline__ int lane_id() { return __builtin_amdgcn_mbcnt_hi(~0u, __builtin_amdgcn_mbcnt_lo(~0u, 0u)); }
+__device__ __forceinline__ int bits_below(uint64_t m) {
+    return __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
 }
 
 template <int K, bool FEAT_LDS>
 __global__ __launch_bounds__(1024) void packed_kernel(PackedArgs a) {
     extern __shared__ __align__(16) unsigned char smem[];
-    Node16* top = reinterpret_cast<Node16*>(smem);
-    float* xs = reinterpret_cast<float*>(smem + (size_t)a.top_cap * sizeof(Node16));
-    int32_t* vl = reinterpret_cast<int32_t*>(xs + (FEAT_LDS ? a.R * a.Fp : 0));
+    const PackedLds L = packed_lds_layout(a.cap, a.bins_per_group, a.trees_per_group, a.Fc, a.Fcp, a.R, a.C, FEAT_LDS);
+    Node16* top = reinterpret_cast<Node16*>(smem + L.top);
+    int4* ttab = reinterpret_cast<int4*>(smem + L.ttab);
+    int32_t* fmap_l = reinterpret_cast<int32_t*>(smem + L.fmap);
+    float* xs = reinterpret_cast<float*>(smem + L.xs);
+    int32_t* vl = reinterpret_cast<int32_t*>(smem + L.votes);
+    int32_t* pool = reinterpret_cast<int32_t*>(smem + L.pool);
 
     const int tid = threadIdx.x, bd = blockDim.x;
-    const int r = tid % a.R, s = tid / a.R;
     const int group = blockIdx.x % a.G;
     const int blocks_per_group = gridDim.x / a.G;
     const int b_lo = group * a.bins_per_group;
     const int b_hi = min(b_lo + a.bins_per_group, a.n_bins);
     if (b_lo >= b_hi) return;  // uniform per block
-    const bool single_bin = (b_hi - b_lo) == 1;
+    const int t_lo = a.bins[b_lo].first_tree;
+    const int nt = a.bins[b_hi - 1].first_tree + a.bins[b_hi - 1].n_trees - t_lo;
 
-    auto stage_top = [&](int b) {
-        const BinEntry be = a.bins[b];
-        const int n = min(be.top_len, a.top_cap);
-        const int4* src = reinterpret_cast<const int4*>(a.nodes + be.node_base);
-        int4* dst = reinterpret_cast<int4*>(top);
-        for (int i = tid; i < n; i += bd) dst[i] = src[i];
-    };
-    if (single_bin) stage_top(b_lo);
+    // once per workgroup: bin tops, tree table, feature map
+    for (int i = tid; i < (b_hi - b_lo) * a.cap; i += bd) {
+        const int bl = i / a.cap, k = i - bl * a.cap;
+        const BinEntry& be = a.bins[b_lo + bl];
+        if (k < be.top_len) top[i] = a.nodes[be.node_base + k];
+    }
+    for (int tl = tid; tl < nt; tl += bd) {
+        const int t = t_lo + tl;
+        const int b = t / a.bin_size;
+        const BinEntry& be = a.bins[b];
+        ttab[tl] = make_int4(a.roots[t], (int32_t)be.node_base, (b - b_lo) * a.cap, min(be.top_len, a.cap));
+    }
+    if (!FEAT_LDS)
+        for (int j = tid; j < a.Fc; j += bd) fmap_l[j] = a.fmap[j];
 
+    const int lane = lane_id();
     for (int tile = blockIdx.x / a.G; tile < a.n_tiles; tile += blocks_per_group) {
         const int64_t row0 = (int64_t)tile * a.R;
         const int rows_here = (int)min<int64_t>(a.R, a.n_rows - row0);
         if (FEAT_LDS) {
-            const int total = a.R * a.F;
+            const int total = rows_here * a.Fc;
             for (int i = tid; i < total; i += bd) {
-                const int rr = i / a.F, ff = i - rr * a.F;
-                xs[rr * a.Fp + ff] = rr < rows_here ? a.X[(row0 + rr) * a.ld + ff] : 0.0f;
+                const int rr = i / a.Fc, j = i - rr * a.Fc;
+                xs[rr * a.Fcp + j] = a.X[(row0 + rr) * a.ld + a.fmap[j]];
             }
         }
-        for (int i = tid; i < a.R * a.C; i += bd) vl[i] = 0;
-        const bool live = r < rows_here;
-        const float* xrow = a.X + (row0 + (live ? r : 0)) * a.ld;
-        const float* xl = xs + r * a.Fp;
-        int32_t* vrow = vl + r * a.C;
+        for (int i = tid; i < rows_here * a.C; i += bd) vl[i] = 0;
+        if (tid == 0) *pool = 0;
+        __syncthreads();
 
-        for (int b = b_lo; b < b_hi; b++) {
-            if (!single_bin) {
-                __syncthreads();
-                stage_top(b);
+        const int U = rows_here * nt;
+        int32_t ref[K], rowk[K], gb[K], lb[K], cp[K];
+#pragma unroll
+        for (int k = 0; k < K; k++) { ref[k] = kDone; rowk[k] = 0; gb[k] = 0; lb[k] = 0; cp[k] = 0; }
+        bool drained = false;  // wave-uniform: the pool has no units left
+        while (true) {
+            if (!drained) {
+#pragma unroll
+                for (int k = 0; k < K; k++) {
+                    while (!drained) {
+                        const uint64_t m = __ballot(ref[k] == kDone);
+                        if (m == 0) break;
+                        int base = 0;
+                        if (lane == 0) base = atomicAdd(pool, (int)__popcll(m));
+                        base = __builtin_amdgcn_readfirstlane(base);
+                        if (base >= U) { drained = true; break; }
+                        if (ref[k] == kDone) {
+                            const int u = base + bits_below(m);
+                            if (u < U) {
+                                const int r = u % rows_here;
+                                const int4 e = ttab[u / rows_here];
+                                rowk[k] = r; gb[k] = e.y; lb[k] = e.z; cp[k] = e.w;
+                                if (e.x < 0) atomicAdd(&vl[r * a.C - e.x - 1], 1);  // the root is a leaf
+                                else ref[k] = e.x;
+                            }
+                        }
+                        if (base + (int)__popcll(m) >= U) drained = true;
+                    }
+                }
             }
-            __syncthreads();
-            if (!live) continue;
-            const BinEntry be = a.bins[b];
-            const Node16* gn = a.nodes + be.node_base;
-            const int32_t* rt = a.roots + be.root_base;
-            const int nt = be.n_trees;
-            const int cap = min(be.top_len, a.top_cap);
-            int32_t ref[K];
-            int next = s + K * a.S;
+            bool live = false;
+#pragma unroll
+            for (int k = 0; k < K; k++) live |= ref[k] >= 0;
+            if (__ballot(live) == 0) break;
+            Node16 nd[K];
+#pragma unroll
+            for (int k = 0; k < K; k++)
+                if (ref[k] >= 0) nd[k] = ref[k] < cp[k] ? top[lb[k] + ref[k]] : a.nodes[gb[k] + ref[k]];
 #pragma unroll
             for (int k = 0; k < K; k++) {
-                const int t = s + k * a.S;
-                ref[k] = t < nt ? rt[t] : kDone;
-            }
-            while (true) {
-                bool any = false;
-#pragma unroll
-                for (int k = 0; k < K; k++) {
-                    // a class reference ends a walk: vote, then start the next tree
-                    while (ref[k] < 0 && ref[k] != kDone) {
-                        atomicAdd(&vrow[-ref[k] - 1], 1);
-                        if (next < nt) {
-                            ref[k] = rt[next];
-                            next += a.S;
-                        } else {
-                            ref[k] = kDone;
-                        }
+                if (ref[k] >= 0) {
+                    const float x = FEAT_LDS ? xs[rowk[k] * a.Fcp + nd[k].feat]
+                                             : a.X[(row0 + rowk[k]) * a.ld + fmap_l[nd[k].feat]];
+                    int32_t nr = (x <= nd[k].thr) ? nd[k].left : nd[k].right;
+                    if (nr < 0) {
+                        atomicAdd(&vl[rowk[k] * a.C - nr - 1], 1);
+                        nr = kDone;
                     }
-                    any |= ref[k] != kDone;
-                }
-                if (!any) break;
-                Node16 nd[K];
-#pragma unroll
-                for (int k = 0; k < K; k++) {
-                    if (ref[k] >= 0) nd[k] = ref[k] < cap ? top[ref[k]] : load_node(gn + ref[k]);
-                }
-#pragma unroll
-                for (int k = 0; k < K; k++) {
-                    if (ref[k] >= 0) {
-                        const float x = FEAT_LDS ? xl[nd[k].feat] : xrow[nd[k].feat];
-                        ref[k] = (x <= nd[k].thr) ? nd[k].left : nd[k].right;
-                    }
+                    ref[k] = nr;
                 }
             }
         }
         __syncthreads();
         for (int i = tid; i < rows_here * a.C; i += bd) {
-            const int rr = i / a.C, c = i - rr * a.C;
-            int32_t* dst = a.votes + (row0 + rr) * a.C + c;
+            int32_t* dst = a.votes + row0 * a.C + i;
             if (a.atomic_votes) {
                 if (vl[i]) atomicAdd(dst, vl[i]);
             } else {
@@ -295,7 +340,7 @@ namespace fp {
 
 // Resolved launch configuration for the packed kernel.
 struct PackedLaunch {
-    int R, S, K, G, threads, top_cap, Fp, blocks;
+    int R, K, G, threads, cap, Fcp, blocks, bins_per_group, trees_per_group;
     bool feat_lds;
     size_t lds_bytes;
 };
@@ -304,48 +349,62 @@ int resolve_packed_launch(const fp_packed* p, const fp_tune* t, int64_t n_rows, 
                           PackedLaunch* L) {
     const Header& h = p->hdr;
     const size_t lds_max = dp.lds_per_block ? dp.lds_per_block : 65536;
-    int threads = t->block_threads > 0 ? t->block_threads : 256;
+    const size_t lds_cu = dp.lds_per_cu ? dp.lds_per_cu : lds_max;
+    if (h.n_nodes >= INT32_MAX) return fp_set_error(FP_E2BIG, "packed forest has %lld nodes (limit 2^31-1)", (long long)h.n_nodes);
+    const int threads = t->block_threads > 0 ? t->block_threads : 256;
     if (threads % 64 || threads < 64 || threads > 1024)
         return fp_set_error(FP_EINVAL, "block_threads %d must be a multiple of 64 in [64, 1024]", threads);
-    int R = t->rows_per_block > 0 ? t->rows_per_block : 16;
-    if (R > threads) R = threads;
-    if (threads % R) return fp_set_error(FP_EINVAL, "rows_per_block %d must divide block_threads %d", R, threads);
-    int K = t->cursors > 0 ? t->cursors : 2;
+    const int R = t->rows_per_block > 0 ? t->rows_per_block : 16;
+    if (R > 4096) return fp_set_error(FP_EINVAL, "rows_per_block %d exceeds 4096", R);
+    const int K = t->cursors > 0 ? t->cursors : 2;
     if (K != 1 && K != 2 && K != 4 && K != 8) return fp_set_error(FP_EINVAL, "cursors must be 1, 2, 4 or 8");
     int G = t->tree_groups > 0 ? t->tree_groups : 1;
     if (G > h.n_bins) G = h.n_bins;
-    const int Fp = h.n_features | 1;
+    const int bpg = (h.n_bins + G - 1) / G;
+    const int Fc = h.n_used_features;
+    const int Fcp = Fc | 1;
+    // trees of the largest group
+    const int tpg = std::min<int64_t>((int64_t)bpg * h.bin_size, h.n_trees);
     // feature_lds: 1 force LDS staging, -1 read features from memory, 0 automatic
     bool feat_lds = t->feature_lds >= 0;
-    size_t votes_b = (size_t)R * h.n_classes * 4;
-    size_t feat_b = feat_lds ? (size_t)R * Fp * 4 : 0;
-    if (votes_b > lds_max) return fp_set_error(FP_E2BIG, "vote tile of %zu bytes exceeds LDS", votes_b);
-    if (votes_b + feat_b > lds_max) {
+    PackedLds base = packed_lds_layout(0, bpg, tpg, Fc, Fcp, R, h.n_classes, feat_lds);
+    if (base.total > lds_max) {
         if (t->feature_lds == 1)
-            return fp_set_error(FP_E2BIG, "observation tile of %zu bytes does not fit in LDS", feat_b);
+            return fp_set_error(FP_E2BIG, "observation tile of %d rows x %d columns does not fit in LDS", R, Fc);
         feat_lds = false;
-        feat_b = 0;
+        base = packed_lds_layout(0, bpg, tpg, Fc, Fcp, R, h.n_classes, false);
+        if (base.total > lds_max)
+            return fp_set_error(FP_E2BIG, "per-workgroup tables of %zu bytes exceed LDS", base.total);
     }
-    int top_cap = t->lds_top_nodes > 0 ? t->lds_top_nodes : h.max_top_len;
-    top_cap = std::min(top_cap, h.max_top_len);
-    const size_t room = (lds_max - votes_b - feat_b) / sizeof(Node16);
-    if ((size_t)top_cap > room) top_cap = (int)room;
-    if (t->lds_top_nodes < 0) top_cap = 0;
+    // LDS for bin tops: an explicit node budget, or by default what keeps two
+    // workgroups resident per CU
+    size_t top_budget_nodes;
+    if (t->lds_top_nodes < 0) {
+        top_budget_nodes = 0;
+    } else if (t->lds_top_nodes > 0) {
+        top_budget_nodes = (size_t)t->lds_top_nodes;
+    } else {
+        const size_t per_block = std::min(lds_max, lds_cu / 2);
+        top_budget_nodes = per_block > base.total ? (per_block - base.total) / sizeof(Node16) : 0;
+    }
+    const size_t room = (lds_max - base.total) / sizeof(Node16);
+    top_budget_nodes = std::min(top_budget_nodes, room);
+    int cap = (int)std::min<size_t>(top_budget_nodes / bpg, (size_t)h.max_top_len);
     L->R = R;
-    L->S = threads / R;
     L->K = K;
     L->G = G;
     L->threads = threads;
-    L->top_cap = top_cap;
-    L->Fp = Fp;
+    L->cap = cap;
+    L->Fcp = Fcp;
     L->feat_lds = feat_lds;
-    L->lds_bytes = (size_t)top_cap * sizeof(Node16) + feat_b + votes_b;
+    L->bins_per_group = bpg;
+    L->trees_per_group = tpg;
+    L->lds_bytes = packed_lds_layout(cap, bpg, tpg, Fc, Fcp, R, h.n_classes, feat_lds).total;
     const int64_t n_tiles = (n_rows + R - 1) / R;
-    // persistent blocks: enough to fill every CU a few times over
     int occ = 0;
     hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, pick_packed(K, feat_lds), threads, L->lds_bytes);
     if (e != hipSuccess || occ < 1) occ = 1;
-    const int64_t per_group = std::min<int64_t>(n_tiles, (int64_t)dp.cus * occ * 2 / std::max(1, G) + 1);
+    const int64_t per_group = std::min<int64_t>(n_tiles, std::max<int64_t>(1, (int64_t)dp.cus * occ / G));
     L->blocks = (int)std::max<int64_t>(1, per_group) * G;
     return FP_OK;
 }
@@ -395,21 +454,23 @@ static int predict_impl(const fp_packed* p, const fp_tune* tune, const float* X,
     PackedArgs a;
     a.bins = reinterpret_cast<const BinEntry*>(base + h.table_offset);
     a.roots = reinterpret_cast<const int32_t*>(base + h.roots_offset);
+    a.fmap = reinterpret_cast<const int32_t*>(base + h.fmap_offset);
     a.nodes = nodes;
     a.X = X;
     a.ld = ld;
     a.n_rows = n_rows;
     a.votes = votes;
     a.cls = cls;
-    a.F = h.n_features;
+    a.Fc = h.n_used_features;
+    a.Fcp = L.Fcp;
     a.C = h.n_classes;
-    a.Fp = L.Fp;
     a.n_bins = h.n_bins;
+    a.bin_size = h.bin_size;
     a.R = L.R;
-    a.S = L.S;
     a.G = L.G;
-    a.bins_per_group = (h.n_bins + L.G - 1) / L.G;
-    a.top_cap = L.top_cap;
+    a.bins_per_group = L.bins_per_group;
+    a.trees_per_group = L.trees_per_group;
+    a.cap = L.cap;
     a.n_tiles = (int32_t)((n_rows + L.R - 1) / L.R);
     a.atomic_votes = L.G > 1;
     if (a.atomic_votes) {

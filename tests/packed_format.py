@@ -6,7 +6,7 @@ import struct
 
 import numpy as np
 
-HEADER = struct.Struct("<QIi" + "i" * 8 + "q" * 7 + "ii" + "Q")
+HEADER = struct.Struct("<QIi" + "i" * 8 + "q" * 7 + "ii" + "Q" + "ii" + "q")
 NODE = np.dtype([("thr", "<f4"), ("feat", "<i4"), ("left", "<i4"), ("right", "<i4")])
 BIN = np.dtype([("node_base", "<i8"), ("first_tree", "<i4"), ("n_trees", "<i4"), ("top_len", "<i4"),
                 ("deep_len", "<i4"), ("root_base", "<i4"), ("pad", "<i4")])
@@ -18,7 +18,7 @@ def decode(buf: np.ndarray) -> dict:
     keys = ["magic", "version", "layout", "n_trees", "n_features", "n_classes", "bin_size",
             "interleave_depth", "n_bins", "max_top_len", "max_bin_trees", "total_bytes", "table_offset",
             "roots_offset", "nodes_offset", "n_nodes", "n_internal", "n_leaves", "max_depth", "line_align",
-            "checksum"]
+            "checksum", "n_used_features", "pad0", "fmap_offset"]
     h = dict(zip(keys, f))
     nodes = np.frombuffer(b, NODE, count=h["n_nodes"], offset=h["nodes_offset"])
     out = {"h": h, "nodes": nodes}
@@ -27,6 +27,7 @@ def decode(buf: np.ndarray) -> dict:
     else:
         out["bins"] = np.frombuffer(b, BIN, count=h["n_bins"], offset=h["table_offset"])
         out["roots"] = np.frombuffer(b, "<i4", count=h["n_trees"], offset=h["roots_offset"])
+        out["fmap"] = np.frombuffer(b, "<i4", count=h["n_used_features"], offset=h["fmap_offset"])
     return out
 
 
@@ -59,7 +60,7 @@ def walk(dec: dict, X: np.ndarray) -> np.ndarray:
             while (ref >= 0).any():
                 live = ref >= 0
                 nd = bn[np.where(live, ref, 0)]
-                go_left = X[rows, nd["feat"]] <= nd["thr"]
+                go_left = X[rows, dec["fmap"][nd["feat"]]] <= nd["thr"]
                 ref = np.where(live, np.where(go_left, nd["left"], nd["right"]), ref)
             np.add.at(votes, (rows, -ref - 1), 1)
     return votes

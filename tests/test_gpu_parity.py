@@ -81,6 +81,9 @@ TUNES = [
     {"rows_per_block": 32, "cursors": 2, "lds_top_nodes": -1},
     {"rows_per_block": 8, "cursors": 1, "lds_top_nodes": 5, "tree_groups": 3},
     {"rows_per_block": 16, "cursors": 8, "feature_lds": 1, "block_threads": 512},
+    {"rows_per_block": 128, "cursors": 2, "block_threads": 1024},
+    {"rows_per_block": 3, "cursors": 4, "tree_groups": 8, "block_threads": 64},
+    {"rows_per_block": 33, "cursors": 1, "lds_top_nodes": 100, "block_threads": 128},
 ]
 
 

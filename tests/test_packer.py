@@ -53,7 +53,7 @@ def node_map(forest, dec, be, j):
         assert ref not in out
         out[ref] = (orig, d)
         nd = bn[ref]
-        assert nd["feat"] == forest.feature[off + orig]
+        assert dec["fmap"][nd["feat"]] == forest.feature[off + orig]
         assert nd["thr"] == forest.threshold[off + orig]
         stack.append((nd["left"], forest.left[off + orig], d + 1))
         stack.append((nd["right"], forest.right[off + orig], d + 1))
@@ -86,6 +86,7 @@ def test_layout_invariants(small_forest, B, D, align):
         assert be["node_base"] % 8 == 0  # every bin starts on a 128-byte line
         bn = dec["nodes"][be["node_base"]:be["node_base"] + be["top_len"] + be["deep_len"]]
         real = ~((bn["feat"] == 0) & (bn["left"] == 0) & (bn["right"] == 0))
+        assert (bn["feat"][real] < h["n_used_features"]).all()
         stored += int(real.sum())
         seen = {}
         tree_of = {}
@@ -128,6 +129,8 @@ def test_layout_invariants(small_forest, B, D, align):
             assert nxt is not None and nxt[0] == hot and nxt[2] == j, (i, orig, hot)
     assert stored == f.n_internal()
     assert h["max_top_len"] == max(int(b["top_len"]) for b in bins)
+    used = np.unique(f.feature[f.feature >= 0])
+    assert np.array_equal(dec["fmap"], used) and info["n_used_features"] == len(used)
 
 
 def test_deterministic_bytes_and_roundtrip(small_forest, tmp_path):
