@@ -27,7 +27,7 @@ if ROOT not in sys.path:
 
 METRIC = "observations/sec packed vs naive layout on 1 MI355X (bit-exact); p99 serve ms"
 HBM_PEAK_GBS = 8000.0
-KERNEL_SRC = os.path.join(ROOT, "paper_1806_07300_amd", "csrc", "predict.hip")
+KERNEL_SRC = os.path.join(ROOT, "paper_1806_07300_amd", "csrc", "traverse.hip")
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "packed_kernel_image_traffic.txt")
 
 

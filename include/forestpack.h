@@ -144,6 +144,9 @@ typedef struct fp_packed_info {
     int32_t max_depth;    /* deepest leaf depth (root = 0) */
     int32_t n_used_features; /* observation columns some split tests */
     int32_t reserved;
+    double expected_depth;   /* internal nodes a training-distributed observation
+                                visits per tree (leaf depths weighted by
+                                cardinality): the average depth of Eq. 1 */
 } fp_packed_info;
 
 /*
@@ -224,6 +227,109 @@ int fp_predict(const fp_packed *p, const float *X_dev, int64_t n_rows, int64_t l
 /* fp_predict with explicit launch parameters (NULL: those of p). */
 int fp_predict_tuned(const fp_packed *p, const fp_tune *tune, const float *X_dev, int64_t n_rows,
                      int64_t ld, int32_t *votes_dev, int32_t *class_dev, void *stream);
+
+
+/* ------------------------------------------------------------------------ */
+/* Autotuning (bin size, interleave depth, launch mapping)                    */
+/* ------------------------------------------------------------------------ */
+/*
+ * Sec. III-A chooses the stripe width B and the interleave depth D with a
+ * design experiment on the target processor (Fig. 2).  fp_autotune runs that
+ * experiment on the GPU: it packs the forest with candidate (B, D), times
+ * candidate launch mappings (observations per workgroup, cursors per lane,
+ * workgroup size, tree groups) on a sample of the caller's rows with HIP
+ * events, and returns the fastest combination.  Votes are never changed by
+ * any candidate.  Results are cached per (forest fingerprint, sample size,
+ * options) for the life of the process.
+ *
+ *   X_dev, n_rows, ld  device fp32 rows used for timing (the first
+ *                      min(n_rows, sample_rows) rows are used)
+ *   opts               NULL for defaults; block_threads / cursors > 0 fix
+ *                      those parameters (a batched plan needs one workgroup
+ *                      size and cursor count for all forests)
+ * The library allocates and frees its own temporary device buffers.
+ * Errors: FP_EINVAL, FP_ECORRUPT (forest), FP_ENOMEM, FP_EHIP.
+ */
+typedef struct fp_autotune_opts {
+    int32_t block_threads;  /* 0: search 256, 512, 1024 */
+    int32_t cursors;        /* 0: search 2, 4 */
+    int32_t reps;           /* timed launches per candidate (0: 3) */
+    int32_t reserved;
+    int64_t sample_rows;    /* 0: 65536 */
+    int64_t reserved2;      /* candidates are timed with the default LDS budget
+                               (half of a CU), the one fp_plan_create uses */
+} fp_autotune_opts;
+
+typedef struct fp_autotune_result {
+    fp_pack_opts pack;      /* best bin size / interleave depth (layout PACKED) */
+    fp_tune tune;           /* best launch parameters */
+    double best_ms;         /* time of one launch over the sample, best candidate */
+    double default_ms;      /* same, library defaults (B = T, D = 4) */
+    int32_t n_tried;        /* candidates timed */
+    int32_t cache_hit;      /* 1: answered from the cache, nothing timed */
+} fp_autotune_result;
+
+int fp_autotune(const fp_forest_view *forest, const float *X_dev, int64_t n_rows, int64_t ld,
+                const fp_autotune_opts *opts, fp_autotune_result *out, void *stream);
+
+/* ------------------------------------------------------------------------ */
+/* Batched prediction: many forests, one persistent launch, one hipGraph      */
+/* ------------------------------------------------------------------------ */
+/*
+ * Bins are independent work (Sec. III: each bin is assigned to a thread or a
+ * process); many resident forests with uneven batches are served by one
+ * persistent kernel whose workgroups pull (forest, tree group, row tiles)
+ * work items from a device counter, largest estimated cost first (cost =
+ * rows x trees x expected depth, the cost model of Eqs. 1-2).  The launch is
+ * captured once in a hipGraph (counter reset, vote zeroing, kernel, argmax)
+ * and replayed by fp_predict_batched.
+ *
+ * fp_job: one forest (uploaded, packed layout) with its rows.  Pointers are
+ * fixed when the plan is created and must stay valid while the plan is used:
+ *   X      device fp32 [n_rows][ld]
+ *   votes  device int32 [n_rows][n_classes] (overwritten by every run)
+ *   cls    device int32 [n_rows] or NULL
+ * Each job uses its forest's launch parameters (fp_packed_set_tune, for
+ * example from fp_autotune), except block_threads and cursors, which the plan
+ * fixes for all jobs.
+ */
+typedef struct fp_job {
+    const fp_packed *forest;
+    const float *X;
+    int64_t n_rows;
+    int64_t ld;
+    int32_t *votes;
+    int32_t *cls;
+} fp_job;
+
+typedef struct fp_plan_opts {
+    int32_t block_threads;  /* 0: 512 */
+    int32_t cursors;        /* 0: 4 */
+    int32_t use_graph;      /* 1 (default when opts is NULL): capture a hipGraph; 0: plain launches */
+    int32_t items_per_block;/* work items per persistent workgroup to aim for (0: 4) */
+    int64_t lds_budget;     /* LDS bytes per workgroup (0: half of a CU's LDS) */
+} fp_plan_opts;
+
+typedef struct fp_plan fp_plan;
+
+typedef struct fp_plan_info {
+    int32_t n_jobs, n_items, blocks, block_threads;
+    int32_t cursors, graph, lds_bytes, reserved;
+    double total_cost;      /* sum of estimated node visits */
+} fp_plan_info;
+
+/* Build the work list and (optionally) the graph.  The library allocates the
+ * plan's device tables (released by fp_plan_free).  Errors: FP_EINVAL (bad
+ * job), FP_ENODEV (forest not uploaded / other device), FP_E2BIG (LDS),
+ * FP_ENOMEM, FP_EHIP. */
+int fp_plan_create(const fp_job *jobs, int32_t n_jobs, const fp_plan_opts *opts, fp_plan **out);
+
+/* Run every job of the plan on `stream` (graph replay or plain launches). */
+int fp_predict_batched(fp_plan *plan, void *stream);
+
+int fp_plan_info_get(const fp_plan *plan, fp_plan_info *out);
+
+void fp_plan_free(fp_plan *plan);
 
 #ifdef __cplusplus
 }

@@ -51,7 +51,8 @@ class fp_packed_info(ctypes.Structure):
     _fields_ = [("layout", _i32), ("n_trees", _i32), ("n_features", _i32), ("n_classes", _i32),
                 ("bin_size", _i32), ("interleave_depth", _i32), ("n_bins", _i32), ("max_top_nodes", _i32),
                 ("n_nodes", _i64), ("n_internal", _i64), ("n_leaves", _i64), ("bytes", _i64),
-                ("uploaded", _i32), ("max_depth", _i32), ("n_used_features", _i32), ("reserved", _i32)]
+                ("uploaded", _i32), ("max_depth", _i32), ("n_used_features", _i32), ("reserved", _i32),
+                ("expected_depth", ctypes.c_double)]
 
 
 class fp_tune(ctypes.Structure):
@@ -61,6 +62,31 @@ class fp_tune(ctypes.Structure):
 
 
 TUNE_FIELDS = [f for f, _ in fp_tune._fields_ if f != "reserved"]
+
+
+class fp_autotune_opts(ctypes.Structure):
+    _fields_ = [("block_threads", _i32), ("cursors", _i32), ("reps", _i32), ("reserved", _i32),
+                ("sample_rows", _i64), ("reserved2", _i64)]
+
+
+class fp_autotune_result(ctypes.Structure):
+    _fields_ = [("pack", fp_pack_opts), ("tune", fp_tune), ("best_ms", ctypes.c_double),
+                ("default_ms", ctypes.c_double), ("n_tried", _i32), ("cache_hit", _i32)]
+
+
+class fp_job(ctypes.Structure):
+    _fields_ = [("forest", _vp), ("X", _vp), ("n_rows", _i64), ("ld", _i64), ("votes", _vp), ("cls", _vp)]
+
+
+class fp_plan_opts(ctypes.Structure):
+    _fields_ = [("block_threads", _i32), ("cursors", _i32), ("use_graph", _i32), ("items_per_block", _i32),
+                ("lds_budget", _i64)]
+
+
+class fp_plan_info(ctypes.Structure):
+    _fields_ = [("n_jobs", _i32), ("n_items", _i32), ("blocks", _i32), ("block_threads", _i32),
+                ("cursors", _i32), ("graph", _i32), ("lds_bytes", _i32), ("reserved", _i32),
+                ("total_cost", ctypes.c_double)]
 
 _lib = None
 
@@ -87,6 +113,13 @@ def lib():
             "fp_packed_get_tune": ([_vp, ctypes.POINTER(fp_tune)], ctypes.c_int),
             "fp_predict": ([_vp, _vp, _i64, _i64, _vp, _vp, _vp], ctypes.c_int),
             "fp_predict_tuned": ([_vp, ctypes.POINTER(fp_tune), _vp, _i64, _i64, _vp, _vp, _vp], ctypes.c_int),
+            "fp_autotune": ([ctypes.POINTER(fp_forest_view), _vp, _i64, _i64, ctypes.POINTER(fp_autotune_opts),
+                             ctypes.POINTER(fp_autotune_result), _vp], ctypes.c_int),
+            "fp_plan_create": ([ctypes.POINTER(fp_job), _i32, ctypes.POINTER(fp_plan_opts), ctypes.POINTER(_vp)],
+                               ctypes.c_int),
+            "fp_predict_batched": ([_vp, _vp], ctypes.c_int),
+            "fp_plan_info_get": ([_vp, ctypes.POINTER(fp_plan_info)], ctypes.c_int),
+            "fp_plan_free": ([_vp], None),
         }
         for name, (args, res) in sig.items():
             fn = getattr(L, name)
@@ -288,3 +321,74 @@ def fp_predict_tuned(p: Packed, tune, X, votes=None, cls=None, stream=None, want
                                   _vp(votes.data_ptr()), _vp(cls.data_ptr()) if cls is not None else None,
                                   _stream_ptr(stream)), "fp_predict_tuned")
     return votes, cls
+
+
+# ---------------------------------------------------------------------------
+# autotuning
+# ---------------------------------------------------------------------------
+def fp_autotune(forest, X, block_threads: int = 0, cursors: int = 0, reps: int = 3, sample_rows: int = 0,
+                stream=None) -> dict:
+    """Time candidate (bin size, interleave depth) packings and launch mappings on
+    rows X (CUDA fp32); returns {"pack": {...}, "tune": {...}, "best_ms", "default_ms", ...}."""
+    view, keep = _view_from(forest)
+    n, ld = _check_rows(X, int(forest.n_features))
+    opts = fp_autotune_opts(block_threads, cursors, reps, 0, sample_rows, 0)
+    res = fp_autotune_result()
+    _check(lib().fp_autotune(ctypes.byref(view), _vp(X.data_ptr()), n, ld, ctypes.byref(opts), ctypes.byref(res),
+                             _stream_ptr(stream)), "fp_autotune")
+    del keep
+    return {"pack": {"bin_size": res.pack.bin_size, "interleave_depth": res.pack.interleave_depth,
+                     "line_align": res.pack.line_align},
+            "tune": {k: getattr(res.tune, k) for k in TUNE_FIELDS},
+            "best_ms": res.best_ms, "default_ms": res.default_ms, "n_tried": res.n_tried,
+            "cache_hit": bool(res.cache_hit)}
+
+
+# ---------------------------------------------------------------------------
+# batched plans
+# ---------------------------------------------------------------------------
+class Plan:
+    """Owns an ``fp_plan*``; keeps the jobs' forests and tensors alive."""
+
+    def __init__(self, handle, keep):
+        self.handle = _vp(handle)
+        self._keep = keep
+
+    def __del__(self):
+        h = getattr(self, "handle", None)
+        if h is not None and h.value and _lib is not None:
+            _lib.fp_plan_free(h)
+            self.handle = None
+
+
+def fp_plan_create(jobs, block_threads: int = 0, cursors: int = 0, use_graph: bool = True,
+                   items_per_block: int = 0, lds_budget: int = 0) -> Plan:
+    """jobs: list of (Packed, X, votes, cls-or-None) with CUDA tensors; pointers are fixed in the plan."""
+    arr = (fp_job * len(jobs))()
+    keep = []
+    for i, (p, X, votes, cls) in enumerate(jobs):
+        n, ld = _check_rows(X, fp_packed_info_get(p)["n_features"])
+        arr[i] = fp_job(p.handle.value, X.data_ptr(), n, ld, votes.data_ptr(),
+                        cls.data_ptr() if cls is not None else None)
+        keep.append((p, X, votes, cls))
+    opts = fp_plan_opts(block_threads, cursors, int(bool(use_graph)), items_per_block, lds_budget)
+    out = _vp()
+    _check(lib().fp_plan_create(arr, len(jobs), ctypes.byref(opts), ctypes.byref(out)), "fp_plan_create")
+    return Plan(out.value, keep)
+
+
+def fp_predict_batched(plan: Plan, stream=None) -> None:
+    _check(lib().fp_predict_batched(plan.handle, _stream_ptr(stream)), "fp_predict_batched")
+
+
+def fp_plan_info_get(plan: Plan) -> dict:
+    info = fp_plan_info()
+    _check(lib().fp_plan_info_get(plan.handle, ctypes.byref(info)), "fp_plan_info_get")
+    return {f: getattr(info, f) for f, _ in fp_plan_info._fields_ if f != "reserved"}
+
+
+def fp_plan_free(plan: Plan) -> None:
+    if plan.handle is not None and plan.handle.value:
+        lib().fp_plan_free(plan.handle)
+    plan.handle = None
+    plan._keep = None

@@ -1,0 +1,233 @@
+// Autotuner: the design experiment of Sec. III-A (Fig. 2 sweeps stripe width
+// and interleave depth) run on the GPU, extended to the launch mapping.
+//
+// Coordinate descent, three passes, every candidate timed with HIP events on
+// a sample of the caller's rows:
+//   1. launch mapping (workgroup size, cursors, observations per workgroup)
+//      on the default packing (one bin of all trees, interleave depth 4);
+//   2. packing: interleave depth 0..7 and bin sizes T, 64, 16 with that mapping;
+//   3. launch mapping again on the best packing, plus tree groups (several
+//      workgroups per observation tile, one per group of bins).
+// Votes never depend on the candidate; only time does.
+#include <hip/hip_runtime_api.h>
+
+#include <algorithm>
+#include <cstring>
+#include <map>
+#include <memory>
+#include <mutex>
+#include <new>
+#include <set>
+#include <tuple>
+#include <vector>
+
+#include "fp_internal.h"
+
+namespace {
+
+std::mutex g_cache_mu;
+std::map<uint64_t, fp_autotune_result> g_cache;
+
+uint64_t mix(uint64_t h, const void* p, size_t n) {
+    const uint8_t* b = static_cast<const uint8_t*>(p);
+    for (size_t i = 0; i < n; i++) h = (h ^ b[i]) * 0x100000001b3ull;
+    return h;
+}
+
+uint64_t fingerprint(const fp_forest_view* v, int64_t sample, int threads, int K, int reps) {
+    uint64_t h = 0xcbf29ce484222325ull;
+    int32_t dims[3] = {v->n_trees, v->n_features, v->n_classes};
+    h = mix(h, dims, sizeof dims);
+    const int64_t n = v->tree_node_offset[v->n_trees];
+    h = mix(h, v->tree_node_offset, sizeof(int64_t) * (v->n_trees + 1));
+    h = mix(h, v->feature, 4 * (size_t)n);
+    h = mix(h, v->threshold, 4 * (size_t)n);
+    h = mix(h, v->left, 4 * (size_t)n);
+    h = mix(h, v->right, 4 * (size_t)n);
+    h = mix(h, v->leaf_class, 4 * (size_t)n);
+    int64_t cfg[4] = {sample, threads, K, reps};
+    return mix(h, cfg, sizeof cfg);
+}
+
+struct DevBuf {
+    void* p = nullptr;
+    size_t cap = 0;
+    ~DevBuf() {
+        if (p) (void)hipFree(p);
+    }
+    int ensure(size_t n) {
+        if (n <= cap) return FP_OK;
+        if (p) (void)hipFree(p);
+        p = nullptr;
+        cap = 0;
+        hipError_t e = hipMalloc(&p, n);
+        if (e != hipSuccess) return fp_set_error(FP_ENOMEM, "hipMalloc(%zu): %s", n, hipGetErrorString(e));
+        cap = n;
+        return FP_OK;
+    }
+};
+
+struct PackedPtr {
+    fp_packed* p = nullptr;
+    ~PackedPtr() { fp_packed_free(p); }
+};
+
+}  // namespace
+
+extern "C" int fp_autotune(const fp_forest_view* forest, const float* X, int64_t n_rows, int64_t ld,
+                           const fp_autotune_opts* opts, fp_autotune_result* out, void* stream_v) {
+    fp_clear_error();
+    if (!forest || !out) return fp_set_error(FP_EINVAL, "NULL argument");
+    if (!X || n_rows < 1) return fp_set_error(FP_EINVAL, "autotuning needs at least one device row");
+    if (ld < forest->n_features) return fp_set_error(FP_EINVAL, "ld %lld < n_features %d", (long long)ld, forest->n_features);
+    if (!forest->tree_node_offset || forest->n_trees < 1) return fp_set_error(FP_EINVAL, "empty forest view");
+    memset(out, 0, sizeof *out);
+    const int fixed_threads = opts ? opts->block_threads : 0;
+    const int fixed_K = opts ? opts->cursors : 0;
+    const int reps = opts && opts->reps > 0 ? opts->reps : 3;
+    const int64_t sample = std::min<int64_t>(n_rows, opts && opts->sample_rows > 0 ? opts->sample_rows : 65536);
+    hipStream_t stream = static_cast<hipStream_t>(stream_v);
+
+    const uint64_t key = fingerprint(forest, sample, fixed_threads, fixed_K, reps);
+    {
+        std::lock_guard<std::mutex> lk(g_cache_mu);
+        auto it = g_cache.find(key);
+        if (it != g_cache.end()) {
+            *out = it->second;
+            out->cache_hit = 1;
+            return FP_OK;
+        }
+    }
+
+    try {
+        DevBuf votes, packed_buf;
+        int rc = votes.ensure((size_t)sample * forest->n_classes * 4);
+        if (rc) return rc;
+        hipEvent_t e0 = nullptr, e1 = nullptr;
+        if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) {
+            if (e0) (void)hipEventDestroy(e0);
+            return fp_set_error(FP_EHIP, "hipEventCreate failed");
+        }
+        struct EvGuard {
+            hipEvent_t a, b;
+            ~EvGuard() {
+                (void)hipEventDestroy(a);
+                (void)hipEventDestroy(b);
+            }
+        } evg{e0, e1};
+
+        // pack + upload with memoisation over (bin size, depth)
+        std::map<std::pair<int, int>, std::unique_ptr<PackedPtr>> packs;
+        PackedPtr* current = nullptr;
+        auto use_pack = [&](int B, int D) -> int {
+            auto k = std::make_pair(B, D);
+            if (!packs.count(k)) {
+                std::unique_ptr<PackedPtr> pp(new PackedPtr());
+                fp_pack_opts po{FP_LAYOUT_PACKED, B, D, 0};
+                int r = fp_pack_forest(forest, &po, &pp->p);
+                if (r) return r;
+                packs[k] = std::move(pp);
+            }
+            current = packs[k].get();
+            const size_t bytes = current->p->bytes.size();
+            int r = packed_buf.ensure(bytes);
+            if (r) return r;
+            return fp_packed_upload(current->p, packed_buf.p, packed_buf.cap, stream);
+        };
+        int max_depth = 0;
+        auto time_one = [&](const fp_tune& t, double* ms) -> int {
+            int r = fp_predict_tuned(current->p, &t, X, sample, ld, static_cast<int32_t*>(votes.p), nullptr, stream);
+            if (r) return r;
+            if (hipEventRecord(e0, stream) != hipSuccess) return fp_set_error(FP_EHIP, "hipEventRecord failed");
+            for (int i = 0; i < reps; i++) {
+                r = fp_predict_tuned(current->p, &t, X, sample, ld, static_cast<int32_t*>(votes.p), nullptr, stream);
+                if (r) return r;
+            }
+            if (hipEventRecord(e1, stream) != hipSuccess) return fp_set_error(FP_EHIP, "hipEventRecord failed");
+            if (hipEventSynchronize(e1) != hipSuccess) return fp_set_error(FP_EHIP, "hipEventSynchronize failed");
+            float f = 0.0f;
+            if (hipEventElapsedTime(&f, e0, e1) != hipSuccess) return fp_set_error(FP_EHIP, "hipEventElapsedTime failed");
+            *ms = f / reps;
+            out->n_tried++;
+            return FP_OK;
+        };
+
+        const int T = forest->n_trees;
+        rc = use_pack(T, 4);
+        if (rc) return rc;
+        max_depth = current->p->hdr.max_depth;
+        // library defaults, for reference
+        fp_tune def{};
+        rc = time_one(def, &out->default_ms);
+        if (rc) return rc;
+
+        std::vector<int> thr_set = fixed_threads > 0 ? std::vector<int>{fixed_threads} : std::vector<int>{256, 512, 1024};
+        std::vector<int> k_set = fixed_K > 0 ? std::vector<int>{fixed_K} : std::vector<int>{2, 4};
+        double best = 1e30;
+        fp_tune best_t{};
+        int best_B = T, best_D = 4;
+        auto try_tune = [&](const fp_tune& t) -> int {
+            double ms = 0;
+            int r = time_one(t, &ms);
+            if (r == FP_E2BIG) return FP_OK;  // does not fit: skip the candidate
+            if (r) return r;
+            if (ms < best) {
+                best = ms;
+                best_t = t;
+            }
+            return FP_OK;
+        };
+        // pass 1: launch mapping on the default packing
+        for (int th : thr_set)
+            for (int K : k_set)
+                for (int R : {16, 32, 64}) {
+                    fp_tune t{};
+                    t.rows_per_block = R;
+                    t.cursors = K;
+                    t.block_threads = th;
+                    t.tree_groups = 1;
+                    rc = try_tune(t);
+                    if (rc) return rc;
+                }
+        // pass 2: packing
+        std::set<std::pair<int, int>> tried{{T, 4}};
+        for (int B : {T, 64, 16}) {
+            if (B > T) continue;
+            for (int D = 0; D <= std::min(7, max_depth); D++) {
+                if (!tried.insert({B, D}).second) continue;
+                rc = use_pack(B, D);
+                if (rc) return rc;
+                const double before = best;
+                rc = try_tune(best_t);
+                if (rc) return rc;
+                if (best < before) {
+                    best_B = B;
+                    best_D = D;
+                }
+            }
+        }
+        // pass 3: launch mapping again on the best packing, with tree groups
+        rc = use_pack(best_B, best_D);
+        if (rc) return rc;
+        const fp_tune base = best_t;
+        const int n_bins = current->p->hdr.n_bins;
+        for (int R : {8, 16, 32, 64, 128})
+            for (int G : {1, 2, 4, 8}) {
+                if (G > n_bins || (R == base.rows_per_block && G == 1)) continue;
+                fp_tune t = base;
+                t.rows_per_block = R;
+                t.tree_groups = G;
+                rc = try_tune(t);
+                if (rc) return rc;
+            }
+        out->pack = fp_pack_opts{FP_LAYOUT_PACKED, best_B, best_D, 0};
+        out->tune = best_t;
+        out->best_ms = best;
+        if (hipStreamSynchronize(stream) != hipSuccess) return fp_set_error(FP_EHIP, "hipStreamSynchronize failed");
+        std::lock_guard<std::mutex> lk(g_cache_mu);
+        g_cache[key] = *out;
+        return FP_OK;
+    } catch (const std::bad_alloc&) {
+        return fp_set_error(FP_ENOMEM, "out of host memory");
+    }
+}

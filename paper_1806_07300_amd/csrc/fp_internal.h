@@ -4,6 +4,8 @@
 #include <stdint.h>
 #include <stddef.h>
 
+#include <hip/hip_runtime_api.h>
+
 #include <string>
 #include <vector>
 
@@ -68,7 +70,8 @@ struct Header {
     uint64_t checksum;      // FNV-1a over 64-bit words of bytes [256, total_bytes)
     int32_t n_used_features, pad0;
     int64_t fmap_offset;    // feature map (packed), 0 for naive
-    uint8_t pad[256 - 136];
+    double expected_depth;  // mean over trees of the cardinality-weighted leaf depth
+    uint8_t pad[256 - 144];
 };
 static_assert(sizeof(Header) == 256, "header is 256 bytes");
 
@@ -80,6 +83,72 @@ int verify_buffer(const uint8_t* bytes, size_t n, std::string* why);
 // Device-side limits of the packed kernel.
 constexpr int kMaxClasses = 4096;
 constexpr int kMaxCursors = 8;
+
+// ---------------------------------------------------------------------------
+// Launch descriptors shared by the single-forest and the batched kernels.
+// ---------------------------------------------------------------------------
+
+// Everything a workgroup needs to process one forest on one batch of rows.
+// Plain data: copied to the device as a kernel argument or in a table.
+struct JobDesc {
+    const BinEntry* bins;
+    const int32_t* roots;
+    const int32_t* fmap;
+    const Node16* nodes;
+    const float* X;
+    int64_t ld;
+    int64_t n_rows;
+    int32_t* votes;
+    int32_t* cls;
+    int32_t Fc, Fcp, C;        // used feature columns, LDS row stride (floats), classes
+    int32_t n_bins, bin_size;
+    int32_t R;                 // observations per tile
+    int32_t G, bins_per_group, trees_per_group;
+    int32_t cap;               // LDS nodes reserved per bin of a group (bin-top prefix)
+    int32_t n_tiles;
+    int32_t atomic_votes;      // several tree groups add into the same votes
+    int32_t feat_lds;          // 1: observation tile in LDS, 0: read from memory
+    int32_t off_top, off_ttab, off_fmap, off_xs, off_votes, off_pool, lds_bytes;
+    int32_t pad;
+};
+
+// One entry of the batched work list: tiles [tile_begin, tile_end) of job
+// `job`, trees of tree group `group`.
+struct WorkItem {
+    int32_t job, group, tile_begin, tile_end;
+};
+
+struct DeviceProps {
+    int cus = 0;
+    size_t lds_per_block = 0;
+    size_t lds_per_cu = 0;
+};
+
+int current_device(int* dev);
+int device_props(int dev, DeviceProps* out);
+
+// LDS layout of a job (byte offsets); returns total bytes.
+size_t job_lds_layout(JobDesc* j);
+
+// Fill `j` for forest p, launch parameters t (threads and cursors decided by
+// the caller), rows X.  `lds_block` caps the job's LDS footprint (bytes).
+int resolve_job(const fp_packed* p, const fp_tune* t, const float* X, int64_t n_rows, int64_t ld,
+                int32_t* votes, int32_t* cls, size_t lds_block, JobDesc* j);
+
+// Default LDS footprint of one workgroup: what keeps two workgroups per CU.
+size_t default_lds_block(const DeviceProps& dp);
+
+int packed_occupancy(int K, int fmode, int threads, size_t lds, int* blocks_per_cu);
+int batched_occupancy(int K, int threads, size_t lds, int* blocks_per_cu);
+
+int launch_fill(int32_t* p, int64_t n, int32_t v, hipStream_t s);
+int launch_argmax(const int32_t* votes, int32_t* cls, int64_t n, int32_t C, hipStream_t s);
+int launch_packed(const JobDesc& j, int K, int threads, int blocks, hipStream_t s);
+int launch_batched(const JobDesc* jobs, const WorkItem* items, int32_t n_items, int32_t* counter, int K,
+                   int threads, size_t lds_bytes, int blocks, hipStream_t s);
+// Zero the work counter and the votes of every job that accumulates with atomics.
+int launch_batched_prologue(const JobDesc* jobs_dev, int32_t n_jobs, int32_t* counter, hipStream_t s);
+int launch_batched_epilogue(const JobDesc* jobs_dev, int32_t n_jobs, hipStream_t s);
 
 }  // namespace fp
 

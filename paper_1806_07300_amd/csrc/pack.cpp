@@ -185,11 +185,22 @@ void fill_header_common(Header* h, const fp_forest_view* v, const std::vector<Tr
     h->n_trees = v->n_trees;
     h->n_features = v->n_features;
     h->n_classes = v->n_classes;
+    double depth_sum = 0.0;
     for (const auto& t : s) {
         h->n_internal += t.n_internal;
         h->n_leaves += t.n_leaves;
         h->max_depth = std::max(h->max_depth, t.max_depth);
+        // expected internal nodes visited by a training-distributed observation
+        // (the average depth of Eq. 1): leaf depths weighted by leaf cardinality
+        double num = 0.0, den = 0.0;
+        for (int32_t n : t.bfs)
+            if (v->feature[t.base + n] < 0) {
+                num += (double)t.card[n] * t.depth[n];
+                den += (double)t.card[n];
+            }
+        depth_sum += den > 0 ? num / den : 0.0;
     }
+    h->expected_depth = depth_sum / (double)s.size();
 }
 
 void finish(std::vector<uint8_t>* bytes, Header* h) {
@@ -535,6 +546,7 @@ extern "C" int fp_packed_info_get(const fp_packed* p, fp_packed_info* out) {
     out->uploaded = p->dev != nullptr;
     out->max_depth = h.max_depth;
     out->n_used_features = h.n_used_features;
+    out->expected_depth = h.expected_depth;
     return FP_OK;
 }
 

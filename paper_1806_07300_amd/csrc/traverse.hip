@@ -1,0 +1,588 @@
+// Traversal kernels for gfx950 and the fp_predict entry points.
+//
+//  naive_kernel    the baseline: one lane per observation, trees one after the
+//                  other, every node (leaves included) fetched from memory in
+//                  breadth-first order, features read from memory.  This is the
+//                  GPU form of the BF layout the paper measures against.
+//
+//  packed_kernel   Forest Packing (Sec. III) on CDNA4, one forest:
+//  batched_kernel  the same walk for many forests in one persistent launch.
+//
+// Packed walk.  A work unit is one (observation, tree) walk.  A workgroup owns
+// a tile of R observations -- the feature columns some split tests are staged
+// in LDS -- and the trees of one tree group, whose bins keep their interleaved
+// top levels (Sec. III-A, Bin) in LDS.  The tile's R x trees units form a pool.
+// Every lane keeps K walks in flight (Bin+, Sec. III-B): per step it issues
+// its K node loads, then its K compares, so K independent fetches per lane
+// overlap, as the paper's prefetch plus out-of-order execution does on a CPU.
+// When walks end the wavefront refills all its empty cursors at once: lane 0
+// reserves as many units as there are empty cursors with one LDS atomic, and
+// every empty cursor takes base + (empty cursors on lower lanes), a
+// ballot/mbcnt prefix.  No lane idles behind a long walk while units remain
+// (the longest-path skew noted in Sec. IV-D).  Leaves are class references
+// (DF-), so a walk ends without fetching a leaf; nodes below the interleaved
+// levels follow the Stat order.  Votes are LDS atomics per (observation,
+// class), then stored, or added into global memory with integer atomics when
+// several tree groups share the rows (order-independent: still exact).
+//
+// Split test everywhere: x <= threshold in fp32 (v_cmp_le_f32; NaN -> right).
+// Built without fast-math and without denormal flushing.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <climits>
+#include <cstdio>
+#include <cstring>
+#include <mutex>
+
+#include "fp_internal.h"
+
+using fp::BinEntry;
+using fp::JobDesc;
+using fp::Node16;
+using fp::WorkItem;
+
+namespace {
+
+constexpr int32_t kDone = INT32_MIN;
+
+// ---------------------------------------------------------------------------
+// naive kernel
+// ---------------------------------------------------------------------------
+struct NaiveArgs {
+    const int64_t* tree_off;
+    const Node16* nodes;
+    const float* X;
+    int64_t ld;
+    int64_t n_rows;
+    int32_t* votes;
+    int32_t* cls;
+    int32_t n_trees, C;
+};
+
+template <bool LDS_VOTES>
+__global__ __launch_bounds__(1024) void naive_kernel(NaiveArgs a) {
+    extern __shared__ int32_t vl[];  // [C][blockDim] when LDS_VOTES
+    const int64_t row = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const bool live = row < a.n_rows;
+    const int bd = blockDim.x, tid = threadIdx.x;
+    int32_t* vg = a.votes + (live ? row : 0) * a.C;
+    if (LDS_VOTES) {
+        for (int c = 0; c < a.C; c++) vl[c * bd + tid] = 0;
+    } else if (live) {
+        for (int c = 0; c < a.C; c++) vg[c] = 0;
+    }
+    if (live) {
+        const float* x = a.X + row * a.ld;
+        for (int32_t t = 0; t < a.n_trees; t++) {
+            const Node16* tn = a.nodes + a.tree_off[t];
+            int32_t n = 0;
+            while (true) {
+                const Node16 nd = tn[n];
+                if (nd.feat < 0) {
+                    if (LDS_VOTES) vl[nd.left * bd + tid] += 1;
+                    else vg[nd.left] += 1;
+                    break;
+                }
+                n = (x[nd.feat] <= nd.thr) ? nd.left : nd.right;
+            }
+        }
+        int32_t best = 0, bestv = INT_MIN;
+        for (int c = 0; c < a.C; c++) {
+            const int32_t v = LDS_VOTES ? vl[c * bd + tid] : vg[c];
+            if (LDS_VOTES) vg[c] = v;
+            if (v > bestv) { bestv = v; best = c; }
+        }
+        if (a.cls) a.cls[row] = best;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// packed walk: device pieces shared by the single-forest and batched kernels
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ int lane_id() { return __builtin_amdgcn_mbcnt_hi(~0u, __builtin_amdgcn_mbcnt_lo(~0u, 0u)); }
+__device__ __forceinline__ int bits_below(uint64_t m) {
+    return __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
+}
+
+// Stage the bin tops, the tree table and (when features are read from memory)
+// the feature map of tree group `group`; returns the group's tree count.
+// The caller must have synchronised since the previous use of LDS.
+__device__ int stage_group(const JobDesc& j, int group, unsigned char* smem) {
+    const int tid = threadIdx.x, bd = blockDim.x;
+    const int b_lo = group * j.bins_per_group;
+    const int b_hi = min(b_lo + j.bins_per_group, j.n_bins);
+    if (b_lo >= b_hi) return 0;
+    Node16* top = reinterpret_cast<Node16*>(smem + j.off_top);
+    int4* ttab = reinterpret_cast<int4*>(smem + j.off_ttab);
+    const int t_lo = j.bins[b_lo].first_tree;
+    const int nt = j.bins[b_hi - 1].first_tree + j.bins[b_hi - 1].n_trees - t_lo;
+    for (int i = tid; i < (b_hi - b_lo) * j.cap; i += bd) {
+        const int bl = i / j.cap, k = i - bl * j.cap;
+        const BinEntry& be = j.bins[b_lo + bl];
+        if (k < be.top_len) top[i] = j.nodes[be.node_base + k];
+    }
+    for (int tl = tid; tl < nt; tl += bd) {
+        const int t = t_lo + tl;
+        const int b = t / j.bin_size;
+        const BinEntry& be = j.bins[b];
+        ttab[tl] = make_int4(j.roots[t], (int32_t)be.node_base, (b - b_lo) * j.cap, min(be.top_len, j.cap));
+    }
+    if (!j.feat_lds) {
+        int32_t* fmap_l = reinterpret_cast<int32_t*>(smem + j.off_fmap);
+        for (int c = tid; c < j.Fc; c += bd) fmap_l[c] = j.fmap[c];
+    }
+    return nt;
+}
+
+// FMODE: 0 features from memory, 1 features in LDS, 2 decided by j.feat_lds.
+template <int K, int FMODE>
+__device__ void run_tile(const JobDesc& j, int nt, int tile, unsigned char* smem) {
+    const bool feat_lds = FMODE == 2 ? (j.feat_lds != 0) : (FMODE == 1);
+    const Node16* top = reinterpret_cast<const Node16*>(smem + j.off_top);
+    const int4* ttab = reinterpret_cast<const int4*>(smem + j.off_ttab);
+    const int32_t* fmap_l = reinterpret_cast<const int32_t*>(smem + j.off_fmap);
+    float* xs = reinterpret_cast<float*>(smem + j.off_xs);
+    int32_t* vl = reinterpret_cast<int32_t*>(smem + j.off_votes);
+    int32_t* pool = reinterpret_cast<int32_t*>(smem + j.off_pool);
+    const int tid = threadIdx.x, bd = blockDim.x;
+    const int lane = lane_id();
+
+    const int64_t row0 = (int64_t)tile * j.R;
+    const int rows_here = (int)min<int64_t>(j.R, j.n_rows - row0);
+    if (feat_lds) {
+        const int total = rows_here * j.Fc;
+        for (int i = tid; i < total; i += bd) {
+            const int rr = i / j.Fc, c = i - rr * j.Fc;
+            xs[rr * j.Fcp + c] = j.X[(row0 + rr) * j.ld + j.fmap[c]];
+        }
+    }
+    for (int i = tid; i < rows_here * j.C; i += bd) vl[i] = 0;
+    if (tid == 0) *pool = 0;
+    __syncthreads();
+
+    const int U = rows_here * nt;
+    int32_t ref[K], rowk[K], gb[K], lb[K], cp[K];
+#pragma unroll
+    for (int k = 0; k < K; k++) { ref[k] = kDone; rowk[k] = 0; gb[k] = 0; lb[k] = 0; cp[k] = 0; }
+    bool drained = false;  // wave-uniform: the pool has no units left
+    while (true) {
+        if (!drained) {
+#pragma unroll
+            for (int k = 0; k < K; k++) {
+                while (!drained) {
+                    const uint64_t m = __ballot(ref[k] == kDone);
+                    if (m == 0) break;
+                    const int cnt = (int)__popcll(m);
+                    int base = 0;
+                    if (lane == 0) base = atomicAdd(pool, cnt);
+                    base = __builtin_amdgcn_readfirstlane(base);
+                    if (base >= U) { drained = true; break; }
+                    if (ref[k] == kDone) {
+                        const int u = base + bits_below(m);
+                        if (u < U) {
+                            const int r = u % rows_here;
+                            const int4 e = ttab[u / rows_here];
+                            rowk[k] = r; gb[k] = e.y; lb[k] = e.z; cp[k] = e.w;
+                            if (e.x < 0) atomicAdd(&vl[r * j.C - e.x - 1], 1);  // the root is a leaf
+                            else ref[k] = e.x;
+                        }
+                    }
+                    if (base + cnt >= U) drained = true;
+                }
+            }
+        }
+        bool live = false;
+#pragma unroll
+        for (int k = 0; k < K; k++) live |= ref[k] >= 0;
+        if (__ballot(live) == 0) break;
+        Node16 nd[K];
+#pragma unroll
+        for (int k = 0; k < K; k++)
+            if (ref[k] >= 0) nd[k] = ref[k] < cp[k] ? top[lb[k] + ref[k]] : j.nodes[gb[k] + ref[k]];
+#pragma unroll
+        for (int k = 0; k < K; k++) {
+            if (ref[k] >= 0) {
+                const float x = feat_lds ? xs[rowk[k] * j.Fcp + nd[k].feat]
+                                         : j.X[(row0 + rowk[k]) * j.ld + fmap_l[nd[k].feat]];
+                int32_t nr = (x <= nd[k].thr) ? nd[k].left : nd[k].right;
+                if (nr < 0) {
+                    atomicAdd(&vl[rowk[k] * j.C - nr - 1], 1);
+                    nr = kDone;
+                }
+                ref[k] = nr;
+            }
+        }
+    }
+    __syncthreads();
+    for (int i = tid; i < rows_here * j.C; i += bd) {
+        int32_t* dst = j.votes + row0 * j.C + i;
+        if (j.atomic_votes) {
+            if (vl[i]) atomicAdd(dst, vl[i]);
+        } else {
+            *dst = vl[i];
+        }
+    }
+    if (!j.atomic_votes && j.cls) {
+        for (int rr = tid; rr < rows_here; rr += bd) {
+            int32_t best = 0, bestv = vl[rr * j.C];
+            for (int c = 1; c < j.C; c++)
+                if (vl[rr * j.C + c] > bestv) { bestv = vl[rr * j.C + c]; best = c; }
+            j.cls[row0 + rr] = best;
+        }
+    }
+    __syncthreads();
+}
+
+// One forest: persistent workgroups, group = blockIdx % G (consecutive
+// workgroups land on different XCDs, so G = 8 gives each XCD its own trees).
+template <int K, int FMODE>
+__global__ __launch_bounds__(1024) void packed_kernel(JobDesc j) {
+    extern __shared__ __align__(16) unsigned char smem[];
+    const int group = blockIdx.x % j.G;
+    const int blocks_per_group = gridDim.x / j.G;
+    const int nt = stage_group(j, group, smem);
+    if (nt == 0) return;  // uniform per block
+    for (int tile = blockIdx.x / j.G; tile < j.n_tiles; tile += blocks_per_group) run_tile<K, FMODE>(j, nt, tile, smem);
+}
+
+// Many forests: persistent workgroups pull work items from a global counter
+// (items are ordered largest first) and restage LDS when the (job, group)
+// changes.  Every workgroup exits once the counter passes n_items.
+template <int K>
+__global__ __launch_bounds__(1024) void batched_kernel(const JobDesc* __restrict__ jobs, const WorkItem* __restrict__ items,
+                                                       int32_t n_items, int32_t* counter) {
+    extern __shared__ __align__(16) unsigned char smem[];
+    __shared__ int32_t s_item;
+    int staged_job = -1, staged_group = -1, nt = 0;
+    while (true) {
+        if (threadIdx.x == 0) s_item = atomicAdd(counter, 1);
+        __syncthreads();
+        const int it = s_item;
+        __syncthreads();
+        if (it >= n_items) break;
+        const WorkItem w = items[it];
+        const JobDesc j = jobs[w.job];
+        if (w.job != staged_job || w.group != staged_group) {
+            nt = stage_group(j, w.group, smem);
+            staged_job = w.job;
+            staged_group = w.group;
+        }
+        if (nt == 0) continue;
+        for (int tile = w.tile_begin; tile < w.tile_end; tile++) run_tile<K, 2>(j, nt, tile, smem);
+    }
+}
+
+__global__ void fill_i32_kernel(int32_t* p, int64_t n, int32_t v) {
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        p[i] = v;
+}
+
+__global__ void argmax_kernel(const int32_t* votes, int32_t* cls, int64_t n, int32_t C) {
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+        const int32_t* v = votes + i * C;
+        int32_t best = 0, bestv = v[0];
+        for (int c = 1; c < C; c++)
+            if (v[c] > bestv) { bestv = v[c]; best = c; }
+        cls[i] = best;
+    }
+}
+
+// blockIdx.y = job: zero the votes of jobs that accumulate with atomics;
+// block (0, 0) also clears the work counter.
+__global__ void batched_prologue_kernel(const JobDesc* jobs, int32_t* counter) {
+    if (blockIdx.x == 0 && blockIdx.y == 0 && threadIdx.x == 0) *counter = 0;
+    const JobDesc& j = jobs[blockIdx.y];
+    if (!j.atomic_votes) return;
+    const int64_t n = j.n_rows * j.C;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        j.votes[i] = 0;
+}
+
+__global__ void batched_epilogue_kernel(const JobDesc* jobs) {
+    const JobDesc& j = jobs[blockIdx.y];
+    if (!j.atomic_votes || !j.cls) return;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < j.n_rows; i += (int64_t)gridDim.x * blockDim.x) {
+        const int32_t* v = j.votes + i * j.C;
+        int32_t best = 0, bestv = v[0];
+        for (int c = 1; c < j.C; c++)
+            if (v[c] > bestv) { bestv = v[c]; best = c; }
+        j.cls[i] = best;
+    }
+}
+
+int check_launch(const char* what) {
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return fp_set_error(FP_EHIP, "%s launch: %s", what, hipGetErrorString(e));
+    return FP_OK;
+}
+
+template <int K, int FM>
+const void* packed_fn() {
+    return reinterpret_cast<const void*>(&packed_kernel<K, FM>);
+}
+
+const void* pick_packed(int K, int fmode) {
+#define FP_PICK(KK) \
+    if (K == KK) return fmode == 0 ? packed_fn<KK, 0>() : fmode == 1 ? packed_fn<KK, 1>() : packed_fn<KK, 2>();
+    FP_PICK(1)
+    FP_PICK(2)
+    FP_PICK(4)
+    FP_PICK(8)
+#undef FP_PICK
+    return nullptr;
+}
+
+const void* pick_batched(int K) {
+    switch (K) {
+        case 1: return reinterpret_cast<const void*>(&batched_kernel<1>);
+        case 2: return reinterpret_cast<const void*>(&batched_kernel<2>);
+        case 4: return reinterpret_cast<const void*>(&batched_kernel<4>);
+        case 8: return reinterpret_cast<const void*>(&batched_kernel<8>);
+        default: return nullptr;
+    }
+}
+
+std::mutex g_props_mu;
+fp::DeviceProps g_props[64];
+bool g_props_ok[64];
+
+size_t round16(size_t v) { return (v + 15) / 16 * 16; }
+
+}  // namespace
+
+namespace fp {
+
+int current_device(int* dev) {
+    hipError_t e = hipGetDevice(dev);
+    if (e != hipSuccess) return fp_set_error(FP_EHIP, "hipGetDevice: %s", hipGetErrorString(e));
+    return FP_OK;
+}
+
+int device_props(int dev, DeviceProps* out) {
+    if (dev < 0 || dev >= 64) return fp_set_error(FP_ENODEV, "device id %d out of range", dev);
+    std::lock_guard<std::mutex> lk(g_props_mu);
+    if (!g_props_ok[dev]) {
+        hipDeviceProp_t pr;
+        hipError_t e = hipGetDeviceProperties(&pr, dev);
+        if (e != hipSuccess) return fp_set_error(FP_EHIP, "hipGetDeviceProperties: %s", hipGetErrorString(e));
+        g_props[dev].cus = pr.multiProcessorCount;
+        g_props[dev].lds_per_block = pr.sharedMemPerBlock;
+        g_props[dev].lds_per_cu = pr.maxSharedMemoryPerMultiProcessor;
+        g_props_ok[dev] = true;
+    }
+    *out = g_props[dev];
+    return FP_OK;
+}
+
+size_t default_lds_block(const DeviceProps& dp) {
+    const size_t blk = dp.lds_per_block ? dp.lds_per_block : 65536;
+    const size_t cu = dp.lds_per_cu ? dp.lds_per_cu : blk;
+    return std::min(blk, cu / 2);
+}
+
+size_t job_lds_layout(JobDesc* j) {
+    size_t o = 0;
+    j->off_top = (int32_t)o;   o += (size_t)j->cap * j->bins_per_group * sizeof(Node16);
+    j->off_ttab = (int32_t)o;  o += (size_t)j->trees_per_group * 16;
+    j->off_fmap = (int32_t)o;  o += j->feat_lds ? 0 : round16((size_t)j->Fc * 4);
+    j->off_xs = (int32_t)o;    o += j->feat_lds ? round16((size_t)j->R * j->Fcp * 4) : 0;
+    j->off_votes = (int32_t)o; o += round16((size_t)j->R * j->C * 4);
+    j->off_pool = (int32_t)o;  o += 16;
+    j->lds_bytes = (int32_t)o;
+    return o;
+}
+
+int resolve_job(const fp_packed* p, const fp_tune* t, const float* X, int64_t n_rows, int64_t ld, int32_t* votes,
+                int32_t* cls, size_t lds_block, JobDesc* j) {
+    const Header& h = p->hdr;
+    if (h.layout != FP_LAYOUT_PACKED) return fp_set_error(FP_EINVAL, "forest is not in the packed layout");
+    if (!p->dev) return fp_set_error(FP_ENODEV, "packed forest is not uploaded");
+    if (h.n_nodes >= INT32_MAX)
+        return fp_set_error(FP_E2BIG, "packed forest has %lld nodes (limit 2^31-1)", (long long)h.n_nodes);
+    const int R = t->rows_per_block > 0 ? t->rows_per_block : 16;
+    if (R > 4096) return fp_set_error(FP_EINVAL, "rows_per_block %d exceeds 4096", R);
+    int G = t->tree_groups > 0 ? t->tree_groups : 1;
+    if (G > h.n_bins) G = h.n_bins;
+    const int bpg = (h.n_bins + G - 1) / G;
+    const int tpg = (int)std::min<int64_t>((int64_t)bpg * h.bin_size, h.n_trees);
+    if ((int64_t)R * tpg >= (1 << 30)) return fp_set_error(FP_E2BIG, "rows_per_block x trees per group too large");
+    const uint8_t* base = static_cast<const uint8_t*>(p->dev);
+    memset(j, 0, sizeof *j);
+    j->bins = reinterpret_cast<const BinEntry*>(base + h.table_offset);
+    j->roots = reinterpret_cast<const int32_t*>(base + h.roots_offset);
+    j->fmap = reinterpret_cast<const int32_t*>(base + h.fmap_offset);
+    j->nodes = reinterpret_cast<const Node16*>(base + h.nodes_offset);
+    j->X = X;
+    j->ld = ld;
+    j->n_rows = n_rows;
+    j->votes = votes;
+    j->cls = cls;
+    j->Fc = h.n_used_features;
+    j->Fcp = h.n_used_features | 1;
+    j->C = h.n_classes;
+    j->n_bins = h.n_bins;
+    j->bin_size = h.bin_size;
+    j->R = R;
+    j->G = G;
+    j->bins_per_group = bpg;
+    j->trees_per_group = tpg;
+    j->n_tiles = (int32_t)((n_rows + R - 1) / R);
+    j->atomic_votes = G > 1;
+    // feature_lds: 1 force LDS staging, -1 read features from memory, 0 automatic
+    j->feat_lds = t->feature_lds >= 0;
+    j->cap = 0;
+    size_t need = job_lds_layout(j);
+    if (need > lds_block) {
+        if (t->feature_lds == 1)
+            return fp_set_error(FP_E2BIG, "observation tile of %d rows x %d columns does not fit in %zu bytes of LDS",
+                                R, j->Fc, lds_block);
+        j->feat_lds = 0;
+        need = job_lds_layout(j);
+        if (need > lds_block)
+            return fp_set_error(FP_E2BIG, "per-workgroup tables of %zu bytes exceed %zu bytes of LDS", need, lds_block);
+    }
+    size_t top_nodes = (lds_block - need) / sizeof(Node16);
+    if (t->lds_top_nodes < 0) top_nodes = 0;
+    else if (t->lds_top_nodes > 0) top_nodes = std::min(top_nodes, (size_t)t->lds_top_nodes);
+    j->cap = (int32_t)std::min<size_t>(top_nodes / bpg, (size_t)h.max_top_len);
+    job_lds_layout(j);
+    return FP_OK;
+}
+
+int packed_occupancy(int K, int fmode, int threads, size_t lds, int* blocks_per_cu) {
+    const void* fn = pick_packed(K, fmode);
+    if (!fn) return fp_set_error(FP_EINVAL, "cursors must be 1, 2, 4 or 8");
+    int occ = 0;
+    hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, fn, threads, lds);
+    *blocks_per_cu = (e == hipSuccess && occ > 0) ? occ : 1;
+    return FP_OK;
+}
+
+int batched_occupancy(int K, int threads, size_t lds, int* blocks_per_cu) {
+    const void* fn = pick_batched(K);
+    if (!fn) return fp_set_error(FP_EINVAL, "cursors must be 1, 2, 4 or 8");
+    int occ = 0;
+    hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, fn, threads, lds);
+    *blocks_per_cu = (e == hipSuccess && occ > 0) ? occ : 1;
+    return FP_OK;
+}
+
+int launch_fill(int32_t* p, int64_t n, int32_t v, hipStream_t s) {
+    if (n <= 0) return FP_OK;
+    hipLaunchKernelGGL(fill_i32_kernel, dim3((unsigned)std::min<int64_t>((n + 255) / 256, 4096)), dim3(256), 0, s, p, n, v);
+    return check_launch("fill_i32_kernel");
+}
+
+int launch_argmax(const int32_t* votes, int32_t* cls, int64_t n, int32_t C, hipStream_t s) {
+    if (n <= 0) return FP_OK;
+    hipLaunchKernelGGL(argmax_kernel, dim3((unsigned)std::min<int64_t>((n + 255) / 256, 4096)), dim3(256), 0, s, votes,
+                       cls, n, C);
+    return check_launch("argmax_kernel");
+}
+
+int launch_packed(const JobDesc& j, int K, int threads, int blocks, hipStream_t s) {
+    const void* fn = pick_packed(K, j.feat_lds ? 1 : 0);
+    if (!fn) return fp_set_error(FP_EINVAL, "cursors must be 1, 2, 4 or 8");
+    JobDesc a = j;
+    void* args[] = {&a};
+    hipError_t e = hipLaunchKernel(fn, dim3(blocks), dim3(threads), args, (size_t)j.lds_bytes, s);
+    if (e != hipSuccess) return fp_set_error(FP_EHIP, "packed_kernel launch: %s", hipGetErrorString(e));
+    return FP_OK;
+}
+
+int launch_batched(const JobDesc* jobs, const WorkItem* items, int32_t n_items, int32_t* counter, int K, int threads,
+                   size_t lds_bytes, int blocks, hipStream_t s) {
+    const void* fn = pick_batched(K);
+    if (!fn) return fp_set_error(FP_EINVAL, "cursors must be 1, 2, 4 or 8");
+    void* args[] = {&jobs, &items, &n_items, &counter};
+    hipError_t e = hipLaunchKernel(fn, dim3(blocks), dim3(threads), args, lds_bytes, s);
+    if (e != hipSuccess) return fp_set_error(FP_EHIP, "batched_kernel launch: %s", hipGetErrorString(e));
+    return FP_OK;
+}
+
+int launch_batched_prologue(const JobDesc* jobs_dev, int32_t n_jobs, int32_t* counter, hipStream_t s) {
+    hipLaunchKernelGGL(batched_prologue_kernel, dim3(64, n_jobs), dim3(256), 0, s, jobs_dev, counter);
+    return check_launch("batched_prologue_kernel");
+}
+
+int launch_batched_epilogue(const JobDesc* jobs_dev, int32_t n_jobs, hipStream_t s) {
+    hipLaunchKernelGGL(batched_epilogue_kernel, dim3(64, n_jobs), dim3(256), 0, s, jobs_dev);
+    return check_launch("batched_epilogue_kernel");
+}
+
+}  // namespace fp
+
+// ---------------------------------------------------------------------------
+// single-forest entry points
+// ---------------------------------------------------------------------------
+static int predict_impl(const fp_packed* p, const fp_tune* tune, const float* X, int64_t n_rows, int64_t ld,
+                        int32_t* votes, int32_t* cls, void* stream_v) {
+    fp_clear_error();
+    if (!p) return fp_set_error(FP_EINVAL, "packed forest is NULL");
+    const fp::Header& h = p->hdr;
+    if (n_rows < 0 || n_rows > INT32_MAX) return fp_set_error(FP_EINVAL, "n_rows %lld outside [0, 2^31)", (long long)n_rows);
+    if (ld < h.n_features) return fp_set_error(FP_EINVAL, "ld %lld < n_features %d", (long long)ld, h.n_features);
+    if (n_rows == 0) return FP_OK;
+    if (!X || !votes) return fp_set_error(FP_EINVAL, "X or votes is NULL");
+    if (!p->dev) return fp_set_error(FP_ENODEV, "packed forest is not uploaded");
+    int dev = -1;
+    int rc = fp::current_device(&dev);
+    if (rc) return rc;
+    if (dev != p->dev_id) return fp_set_error(FP_ENODEV, "forest uploaded to device %d, current device is %d", p->dev_id, dev);
+    fp::DeviceProps dp;
+    rc = fp::device_props(dev, &dp);
+    if (rc) return rc;
+    hipStream_t stream = static_cast<hipStream_t>(stream_v);
+    const int threads = tune && tune->block_threads > 0 ? tune->block_threads : 256;
+    if (threads % 64 || threads < 64 || threads > 1024)
+        return fp_set_error(FP_EINVAL, "block_threads %d must be a multiple of 64 in [64, 1024]", threads);
+
+    if (h.layout == FP_LAYOUT_NAIVE) {
+        const uint8_t* base = static_cast<const uint8_t*>(p->dev);
+        NaiveArgs a{reinterpret_cast<const int64_t*>(base + h.table_offset),
+                    reinterpret_cast<const Node16*>(base + h.nodes_offset), X, ld, n_rows, votes, cls, h.n_trees,
+                    h.n_classes};
+        const size_t lds = (size_t)h.n_classes * threads * 4;
+        const bool use_lds = lds <= 32768;
+        const int blocks = (int)((n_rows + threads - 1) / threads);
+        if (use_lds)
+            hipLaunchKernelGGL(naive_kernel<true>, dim3(blocks), dim3(threads), lds, stream, a);
+        else
+            hipLaunchKernelGGL(naive_kernel<false>, dim3(blocks), dim3(threads), 0, stream, a);
+        return check_launch("naive_kernel");
+    }
+
+    const int K = tune && tune->cursors > 0 ? tune->cursors : 2;
+    if (K != 1 && K != 2 && K != 4 && K != 8) return fp_set_error(FP_EINVAL, "cursors must be 1, 2, 4 or 8");
+    const size_t lds_block = tune && tune->lds_top_nodes > 0 ? (dp.lds_per_block ? dp.lds_per_block : 65536)
+                                                              : fp::default_lds_block(dp);
+    fp::JobDesc j;
+    rc = fp::resolve_job(p, tune, X, n_rows, ld, votes, cls, lds_block, &j);
+    if (rc) return rc;
+    int occ = 1;
+    rc = fp::packed_occupancy(K, j.feat_lds, threads, (size_t)j.lds_bytes, &occ);
+    if (rc) return rc;
+    const int64_t per_group = std::min<int64_t>(j.n_tiles, std::max<int64_t>(1, (int64_t)dp.cus * occ / j.G));
+    const int blocks = (int)std::max<int64_t>(1, per_group) * j.G;
+    if (j.atomic_votes) {
+        rc = fp::launch_fill(votes, n_rows * h.n_classes, 0, stream);
+        if (rc) return rc;
+    }
+    rc = fp::launch_packed(j, K, threads, blocks, stream);
+    if (rc) return rc;
+    if (j.atomic_votes && cls) return fp::launch_argmax(votes, cls, n_rows, h.n_classes, stream);
+    return FP_OK;
+}
+
+extern "C" int fp_predict(const fp_packed* p, const float* X_dev, int64_t n_rows, int64_t ld, int32_t* votes_dev,
+                          int32_t* class_dev, void* stream) {
+    if (!p) return fp_set_error(FP_EINVAL, "packed forest is NULL");
+    return predict_impl(p, &p->tune, X_dev, n_rows, ld, votes_dev, class_dev, stream);
+}
+
+extern "C" int fp_predict_tuned(const fp_packed* p, const fp_tune* tune, const float* X_dev, int64_t n_rows,
+                                int64_t ld, int32_t* votes_dev, int32_t* class_dev, void* stream) {
+    if (!p) return fp_set_error(FP_EINVAL, "packed forest is NULL");
+    return predict_impl(p, tune ? tune : &p->tune, X_dev, n_rows, ld, votes_dev, class_dev, stream);
+}

@@ -6,7 +6,7 @@ import struct
 
 import numpy as np
 
-HEADER = struct.Struct("<QIi" + "i" * 8 + "q" * 7 + "ii" + "Q" + "ii" + "q")
+HEADER = struct.Struct("<QIi" + "i" * 8 + "q" * 7 + "ii" + "Q" + "ii" + "q" + "d")
 NODE = np.dtype([("thr", "<f4"), ("feat", "<i4"), ("left", "<i4"), ("right", "<i4")])
 BIN = np.dtype([("node_base", "<i8"), ("first_tree", "<i4"), ("n_trees", "<i4"), ("top_len", "<i4"),
                 ("deep_len", "<i4"), ("root_base", "<i4"), ("pad", "<i4")])
@@ -18,7 +18,7 @@ def decode(buf: np.ndarray) -> dict:
     keys = ["magic", "version", "layout", "n_trees", "n_features", "n_classes", "bin_size",
             "interleave_depth", "n_bins", "max_top_len", "max_bin_trees", "total_bytes", "table_offset",
             "roots_offset", "nodes_offset", "n_nodes", "n_internal", "n_leaves", "max_depth", "line_align",
-            "checksum", "n_used_features", "pad0", "fmap_offset"]
+            "checksum", "n_used_features", "pad0", "fmap_offset", "expected_depth"]
     h = dict(zip(keys, f))
     nodes = np.frombuffer(b, NODE, count=h["n_nodes"], offset=h["nodes_offset"])
     out = {"h": h, "nodes": nodes}

@@ -1,0 +1,140 @@
+"""GPU parity of the batched path (many forests, one persistent launch in a
+hipGraph) and of the autotuner: every forest's votes equal the CPU checker's
+and its own single-forest prediction, bit for bit, on every graph replay."""
+import os
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import paper_1806_07300_amd as fp
+import synth
+
+pytestmark = pytest.mark.gpu
+
+CACHE = os.environ.get("FP_TEST_CACHE", "/tmp/forestpack_cache")
+
+SMALL_SPECS = [  # (trees, features, classes, rows, max_depth, bin, depth, tune)
+    (16, 4, 2, 1, 12, 16, 3, {}),
+    (40, 30, 3, 17, 6, 8, 2, {"rows_per_block": 8}),
+    (64, 100, 5, 1000, 12, 64, 4, {"rows_per_block": 32, "tree_groups": 1}),
+    (33, 7, 2, 5000, -1, 16, 1, {"rows_per_block": 16, "tree_groups": 3}),
+    (20, 12, 6, 0, 12, 20, 3, {}),
+    (48, 60, 4, 2049, 10, 4, 5, {"rows_per_block": 64, "feature_lds": -1}),
+    (1, 5, 2, 300, 8, 1, 0, {"rows_per_block": 1}),
+    (57, 9, 10, 3000, 12, 19, 3, {"rows_per_block": 32, "tree_groups": 2, "lds_top_nodes": 40}),
+]
+
+
+def make_job(i, spec):
+    T, F, C, N, depth, B, D, tune = spec
+    Xt, yt = synth.gaussian_mixture(3000, F, C, seed=500 + i)
+    f = synth.train_forest(Xt, yt, n_trees=T, n_classes=C, mtry=max(1, int(np.sqrt(F))), max_depth=depth, seed=600 + i)
+    X, _ = synth.gaussian_mixture(N, F, C, seed=700 + i)
+    p = fp.fp_pack_forest(f, bin_size=B, interleave_depth=D)
+    fp.fp_packed_upload(p)
+    if tune:
+        fp.fp_packed_set_tune(p, tune)
+    Xd = torch.from_numpy(X).cuda()
+    votes = torch.full((N, C), -7, dtype=torch.int32, device="cuda")
+    cls = torch.full((N,), -7, dtype=torch.int32, device="cuda")
+    return {"forest": f, "X": X, "packed": p, "Xd": Xd, "votes": votes, "cls": cls, "tune": tune}
+
+
+@pytest.fixture(scope="module")
+def small_jobs():
+    jobs = [make_job(i, s) for i, s in enumerate(SMALL_SPECS)]
+    for j in jobs:
+        j["want"] = oracle.predict(j["forest"], j["X"])
+    return jobs
+
+
+def check_jobs(jobs, what):
+    torch.cuda.synchronize()
+    for i, j in enumerate(jobs):
+        wv, wc = j["want"]
+        gv, gc = j["votes"].cpu().numpy(), j["cls"].cpu().numpy()
+        assert np.array_equal(gv, wv), f"{what}: job {i} votes differ"
+        assert np.array_equal(gc, wc), f"{what}: job {i} classes differ"
+
+
+@pytest.mark.parametrize("use_graph", [True, False])
+@pytest.mark.parametrize("threads,cursors", [(512, 4), (256, 2), (1024, 1)])
+def test_batched_small(small_jobs, use_graph, threads, cursors):
+    plan = fp.fp_plan_create([(j["packed"], j["Xd"], j["votes"], j["cls"]) for j in small_jobs],
+                             block_threads=threads, cursors=cursors, use_graph=use_graph)
+    info = fp.fp_plan_info_get(plan)
+    assert info["graph"] == int(use_graph) and info["n_jobs"] == len(small_jobs)
+    for replay in range(3):
+        # eager work between replays: scribble over every output
+        for j in small_jobs:
+            j["votes"].fill_(-1)
+            j["cls"].fill_(-1)
+        fp.fp_predict_batched(plan)
+        check_jobs(small_jobs, f"graph={use_graph} replay {replay}")
+        torch.cuda.synchronize()
+
+
+def test_batched_equals_solo(small_jobs):
+    for j in small_jobs:
+        if j["X"].shape[0] == 0:
+            continue
+        v, c = fp.fp_predict(j["packed"], j["Xd"])
+        torch.cuda.synchronize()
+        assert np.array_equal(v.cpu().numpy(), j["want"][0])
+        assert np.array_equal(c.cpu().numpy(), j["want"][1])
+
+
+def test_autotune_small(small_jobs):
+    j = small_jobs[2]
+    res = fp.fp_autotune(j["forest"], j["Xd"], block_threads=512, cursors=4, sample_rows=1000)
+    assert res["n_tried"] > 5 and res["best_ms"] > 0 and not res["cache_hit"]
+    assert res["tune"]["block_threads"] == 512 and res["tune"]["cursors"] == 4
+    again = fp.fp_autotune(j["forest"], j["Xd"], block_threads=512, cursors=4, sample_rows=1000)
+    assert again["cache_hit"] and again["pack"] == res["pack"]
+    p = fp.fp_pack_forest(j["forest"], **res["pack"])
+    fp.fp_packed_upload(p)
+    v, c = fp.fp_predict_tuned(p, res["tune"], j["Xd"])
+    torch.cuda.synchronize()
+    assert np.array_equal(v.cpu().numpy(), j["want"][0]) and np.array_equal(c.cpu().numpy(), j["want"][1])
+
+
+def test_batched_workload_64_forests():
+    """The 64-forest workload (16-2048 trees, 4-784 features, 2-10 classes,
+    1-200,000 rows each), every forest autotuned, one persistent graph launch.
+    Every row's votes sum to its forest's tree count; sampled rows match the
+    checker; every forest matches its single-forest prediction exactly."""
+    threads, cursors = 512, 4
+    jobs = []
+    for i in range(64):
+        w = synth.batched_workload(i)
+        f = w.forest(cache_dir=CACHE)
+        X, _ = w.predict_rows()
+        Xd = torch.from_numpy(X).cuda()
+        res = fp.fp_autotune(f, Xd, block_threads=threads, cursors=cursors, sample_rows=16384)
+        p = fp.fp_pack_forest(f, **res["pack"])
+        fp.fp_packed_upload(p)
+        fp.fp_packed_set_tune(p, res["tune"])
+        votes = torch.full((len(X), f.n_classes), -7, dtype=torch.int32, device="cuda")
+        cls = torch.full((len(X),), -7, dtype=torch.int32, device="cuda")
+        jobs.append({"forest": f, "X": X, "Xd": Xd, "packed": p, "votes": votes, "cls": cls})
+    plan = fp.fp_plan_create([(j["packed"], j["Xd"], j["votes"], j["cls"]) for j in jobs],
+                             block_threads=threads, cursors=cursors)
+    rng = np.random.default_rng(3)
+    for replay in range(2):
+        for j in jobs:
+            j["votes"].fill_(-1)
+        fp.fp_predict_batched(plan)
+        torch.cuda.synchronize()
+        for i, j in enumerate(jobs):
+            f, X = j["forest"], j["X"]
+            gv, gc = j["votes"].cpu().numpy(), j["cls"].cpu().numpy()
+            assert (gv.sum(1) == f.n_trees).all(), f"forest {i}: votes do not sum to T"
+            rows = np.unique(np.concatenate([[0, len(X) - 1], rng.integers(0, len(X), 300)]))
+            wv, wc = oracle.predict(f, X[rows])
+            assert np.array_equal(gv[rows], wv) and np.array_equal(gc[rows], wc), f"forest {i} vs checker"
+            if replay == 0:
+                sv, sc = fp.fp_predict(j["packed"], j["Xd"])
+                torch.cuda.synchronize()
+                assert np.array_equal(sv.cpu().numpy(), gv) and np.array_equal(sc.cpu().numpy(), gc), f"forest {i} solo"
