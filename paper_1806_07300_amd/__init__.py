@@ -286,10 +286,13 @@ def _check_rows(X, n_features):
     import torch
     if not (isinstance(X, torch.Tensor) and X.is_cuda and X.dtype == torch.float32 and X.dim() == 2):
         raise FPError(FP_EINVAL, "fp_predict", "X must be a 2-D float32 CUDA tensor")
-    if X.stride(1) != 1:
+    n = X.shape[0]
+    if n == 0:
+        return 0, max(X.shape[1], n_features)
+    if X.shape[1] > 1 and X.stride(1) != 1:
         raise FPError(FP_EINVAL, "fp_predict", "X rows must be contiguous (stride(1) == 1)")
-    ld = X.stride(0) if X.shape[0] > 1 else max(X.shape[1], n_features)
-    return X.shape[0], ld
+    ld = X.stride(0) if n > 1 else X.shape[1]
+    return n, ld
 
 
 def _outputs(n, C, votes, cls, want_cls):
