@@ -93,6 +93,106 @@ def cpu_baseline(forest, X, target_s=10.0):
             "sample": f"first {n} rows of the batch, all {n_threads} host threads, {dt:.1f} s"}, visits / n
 
 
+def serve_leg(fp, synth, np, torch, image_forest, seconds, warm, rate, cache, submit_threads=4):
+    """Open-loop serving measurement: 8 resident forests (the image forest, a
+    tabular forest, six of the 64 batched-workload forests chosen by seed 4),
+    Poisson arrivals at `rate` requests/s, rows per request log-uniform in
+    1..4096, rows sliced at random offsets from a 65,536-row pool per forest.
+    Latency is submit -> votes ready (server clock); the lag of each submit
+    behind its scheduled arrival time is reported too."""
+    import threading
+    rng = np.random.default_rng(4)
+    picks = sorted(int(i) for i in rng.choice(np.arange(64), 6, replace=False))
+    workloads = [("image", synth.image(), image_forest),
+                 ("tabular", synth.tabular(n_train=200_000, n_trees=128), None)]
+    workloads += [(f"batched_{i}", synth.batched_workload(i), None) for i in picks]
+    server = fp.fp_server_create(hbm_budget_bytes=4 << 30, max_inflight=4, max_rows_per_launch=262144)
+    forests = []
+    for name, w, f in workloads:
+        f = f if f is not None else w.forest(cache_dir=cache)
+        pool, _ = w.rows(65536, w.predict_seed + 1000)
+        p = fp.fp_pack_forest(f, bin_size=f.n_trees, interleave_depth=4)
+        fp.fp_packed_upload(p)
+        v, _ = fp.fp_predict(p, torch.from_numpy(pool).cuda())
+        torch.cuda.synchronize()
+        forests.append({"name": name, "pool": pool, "C": f.n_classes, "id": fp.fp_server_add_forest(server, p),
+                        "alone": v.cpu().numpy(), "packed": p})
+    log("serve forests: " + ", ".join(x["name"] for x in forests))
+    total = int(rate * (warm + seconds))
+    gen = np.random.default_rng(5000)
+    arrival = np.cumsum(gen.exponential(1.0 / rate, size=total))
+    fid = gen.integers(0, len(forests), size=total)
+    rows = np.clip(np.floor(np.exp(gen.uniform(0.0, np.log(4097.0), size=total))), 1, 4096).astype(np.int64)
+    offs = (gen.random(total) * (65536 - rows + 1)).astype(np.int64)
+    tickets = [0] * total
+    ready = [threading.Event() for _ in range(submit_threads)]
+    lag = np.zeros(total)
+    check_every = 97
+    kept = {}
+    submitted_upto = [0] * submit_threads
+    t0 = time.perf_counter() + 0.5
+
+    def submitter(k):
+        for i in range(k, total, submit_threads):
+            due = t0 + arrival[i]
+            while True:
+                now = time.perf_counter()
+                if now >= due:
+                    break
+                if due - now > 0.002:
+                    time.sleep(due - now - 0.001)
+            f = forests[fid[i]]
+            out = np.empty((rows[i], f["C"]), np.int32)
+            if i % check_every == 0:
+                kept[i] = out
+            tickets[i] = fp.fp_serve_submit(server, f["id"], f["pool"][offs[i]:offs[i] + rows[i]], out)
+            lag[i] = time.perf_counter() - due
+            submitted_upto[k] = i + 1
+        ready[k].set()
+
+    def poller():
+        # retire tickets in arrival order as soon as they exist, so output
+        # buffers are released promptly
+        for i in range(total):
+            while tickets[i] == 0:
+                time.sleep(50e-6)
+            fp.fp_serve_poll(server, tickets[i], -1)
+
+    th = [threading.Thread(target=submitter, args=(k,), daemon=True) for k in range(submit_threads)]
+    pt = threading.Thread(target=poller, daemon=True)
+    for t in th:
+        t.start()
+    pt.start()
+    while time.perf_counter() < t0 + warm:
+        time.sleep(0.01)
+    fp.fp_server_reset_stats(server)
+    first_measured = int(np.searchsorted(arrival, warm))
+    for r in ready:
+        r.wait()
+    end_submit = time.perf_counter()
+    st_window = fp.fp_server_stats(server)
+    pt.join()
+    st = fp.fp_server_stats(server)
+    exact = all(np.array_equal(kept[i], forests[fid[i]]["alone"][offs[i]:offs[i] + rows[i]]) for i in kept)
+    measured = total - first_measured
+    window = end_submit - (t0 + warm)
+    out = {
+        "forests": [x["name"] for x in forests],
+        "offered_req_per_s": measured / window,
+        "offered_rows_per_s": float(rows[first_measured:].sum()) / window,
+        "served_rows_per_s": st["rows"] / st["elapsed_s"],
+        "p50_ms": st["p50_ms"], "p99_ms": st["p99_ms"], "mean_ms": st["mean_ms"], "max_ms": st["max_ms"],
+        "launches": st["launches"], "mean_rows_per_launch": st["mean_rows_per_launch"],
+        "pending_at_end_of_arrivals": st_window["pending"],
+        "saturated": bool(st_window["pending"] > 0.05 * rate),
+        "submit_lag_p99_ms": float(np.percentile(lag[first_measured:], 99) * 1e3),
+        "bit_exact_checked": len(kept), "bit_exact": bool(exact),
+        "seconds": seconds, "rate": rate,
+    }
+    fp.fp_server_destroy(server)
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -102,6 +202,9 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--only", choices=["packed", "naive", "copy"], default=None)
     ap.add_argument("--cache", default=os.environ.get("FP_BENCH_CACHE", "/tmp/forestpack_cache"))
+    ap.add_argument("--no-serve", action="store_true")
+    ap.add_argument("--serve-seconds", type=float, default=10.0)
+    ap.add_argument("--serve-rate", type=float, default=20000.0)
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print(f"bench.py measures one GPU only (asked for {args.gpus}); the multi-GPU design is "
@@ -185,6 +288,12 @@ def main():
         cpu, visits_per_row = cpu_baseline(forest, X)
         log(f"cpu baseline: {cpu['value']:.0f} obs/s ({cpu['sample']})")
 
+    serve = None
+    if not args.no_serve:
+        serve = serve_leg(fp, synth, np, torch, forest, args.serve_seconds, 1.0, args.serve_rate, args.cache)
+        log(f"serve: p50 {serve['p50_ms']:.2f} ms, p99 {serve['p99_ms']:.2f} ms, "
+            f"{serve['served_rows_per_s'] / 1e6:.2f} M rows/s, saturated={serve['saturated']}")
+
     value = n / (ms_packed / 1e3)
     # compulsory HBM bytes per launch: observations in, votes and classes out, the packed forest once
     algo_bytes = n * (F * 4 + C * 4 + 4) + info["bytes"]
@@ -228,6 +337,8 @@ def main():
         out["node_visits_per_s"] = visits_per_row * value
     if cpu is not None:
         out["cpu_baseline"] = cpu
+    if serve is not None:
+        out["serve"] = serve
     print(json.dumps(out), flush=True)
 
 

@@ -331,6 +331,73 @@ int fp_plan_info_get(const fp_plan *plan, fp_plan_info *out);
 
 void fp_plan_free(fp_plan *plan);
 
+/* ------------------------------------------------------------------------ */
+/* Serving: continuous batching of prediction requests                       */
+/* ------------------------------------------------------------------------ */
+/*
+ * Classification is trained once and used repeatedly (Sec. II); a server
+ * keeps packed forests resident in HBM and answers a stream of requests of
+ * varying size.  A scheduler thread admits pending requests in arrival order
+ * while device staging memory (the HBM budget) and launch slots allow,
+ * coalesces every admitted request into one batched persistent launch (same
+ * kernel as fp_predict_batched), and overlaps up to max_inflight launches,
+ * each on its own stream with its own H2D copy of the rows and D2H copy of
+ * the votes.  Requests that arrive while launches run join the next launch
+ * (continuous batching).  Results are bit-identical to fp_predict on the
+ * same rows: a request's votes do not depend on what it was batched with.
+ *
+ * Ownership: the server borrows added forests (they must stay uploaded and
+ * alive until fp_server_destroy); fp_serve_submit copies X_host before
+ * returning; votes_host_out (int32 [n_rows][n_classes], host) must stay
+ * valid until fp_serve_poll returns FP_OK for the ticket (or the server is
+ * destroyed).  fp_serve_submit / fp_serve_poll may be called from any thread.
+ */
+typedef struct fp_server_opts {
+    int64_t hbm_budget_bytes;    /* device staging for in-flight rows + votes (0: 1 GiB) */
+    int64_t max_rows_per_launch; /* coalescing cap per launch (0: 262144) */
+    int32_t max_inflight;        /* launches in flight (0: 4) */
+    int32_t max_queue;           /* pending requests before FP_EAGAIN (0: 1 << 20) */
+    int32_t block_threads;       /* workgroup size of the launches (0: 512) */
+    int32_t cursors;             /* cursors per lane (0: 4) */
+} fp_server_opts;
+
+typedef struct fp_serve_stats {
+    int64_t submitted, completed, rejected, launches, rows;
+    int64_t pending, inflight;
+    double mean_ms, p50_ms, p99_ms, max_ms; /* submit -> result ready, completed requests */
+    double mean_rows_per_launch;
+    double elapsed_s;                       /* since creation or the last reset */
+} fp_serve_stats;
+
+typedef struct fp_server fp_server;
+
+/* Allocates the HBM staging arena, its pinned host mirror, streams and the
+ * scheduler thread.  Errors: FP_EINVAL, FP_ENOMEM, FP_EHIP. */
+int fp_server_create(const fp_server_opts *opts, fp_server **out);
+
+/* Register an uploaded packed forest (layout PACKED) on the server's device;
+ * *forest_id receives its id.  Its fp_tune (rows_per_block, tree_groups,
+ * lds_top_nodes, feature_lds) is used for its requests. */
+int fp_server_add_forest(fp_server *s, const fp_packed *forest, int32_t *forest_id);
+
+/* Queue a request: rows X_host [n_rows][ld] (host fp32, copied before return).
+ * Never blocks.  Errors: FP_EINVAL, FP_E2BIG (request larger than the whole
+ * HBM budget or than max_rows_per_launch), FP_EAGAIN (queue full). */
+int fp_serve_submit(fp_server *s, int32_t forest_id, const float *X_host, int64_t n_rows, int64_t ld,
+                    int32_t *votes_host_out, uint64_t *ticket);
+
+/* Wait up to timeout_us (0: just test, < 0: forever) for a ticket.  FP_OK:
+ * votes written, ticket retired.  FP_ENOTREADY: not yet.  FP_EINVAL: unknown
+ * ticket.  FP_EHIP: the request's launch failed. */
+int fp_serve_poll(fp_server *s, uint64_t ticket, int64_t timeout_us);
+
+int fp_server_stats(fp_server *s, fp_serve_stats *out);
+int fp_server_reset_stats(fp_server *s);
+
+/* Stops the scheduler after in-flight launches finish; pending requests are
+ * dropped.  Frees every server resource. */
+void fp_server_destroy(fp_server *s);
+
 #ifdef __cplusplus
 }
 #endif

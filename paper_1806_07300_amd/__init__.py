@@ -83,6 +83,18 @@ class fp_plan_opts(ctypes.Structure):
                 ("lds_budget", _i64)]
 
 
+class fp_server_opts(ctypes.Structure):
+    _fields_ = [("hbm_budget_bytes", _i64), ("max_rows_per_launch", _i64), ("max_inflight", _i32),
+                ("max_queue", _i32), ("block_threads", _i32), ("cursors", _i32)]
+
+
+class fp_serve_stats(ctypes.Structure):
+    _fields_ = [("submitted", _i64), ("completed", _i64), ("rejected", _i64), ("launches", _i64), ("rows", _i64),
+                ("pending", _i64), ("inflight", _i64), ("mean_ms", ctypes.c_double), ("p50_ms", ctypes.c_double),
+                ("p99_ms", ctypes.c_double), ("max_ms", ctypes.c_double),
+                ("mean_rows_per_launch", ctypes.c_double), ("elapsed_s", ctypes.c_double)]
+
+
 class fp_plan_info(ctypes.Structure):
     _fields_ = [("n_jobs", _i32), ("n_items", _i32), ("blocks", _i32), ("block_threads", _i32),
                 ("cursors", _i32), ("graph", _i32), ("lds_bytes", _i32), ("reserved", _i32),
@@ -120,6 +132,13 @@ def lib():
             "fp_predict_batched": ([_vp, _vp], ctypes.c_int),
             "fp_plan_info_get": ([_vp, ctypes.POINTER(fp_plan_info)], ctypes.c_int),
             "fp_plan_free": ([_vp], None),
+            "fp_server_create": ([ctypes.POINTER(fp_server_opts), ctypes.POINTER(_vp)], ctypes.c_int),
+            "fp_server_add_forest": ([_vp, _vp, ctypes.POINTER(_i32)], ctypes.c_int),
+            "fp_serve_submit": ([_vp, _i32, _vp, _i64, _i64, _vp, ctypes.POINTER(ctypes.c_uint64)], ctypes.c_int),
+            "fp_serve_poll": ([_vp, ctypes.c_uint64, _i64], ctypes.c_int),
+            "fp_server_stats": ([_vp, ctypes.POINTER(fp_serve_stats)], ctypes.c_int),
+            "fp_server_reset_stats": ([_vp], ctypes.c_int),
+            "fp_server_destroy": ([_vp], None),
         }
         for name, (args, res) in sig.items():
             fn = getattr(L, name)
@@ -395,3 +414,79 @@ def fp_plan_free(plan: Plan) -> None:
         lib().fp_plan_free(plan.handle)
     plan.handle = None
     plan._keep = None
+
+
+# ---------------------------------------------------------------------------
+# serving
+# ---------------------------------------------------------------------------
+class Server:
+    """Owns an ``fp_server*``; keeps forests and pending output buffers alive."""
+
+    def __init__(self, handle):
+        self.handle = _vp(handle)
+        self.forests = []
+        self.outputs = {}
+
+    def __del__(self):
+        h = getattr(self, "handle", None)
+        if h is not None and h.value and _lib is not None:
+            _lib.fp_server_destroy(h)
+            self.handle = None
+
+
+def fp_server_create(hbm_budget_bytes: int = 0, max_rows_per_launch: int = 0, max_inflight: int = 0,
+                     max_queue: int = 0, block_threads: int = 0, cursors: int = 0) -> Server:
+    opts = fp_server_opts(hbm_budget_bytes, max_rows_per_launch, max_inflight, max_queue, block_threads, cursors)
+    out = _vp()
+    _check(lib().fp_server_create(ctypes.byref(opts), ctypes.byref(out)), "fp_server_create")
+    return Server(out.value)
+
+
+def fp_server_add_forest(server: Server, p: Packed) -> int:
+    fid = _i32()
+    _check(lib().fp_server_add_forest(server.handle, p.handle, ctypes.byref(fid)), "fp_server_add_forest")
+    server.forests.append(p)
+    return fid.value
+
+
+def fp_serve_submit(server: Server, forest_id: int, X: np.ndarray, votes_out: np.ndarray) -> int:
+    """Queue rows X (host fp32 [n, >=F], row-major); votes_out (host int32 [n, C],
+    C-contiguous) is filled once fp_serve_poll reports the ticket ready."""
+    if X.dtype != np.float32 or X.ndim != 2 or (X.shape[0] > 1 and X.strides[1] != 4):
+        raise FPError(FP_EINVAL, "fp_serve_submit", "X must be a row-major float32 matrix")
+    if votes_out.dtype != np.int32 or not votes_out.flags["C_CONTIGUOUS"]:
+        raise FPError(FP_EINVAL, "fp_serve_submit", "votes_out must be a C-contiguous int32 array")
+    n = X.shape[0]
+    ld = X.strides[0] // 4 if n > 1 else X.shape[1]
+    t = ctypes.c_uint64()
+    _check(lib().fp_serve_submit(server.handle, forest_id, X.ctypes.data, n, ld, votes_out.ctypes.data,
+                                 ctypes.byref(t)), "fp_serve_submit")
+    server.outputs[t.value] = votes_out
+    return t.value
+
+
+def fp_serve_poll(server: Server, ticket: int, timeout_us: int = -1) -> bool:
+    """True once the ticket's votes are written (the ticket is then retired)."""
+    rc = lib().fp_serve_poll(server.handle, ticket, timeout_us)
+    if rc == FP_ENOTREADY:
+        return False
+    server.outputs.pop(ticket, None)
+    _check(rc, "fp_serve_poll")
+    return True
+
+
+def fp_server_stats(server: Server) -> dict:
+    st = fp_serve_stats()
+    _check(lib().fp_server_stats(server.handle, ctypes.byref(st)), "fp_server_stats")
+    return {f: getattr(st, f) for f, _ in fp_serve_stats._fields_}
+
+
+def fp_server_reset_stats(server: Server) -> None:
+    _check(lib().fp_server_reset_stats(server.handle), "fp_server_reset_stats")
+
+
+def fp_server_destroy(server: Server) -> None:
+    if server.handle is not None and server.handle.value:
+        lib().fp_server_destroy(server.handle)
+    server.handle = None
+    server.outputs.clear()

@@ -150,6 +150,12 @@ int launch_batched(const JobDesc* jobs, const WorkItem* items, int32_t n_items, 
 int launch_batched_prologue(const JobDesc* jobs_dev, int32_t n_jobs, int32_t* counter, hipStream_t s);
 int launch_batched_epilogue(const JobDesc* jobs_dev, int32_t n_jobs, hipStream_t s);
 
+// Work list of a batched launch (plan.cpp): chunks of row tiles per (job,
+// tree group), about `items_per_block` items per resident workgroup, largest
+// estimated cost first.  `expected_depth[i]` is job i's forest cost model.
+void build_items(const std::vector<JobDesc>& jobs, const std::vector<double>& expected_depth, int64_t resident,
+                 int items_per_block, std::vector<WorkItem>* items, double* total_cost);
+
 }  // namespace fp
 
 // ---------------------------------------------------------------------------

@@ -54,6 +54,40 @@ static int enqueue(fp_plan* p, hipStream_t s) {
     return fp::launch_batched_epilogue(p->jobs_dev, n_jobs, s);
 }
 
+namespace fp {
+
+void build_items(const std::vector<JobDesc>& jobs, const std::vector<double>& expected_depth, int64_t resident,
+                 int items_per_block, std::vector<WorkItem>* items, double* total_cost) {
+    const size_t n = jobs.size();
+    std::vector<double> tile_cost(n, 0.0);
+    double total = 0.0;
+    for (size_t i = 0; i < n; i++) {
+        const JobDesc& j = jobs[i];
+        const double d = std::max(1.0, expected_depth[i]);
+        tile_cost[i] = (double)j.R * j.trees_per_group * d;
+        const int64_t trees = std::min<int64_t>((int64_t)j.n_bins * j.bin_size, (int64_t)j.trees_per_group * j.G);
+        total += (double)j.n_rows * trees * d;
+    }
+    const double target = total / (double)std::max<int64_t>(1, resident * std::max(1, items_per_block));
+    items->clear();
+    for (size_t i = 0; i < n; i++) {
+        const JobDesc& j = jobs[i];
+        if (j.n_rows == 0) continue;
+        const int chunk = (int)std::max(1.0, std::min((double)j.n_tiles, std::floor(target / std::max(tile_cost[i], 1.0))));
+        for (int32_t g = 0; g < j.G; g++) {
+            if (g * j.bins_per_group >= j.n_bins) break;
+            for (int32_t t = 0; t < j.n_tiles; t += chunk)
+                items->push_back(WorkItem{(int32_t)i, g, t, std::min(j.n_tiles, t + chunk)});
+        }
+    }
+    std::stable_sort(items->begin(), items->end(), [&](const WorkItem& a, const WorkItem& b) {
+        return tile_cost[a.job] * (a.tile_end - a.tile_begin) > tile_cost[b.job] * (b.tile_end - b.tile_begin);
+    });
+    *total_cost = total;
+}
+
+}  // namespace fp
+
 #define HIPCHK(call)                                                                   \
     do {                                                                               \
         hipError_t e_ = (call);                                                        \
@@ -86,7 +120,7 @@ extern "C" int fp_plan_create(const fp_job* jobs, int32_t n_jobs, const fp_plan_
 
         // 1) job descriptors
         p->jobs.resize(n_jobs);
-        std::vector<double> tile_cost(n_jobs, 0.0);
+        std::vector<double> depth(n_jobs, 1.0);
         for (int32_t i = 0; i < n_jobs; i++) {
             const fp_job& jb = jobs[i];
             if (!jb.forest) return fp_set_error(FP_EINVAL, "job %d: forest is NULL", i);
@@ -104,9 +138,7 @@ extern "C" int fp_plan_create(const fp_job* jobs, int32_t n_jobs, const fp_plan_
                 return fp_set_error(rc, "job %d: %s", i, msg.c_str());
             }
             p->lds_bytes = std::max(p->lds_bytes, (size_t)p->jobs[i].lds_bytes);
-            const JobDesc& j = p->jobs[i];
-            tile_cost[i] = (double)j.R * j.trees_per_group * std::max(1.0, h.expected_depth);
-            p->total_cost += (double)jb.n_rows * h.n_trees * std::max(1.0, h.expected_depth);
+            depth[i] = h.expected_depth;
         }
 
         // 2) persistent grid and work items
@@ -114,20 +146,7 @@ extern "C" int fp_plan_create(const fp_job* jobs, int32_t n_jobs, const fp_plan_
         rc = fp::batched_occupancy(p->K, p->threads, p->lds_bytes, &occ);
         if (rc) return rc;
         const int64_t resident = (int64_t)dp.cus * occ;
-        const double target = p->total_cost / std::max<int64_t>(1, resident * items_per_block);
-        for (int32_t i = 0; i < n_jobs; i++) {
-            const JobDesc& j = p->jobs[i];
-            if (j.n_rows == 0) continue;
-            const int chunk = (int)std::max(1.0, std::min((double)j.n_tiles, std::floor(target / std::max(tile_cost[i], 1.0))));
-            for (int32_t g = 0; g < j.G; g++) {
-                if (g * j.bins_per_group >= j.n_bins) break;
-                for (int32_t t = 0; t < j.n_tiles; t += chunk)
-                    p->items.push_back(WorkItem{i, g, t, std::min(j.n_tiles, t + chunk)});
-            }
-        }
-        std::stable_sort(p->items.begin(), p->items.end(), [&](const WorkItem& a, const WorkItem& b) {
-            return tile_cost[a.job] * (a.tile_end - a.tile_begin) > tile_cost[b.job] * (b.tile_end - b.tile_begin);
-        });
+        fp::build_items(p->jobs, depth, resident, items_per_block, &p->items, &p->total_cost);
         p->blocks = (int)std::max<int64_t>(1, std::min<int64_t>(resident, (int64_t)p->items.size()));
 
         // 3) device tables

@@ -1,0 +1,120 @@
+"""GPU tests of the serving loop: every request's votes in the mix equal the
+same rows predicted alone (fp_predict) and the CPU checker, bit for bit,
+including under a tiny HBM budget that forces waiting admission and ring
+wrap-around; argument errors are reported without touching the GPU work."""
+import threading
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import paper_1806_07300_amd as fp
+import synth
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def forests():
+    out = []
+    specs = [synth.small(), synth.image(n_train=6000, n_trees=16), synth.tabular(n_train=20_000, n_trees=24)]
+    for i, w in enumerate(specs):
+        f = w.forest()
+        pool, _ = w.predict_rows(20_000)
+        p = fp.fp_pack_forest(f, bin_size=8, interleave_depth=3)
+        fp.fp_packed_upload(p)
+        if i == 1:
+            fp.fp_packed_set_tune(p, {"rows_per_block": 16, "tree_groups": 2})
+        v, _ = fp.fp_predict(p, torch.from_numpy(pool).cuda())
+        torch.cuda.synchronize()
+        out.append({"forest": f, "pool": pool, "packed": p, "alone": v.cpu().numpy()})
+    return out
+
+
+def make_requests(forests, n, seed, max_rows=2000):
+    rng = np.random.default_rng(seed)
+    reqs = []
+    for _ in range(n):
+        fi = int(rng.integers(0, len(forests)))
+        rows = int(np.floor(np.exp(rng.uniform(0, np.log(max_rows + 1)))))
+        rows = max(1, min(rows, max_rows))
+        off = int(rng.integers(0, len(forests[fi]["pool"]) - rows + 1))
+        reqs.append((fi, off, rows))
+    return reqs
+
+
+def run_requests(server, ids, forests, reqs, n_threads=2):
+    outs = [None] * len(reqs)
+    tickets = [None] * len(reqs)
+
+    def submitter(k):
+        for i in range(k, len(reqs), n_threads):
+            fi, off, rows = reqs[i]
+            f = forests[fi]
+            outs[i] = np.full((rows, f["forest"].n_classes), -1, np.int32)
+            tickets[i] = fp.fp_serve_submit(server, ids[fi], f["pool"][off:off + rows], outs[i])
+
+    th = [threading.Thread(target=submitter, args=(k,)) for k in range(n_threads)]
+    for t in th:
+        t.start()
+    for t in th:
+        t.join()
+    for t in tickets:
+        assert fp.fp_serve_poll(server, t, 30_000_000)
+    return outs
+
+
+@pytest.mark.parametrize("budget,inflight,max_rows", [(0, 4, 2000), (4 << 20, 2, 1000), (2 << 20, 1, 500)])
+def test_mix_equals_alone(forests, budget, inflight, max_rows):
+    server = fp.fp_server_create(hbm_budget_bytes=budget, max_inflight=inflight, max_rows_per_launch=8192)
+    ids = [fp.fp_server_add_forest(server, f["packed"]) for f in forests]
+    reqs = make_requests(forests, 400, seed=budget + inflight, max_rows=max_rows)
+    outs = run_requests(server, ids, forests, reqs)
+    for (fi, off, rows), out in zip(reqs, outs):
+        assert np.array_equal(out, forests[fi]["alone"][off:off + rows]), (fi, off, rows)
+    st = fp.fp_server_stats(server)
+    assert st["completed"] == st["submitted"] == len(reqs)
+    assert st["pending"] == 0 and st["launches"] >= 1
+    assert 0 < st["p50_ms"] <= st["p99_ms"] <= st["max_ms"]
+    # spot-check against the CPU checker
+    for fi, off, rows in reqs[:20]:
+        f = forests[fi]
+        want, _ = oracle.predict(f["forest"], f["pool"][off:off + rows])
+        assert np.array_equal(want, f["alone"][off:off + rows])
+    fp.fp_server_destroy(server)
+
+
+def test_strided_request_and_errors(forests):
+    server = fp.fp_server_create(hbm_budget_bytes=1 << 20)
+    ids = [fp.fp_server_add_forest(server, f["packed"]) for f in forests]
+    f = forests[0]
+    wide = np.full((300, 40), np.nan, np.float32)
+    wide[:, :16] = f["pool"][:300]
+    out = np.zeros((300, 2), np.int32)
+    t = fp.fp_serve_submit(server, ids[0], wide, out)
+    assert fp.fp_serve_poll(server, t, 10_000_000)
+    assert np.array_equal(out, f["alone"][:300])
+    # larger than the whole HBM budget
+    big = np.zeros((3000, 784), np.float32)
+    with pytest.raises(fp.FPError) as e:
+        fp.fp_serve_submit(server, ids[1], big, np.zeros((3000, 10), np.int32))
+    assert e.value.code == fp.FP_E2BIG
+    with pytest.raises(fp.FPError) as e:
+        fp.fp_serve_submit(server, 99, f["pool"][:5], np.zeros((5, 2), np.int32))
+    assert e.value.code == fp.FP_EINVAL
+    with pytest.raises(fp.FPError) as e:
+        fp.fp_serve_poll(server, 123456789, 0)
+    assert e.value.code == fp.FP_EINVAL
+    fp.fp_server_destroy(server)
+
+
+def test_destroy_with_requests_in_flight(forests):
+    server = fp.fp_server_create(max_inflight=2)
+    ids = [fp.fp_server_add_forest(server, f["packed"]) for f in forests]
+    keep = []
+    for i in range(50):
+        out = np.zeros((500, forests[2]["forest"].n_classes), np.int32)
+        keep.append(out)
+        fp.fp_serve_submit(server, ids[2], forests[2]["pool"][i * 100:i * 100 + 500], out)
+    fp.fp_server_destroy(server)  # waits for launches in flight, drops the rest
