@@ -398,6 +398,29 @@ int fp_server_reset_stats(fp_server *s);
  * dropped.  Frees every server resource. */
 void fp_server_destroy(fp_server *s);
 
+/*
+ * Open-loop load driver used to measure a server without client-side
+ * coordinated omission: `submit_threads` library threads submit request i at
+ * replay start + arrival_s (arrival times must be non-decreasing), and the
+ * call returns once every request is answered.  latency_ms[i] = votes ready
+ * - scheduled arrival (so time a request waited in the client counts);
+ * lag_ms[i] = actual submit - scheduled arrival.  A request that failed has
+ * latency -1 and the call returns its error.  Arrays are host memory of n
+ * entries; rows and vote buffers follow fp_serve_submit's rules.
+ */
+typedef struct fp_replay_request {
+    int32_t forest_id;
+    int32_t reserved;
+    const float *X_host;
+    int64_t n_rows;
+    int64_t ld;
+    int32_t *votes_host_out;
+    double arrival_s;
+} fp_replay_request;
+
+int fp_serve_replay(fp_server *s, const fp_replay_request *reqs, int64_t n, int32_t submit_threads,
+                    double *latency_ms, double *lag_ms);
+
 #ifdef __cplusplus
 }
 #endif

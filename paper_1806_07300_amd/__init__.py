@@ -139,6 +139,7 @@ def lib():
             "fp_server_stats": ([_vp, ctypes.POINTER(fp_serve_stats)], ctypes.c_int),
             "fp_server_reset_stats": ([_vp], ctypes.c_int),
             "fp_server_destroy": ([_vp], None),
+            "fp_serve_replay": ([_vp, _vp, _i64, _i32, _vp, _vp], ctypes.c_int),
         }
         for name, (args, res) in sig.items():
             fn = getattr(L, name)
@@ -490,3 +491,21 @@ def fp_server_destroy(server: Server) -> None:
         lib().fp_server_destroy(server.handle)
     server.handle = None
     server.outputs.clear()
+
+
+REPLAY_DTYPE = np.dtype([("forest_id", "<i4"), ("reserved", "<i4"), ("X", "<u8"), ("n_rows", "<i8"),
+                         ("ld", "<i8"), ("votes", "<u8"), ("arrival_s", "<f8")])
+
+
+def fp_serve_replay(server: Server, reqs: np.ndarray, submit_threads: int = 2):
+    """Open-loop replay of a request schedule (structured array of REPLAY_DTYPE
+    whose X / votes fields are host addresses the caller keeps alive).
+    Returns (latency_ms, lag_ms) per request: ready - scheduled arrival, and
+    actual submit - scheduled arrival."""
+    reqs = np.ascontiguousarray(reqs, dtype=REPLAY_DTYPE)
+    n = len(reqs)
+    lat = np.zeros(n, np.float64)
+    lag = np.zeros(n, np.float64)
+    _check(lib().fp_serve_replay(server.handle, reqs.ctypes.data if n else None, n, submit_threads,
+                                 lat.ctypes.data, lag.ctypes.data), "fp_serve_replay")
+    return lat, lag

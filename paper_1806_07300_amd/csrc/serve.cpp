@@ -22,6 +22,7 @@
 #include <hip/hip_runtime_api.h>
 
 #include <algorithm>
+#include <atomic>
 #include <chrono>
 #include <cmath>
 #include <condition_variable>
@@ -58,7 +59,7 @@ struct Request {
     int32_t F = 0, C = 0;
     std::vector<float> heap;    // rows kept here while the rings are full
     int32_t* out = nullptr;     // caller's votes buffer
-    Clock::time_point t_submit;
+    Clock::time_point t_submit, t_done;
     size_t x_start = 0, x_size = 0, v_start = 0, v_size = 0;
     State state = kStaging;
 };
@@ -238,6 +239,7 @@ struct fp_server {
         const auto now = Clock::now();
         for (Request* r : s.reqs) {
             if (ok) memcpy(r->out, h_v + r->v_start, (size_t)r->n_rows * r->C * sizeof(int32_t));
+            r->t_done = now;
             r->state = ok ? kDone : kFailed;
             xring.release(r->x_start);
             vring.release(r->v_start);
@@ -529,4 +531,67 @@ extern "C" void fp_server_destroy(fp_server* s) {
     s->cv_work.notify_all();
     if (s->sched.joinable()) s->sched.join();
     delete s;  // requests never launched are dropped with their tickets
+}
+
+// ---------------------------------------------------------------------------
+// open-loop load driver
+// ---------------------------------------------------------------------------
+extern "C" int fp_serve_replay(fp_server* s, const fp_replay_request* reqs, int64_t n, int32_t submit_threads,
+                               double* latency_ms, double* lag_ms) {
+    fp_clear_error();
+    if (!s || (n > 0 && (!reqs || !latency_ms || !lag_ms))) return fp_set_error(FP_EINVAL, "NULL argument");
+    if (n <= 0) return FP_OK;
+    const int T = std::max(1, std::min<int32_t>(submit_threads, 64));
+    std::vector<uint64_t> tickets((size_t)n, 0);
+    std::vector<int> rcs((size_t)n, FP_OK);
+    std::vector<std::atomic<int>> posted((size_t)n);
+    for (auto& p : posted) p.store(0);
+    const Clock::time_point start = Clock::now() + std::chrono::milliseconds(2);
+    auto due = [&](int64_t i) {
+        return start + std::chrono::duration_cast<Clock::duration>(std::chrono::duration<double>(reqs[i].arrival_s));
+    };
+    std::vector<std::thread> th;
+    try {
+        for (int k = 0; k < T; k++)
+            th.emplace_back([&, k] {
+                for (int64_t i = k; i < n; i += T) {
+                    const auto d = due(i);
+                    auto now = Clock::now();
+                    if (d - now > std::chrono::microseconds(200)) std::this_thread::sleep_until(d - std::chrono::microseconds(100));
+                    while (Clock::now() < d) {
+                    }
+                    const fp_replay_request& q = reqs[i];
+                    rcs[i] = fp_serve_submit(s, q.forest_id, q.X_host, q.n_rows, q.ld, q.votes_host_out, &tickets[i]);
+                    lag_ms[i] = std::chrono::duration<double, std::milli>(Clock::now() - d).count();
+                    posted[i].store(1, std::memory_order_release);
+                }
+            });
+    } catch (const std::system_error&) {
+        for (auto& t : th) t.join();
+        return fp_set_error(FP_ENOMEM, "cannot start submit threads");
+    }
+    int first_error = FP_OK;
+    for (int64_t i = 0; i < n; i++) {
+        while (!posted[i].load(std::memory_order_acquire)) std::this_thread::yield();
+        if (rcs[i] != FP_OK) {
+            latency_ms[i] = -1.0;
+            if (!first_error) first_error = rcs[i];
+            continue;
+        }
+        std::unique_lock<std::mutex> lk(s->mu);
+        auto it = s->tickets.find(tickets[i]);
+        if (it == s->tickets.end()) {
+            latency_ms[i] = -1.0;
+            continue;
+        }
+        Request* r = it->second;
+        s->cv_done.wait(lk, [&] { return r->state == kDone || r->state == kFailed; });
+        latency_ms[i] = r->state == kDone ? std::chrono::duration<double, std::milli>(r->t_done - due(i)).count() : -1.0;
+        if (r->state == kFailed && !first_error) first_error = FP_EHIP;
+        s->tickets.erase(it);
+        delete r;
+    }
+    for (auto& t : th) t.join();
+    if (first_error) return fp_set_error(first_error, "replay: some requests failed (latency -1)");
+    return FP_OK;
 }

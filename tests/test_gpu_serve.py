@@ -118,3 +118,23 @@ def test_destroy_with_requests_in_flight(forests):
         keep.append(out)
         fp.fp_serve_submit(server, ids[2], forests[2]["pool"][i * 100:i * 100 + 500], out)
     fp.fp_server_destroy(server)  # waits for launches in flight, drops the rest
+
+
+def test_replay_open_loop(forests):
+    server = fp.fp_server_create(max_inflight=3)
+    ids = [fp.fp_server_add_forest(server, f["packed"]) for f in forests]
+    reqs = make_requests(forests, 600, seed=9, max_rows=1500)
+    sched = np.zeros(len(reqs), fp.REPLAY_DTYPE)
+    outs = []
+    for i, (fi, off, rows) in enumerate(reqs):
+        f = forests[fi]
+        out = np.full((rows, f["forest"].n_classes), -1, np.int32)
+        outs.append(out)
+        sched[i] = (ids[fi], 0, f["pool"].ctypes.data + off * f["pool"].shape[1] * 4, rows, f["pool"].shape[1],
+                    out.ctypes.data, i * 200e-6)
+    lat, lag = fp.fp_serve_replay(server, sched, submit_threads=2)
+    assert (lat > 0).all() and (lag >= 0).all()
+    for (fi, off, rows), out in zip(reqs, outs):
+        assert np.array_equal(out, forests[fi]["alone"][off:off + rows])
+    assert fp.fp_server_stats(server)["completed"] == len(reqs)
+    fp.fp_server_destroy(server)
