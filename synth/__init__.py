@@ -46,6 +46,7 @@ class _Params(ctypes.Structure):
                 ("n_classes", ctypes.c_int32), ("mtry", ctypes.c_int32),
                 ("max_depth", ctypes.c_int32), ("min_samples_split", ctypes.c_int32),
                 ("bootstrap", ctypes.c_int32), ("n_threads", ctypes.c_int32),
+                ("tree_offset", ctypes.c_int32), ("reserved", ctypes.c_int32),
                 ("seed", ctypes.c_uint64)]
 
 
@@ -127,14 +128,29 @@ class Forest:
 
 def train_forest(X: np.ndarray, y: np.ndarray, *, n_trees: int, n_classes: int, mtry: int,
                  max_depth: int = -1, bootstrap: bool = True, seed: int = 0,
-                 min_samples_split: int = 2, n_threads: int = 0) -> Forest:
-    """Train a seeded CART random forest (see the header of cart.c)."""
+                 min_samples_split: int = 2, n_threads: int = 0, tree_offset: int = 0,
+                 progress=None) -> Forest:
+    """Train a seeded CART random forest (see the header of cart.c).
+
+    Tree t depends only on (seed, tree_offset + t), so a forest can be trained
+    in chunks; with ``progress`` set, trees are trained in chunks of that many
+    and ``progress(done, total)`` is called after each chunk."""
+    chunk = max(1, int(getattr(progress, "chunk", 64))) if progress is not None else n_trees
+    if chunk < n_trees:
+        parts = []
+        for t0 in range(0, n_trees, chunk):
+            k = min(chunk, n_trees - t0)
+            parts.append(train_forest(X, y, n_trees=k, n_classes=n_classes, mtry=mtry, max_depth=max_depth,
+                                      bootstrap=bootstrap, seed=seed, min_samples_split=min_samples_split,
+                                      n_threads=n_threads, tree_offset=tree_offset + t0))
+            progress(t0 + k, n_trees)
+        return concat_forests(parts)
     lib = _load()
     X = np.ascontiguousarray(X, dtype=np.float32)
     y = np.ascontiguousarray(y, dtype=np.int32)
     n, F = X.shape
     p = _Params(n_trees, F, n_classes, mtry, max_depth, min_samples_split, int(bool(bootstrap)),
-                n_threads, seed & 0xFFFFFFFFFFFFFFFF)
+                n_threads, tree_offset, 0, seed & 0xFFFFFFFFFFFFFFFF)
     h = ctypes.c_void_p()
     rc = lib.cart_train(X.ctypes.data, n, F, y.ctypes.data, ctypes.byref(p), ctypes.byref(h))
     if rc != 0:
@@ -152,6 +168,17 @@ def train_forest(X: np.ndarray, y: np.ndarray, *, n_trees: int, n_classes: int, 
     finally:
         lib.cart_free(h)
     return Forest(n_trees, F, n_classes, off, **arrs)
+
+
+def concat_forests(parts) -> Forest:
+    """Forest made of the trees of several forests, in order."""
+    sizes = np.concatenate([np.diff(f.tree_node_offset) for f in parts])
+    off = np.zeros(len(sizes) + 1, np.int64)
+    off[1:] = np.cumsum(sizes)
+    f0 = parts[0]
+    return Forest(int(len(sizes)), f0.n_features, f0.n_classes, off,
+                  *(np.concatenate([getattr(f, k) for f in parts]) for k in
+                    ("feature", "threshold", "left", "right", "leaf_class", "cardinality", "depth")))
 
 
 # --------------------------------------------------------------------------
@@ -324,7 +351,7 @@ class Workload:
     def predict_rows(self, n: int | None = None, start: int = 0):
         return self.rows(self.n_predict if n is None else n, self.predict_seed, start)
 
-    def forest(self, cache_dir: str | None = None, n_threads: int = 0) -> Forest:
+    def forest(self, cache_dir: str | None = None, n_threads: int = 0, progress=None) -> Forest:
         path = None
         if cache_dir:
             os.makedirs(cache_dir, exist_ok=True)
@@ -334,7 +361,7 @@ class Workload:
         X, y = self.train_rows()
         f = train_forest(X, y, n_trees=self.n_trees, n_classes=self.n_classes, mtry=self.mtry,
                          max_depth=self.max_depth, bootstrap=True, seed=self.forest_seed,
-                         n_threads=n_threads)
+                         n_threads=n_threads, progress=progress)
         if path:
             f.save(path)
         return f

@@ -47,6 +47,8 @@ typedef struct {
     int32_t min_samples_split; /* nodes with fewer in-bag samples become leaves (>=2) */
     int32_t bootstrap;         /* 1: n draws with replacement; 0: every row once */
     int32_t n_threads;         /* 0: OpenMP default */
+    int32_t tree_offset;       /* index of the first tree: trees [off, off+n_trees) of the seeded forest */
+    int32_t reserved;
     uint64_t seed;
 } cart_params;
 
@@ -298,7 +300,7 @@ int cart_train(const float *X, int64_t n, int64_t ld, const int32_t *y, const ca
 #pragma omp parallel for schedule(dynamic, 1) num_threads(nt) reduction(| : failed)
 #endif
     for (int32_t t = 0; t < p->n_trees; t++)
-        if (train_tree(Xt, n, y, p, t, &fo->trees[t])) failed = 1;
+        if (train_tree(Xt, n, y, p, (int64_t)p->tree_offset + t, &fo->trees[t])) failed = 1;
     free(Xt);
     if (failed) { cart_free(fo); return -1; }
     *out = fo;

@@ -204,3 +204,21 @@ def test_batched_specs():
     for b in s:
         assert 16 <= b.n_trees <= 2048 and 4 <= b.n_features <= 784
         assert 2 <= b.n_classes <= 10 and 1 <= b.n_rows <= 200_000
+
+
+def test_chunked_training_is_identical():
+    w = synth.small()
+    X, y = w.train_rows()
+    a = synth.train_forest(X, y, n_trees=10, n_classes=2, mtry=4, max_depth=12, seed=3)
+    seen = []
+
+    class Progress:
+        chunk = 3
+
+        def __call__(self, done, total):
+            seen.append((done, total))
+
+    b = synth.train_forest(X, y, n_trees=10, n_classes=2, mtry=4, max_depth=12, seed=3, progress=Progress())
+    assert seen == [(3, 10), (6, 10), (9, 10), (10, 10)]
+    for k in ("tree_node_offset", "feature", "threshold", "left", "right", "leaf_class", "cardinality"):
+        assert np.array_equal(getattr(a, k), getattr(b, k)), k
