@@ -109,7 +109,14 @@ enum {
      * per-tree statistical depth-first order with the more frequently taken
      * child adjacent to its parent (Stat), trees grouped into bins whose top
      * levels are interleaved level by level across the bin's trees (Bin). */
-    FP_LAYOUT_PACKED = 1
+    FP_LAYOUT_PACKED = 1,
+    /* PACKED with 8-byte nodes below the interleaved levels: the Stat hot
+     * child is implicitly the next node, so a 16-byte load fetches a node and
+     * its most likely successor (the prefetch of the adjacent line that the
+     * paper's EU estimate credits, Sec. III-A).  Needs the feature index, the
+     * classes and in-tree distances to fit 32 bits (FP_E2BIG otherwise);
+     * line_align is ignored. */
+    FP_LAYOUT_COMPACT = 2
 };
 
 /*
@@ -261,7 +268,7 @@ typedef struct fp_autotune_opts {
 } fp_autotune_opts;
 
 typedef struct fp_autotune_result {
-    fp_pack_opts pack;      /* best bin size / interleave depth (layout PACKED) */
+    fp_pack_opts pack;      /* best layout (PACKED or COMPACT), bin size, interleave depth */
     fp_tune tune;           /* best launch parameters */
     double best_ms;         /* time of one launch over the sample, best candidate */
     double default_ms;      /* same, library defaults (B = T, D = 4) */

@@ -19,7 +19,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libforestpack.so")
 
 FP_OK, FP_EINVAL, FP_ENOMEM, FP_EHIP, FP_ECORRUPT, FP_E2BIG, FP_EAGAIN, FP_ENOTREADY, FP_ENODEV = range(9)
-FP_LAYOUT_NAIVE, FP_LAYOUT_PACKED = 0, 1
+FP_LAYOUT_NAIVE, FP_LAYOUT_PACKED, FP_LAYOUT_COMPACT = 0, 1, 2
 ERROR_NAMES = {0: "FP_OK", 1: "FP_EINVAL", 2: "FP_ENOMEM", 3: "FP_EHIP", 4: "FP_ECORRUPT",
                5: "FP_E2BIG", 6: "FP_EAGAIN", 7: "FP_ENOTREADY", 8: "FP_ENODEV"}
 
@@ -360,8 +360,8 @@ def fp_autotune(forest, X, block_threads: int = 0, cursors: int = 0, reps: int =
     _check(lib().fp_autotune(ctypes.byref(view), _vp(X.data_ptr()), n, ld, ctypes.byref(opts), ctypes.byref(res),
                              _stream_ptr(stream)), "fp_autotune")
     del keep
-    return {"pack": {"bin_size": res.pack.bin_size, "interleave_depth": res.pack.interleave_depth,
-                     "line_align": res.pack.line_align},
+    return {"pack": {"layout": res.pack.layout, "bin_size": res.pack.bin_size,
+                     "interleave_depth": res.pack.interleave_depth, "line_align": res.pack.line_align},
             "tune": {k: getattr(res.tune, k) for k in TUNE_FIELDS},
             "best_ms": res.best_ms, "default_ms": res.default_ms, "n_tried": res.n_tried,
             "cache_hit": bool(res.cache_hit)}

@@ -5,7 +5,8 @@
 // a sample of the caller's rows:
 //   1. launch mapping (workgroup size, cursors, observations per workgroup)
 //      on the default packing (one bin of all trees, interleave depth 4);
-//   2. packing: interleave depth 0..7 and bin sizes T, 64, 16 with that mapping;
+//   2. packing: layout (16-byte nodes or compact 8-byte deep nodes), interleave
+//      depth 0..7 and bin sizes T, 64, 16 with that mapping;
 //   3. launch mapping again on the best packing, plus tree groups (several
 //      workgroups per observation tile, one per group of bins).
 // Votes never depend on the candidate; only time does.
@@ -117,13 +118,13 @@ extern "C" int fp_autotune(const fp_forest_view* forest, const float* X, int64_t
         } evg{e0, e1};
 
         // pack + upload with memoisation over (bin size, depth)
-        std::map<std::pair<int, int>, std::unique_ptr<PackedPtr>> packs;
+        std::map<std::tuple<int, int, int>, std::unique_ptr<PackedPtr>> packs;
         PackedPtr* current = nullptr;
-        auto use_pack = [&](int B, int D) -> int {
-            auto k = std::make_pair(B, D);
+        auto use_pack = [&](int layout, int B, int D) -> int {
+            auto k = std::make_tuple(layout, B, D);
             if (!packs.count(k)) {
                 std::unique_ptr<PackedPtr> pp(new PackedPtr());
-                fp_pack_opts po{FP_LAYOUT_PACKED, B, D, 0};
+                fp_pack_opts po{layout, B, D, 0};
                 int r = fp_pack_forest(forest, &po, &pp->p);
                 if (r) return r;
                 packs[k] = std::move(pp);
@@ -153,7 +154,7 @@ extern "C" int fp_autotune(const fp_forest_view* forest, const float* X, int64_t
         };
 
         const int T = forest->n_trees;
-        rc = use_pack(T, 4);
+        rc = use_pack(FP_LAYOUT_PACKED, T, 4);
         if (rc) return rc;
         max_depth = current->p->hdr.max_depth;
         // library defaults, for reference
@@ -165,7 +166,7 @@ extern "C" int fp_autotune(const fp_forest_view* forest, const float* X, int64_t
         std::vector<int> k_set = fixed_K > 0 ? std::vector<int>{fixed_K} : std::vector<int>{2, 4};
         double best = 1e30;
         fp_tune best_t{};
-        int best_B = T, best_D = 4;
+        int best_B = T, best_D = 4, best_L = FP_LAYOUT_PACKED;
         auto try_tune = [&](const fp_tune& t) -> int {
             double ms = 0;
             int r = time_one(t, &ms);
@@ -189,25 +190,28 @@ extern "C" int fp_autotune(const fp_forest_view* forest, const float* X, int64_t
                     rc = try_tune(t);
                     if (rc) return rc;
                 }
-        // pass 2: packing
-        std::set<std::pair<int, int>> tried{{T, 4}};
-        for (int B : {T, 64, 16}) {
-            if (B > T) continue;
-            for (int D = 0; D <= std::min(7, max_depth); D++) {
-                if (!tried.insert({B, D}).second) continue;
-                rc = use_pack(B, D);
-                if (rc) return rc;
-                const double before = best;
-                rc = try_tune(best_t);
-                if (rc) return rc;
-                if (best < before) {
-                    best_B = B;
-                    best_D = D;
+        // pass 2: packing (layout, bin size, interleave depth)
+        std::set<std::tuple<int, int, int>> tried{{FP_LAYOUT_PACKED, T, 4}};
+        for (int L : {FP_LAYOUT_PACKED, FP_LAYOUT_COMPACT})
+            for (int B : {T, 64, 16}) {
+                if (B > T) continue;
+                for (int D = 0; D <= std::min(7, max_depth); D++) {
+                    if (!tried.insert(std::make_tuple(L, B, D)).second) continue;
+                    rc = use_pack(L, B, D);
+                    if (rc == FP_E2BIG) continue;  // the compact encoding does not fit this forest
+                    if (rc) return rc;
+                    const double before = best;
+                    rc = try_tune(best_t);
+                    if (rc) return rc;
+                    if (best < before) {
+                        best_L = L;
+                        best_B = B;
+                        best_D = D;
+                    }
                 }
             }
-        }
         // pass 3: launch mapping again on the best packing, with tree groups
-        rc = use_pack(best_B, best_D);
+        rc = use_pack(best_L, best_B, best_D);
         if (rc) return rc;
         const fp_tune base = best_t;
         const int n_bins = current->p->hdr.n_bins;
@@ -220,7 +224,7 @@ extern "C" int fp_autotune(const fp_forest_view* forest, const float* X, int64_t
                 rc = try_tune(t);
                 if (rc) return rc;
             }
-        out->pack = fp_pack_opts{FP_LAYOUT_PACKED, best_B, best_D, 0};
+        out->pack = fp_pack_opts{best_L, best_B, best_D, 0};
         out->tune = best_t;
         out->best_ms = best;
         if (hipStreamSynchronize(stream) != hipSuccess) return fp_set_error(FP_EHIP, "hipStreamSynchronize failed");

@@ -43,6 +43,25 @@ struct alignas(16) Node16 {
 };
 static_assert(sizeof(Node16) == 16, "node is 16 bytes");
 
+// COMPACT layout: the node section is an array of 8-byte words.  A bin's
+// top region holds Node16 entries (two words each); its deep region holds
+// Node8 entries in Stat pre-order.  References (roots, Node16 children) live
+// in one space per bin: r < top_len is top node r, r >= top_len is deep node
+// r - top_len, r < 0 is class -r-1.  A Node8 at deep index i (reference
+// p = top_len + i) packs in `w`:
+//   bits [0, fb)        compacted feature
+//   bit fb      ADJ     the child at p + 1 is internal (the hot child of Stat)
+//   bit fb + 1  ADJ_L   that adjacent child is the left one
+//   bit fb + 2  COLD_C  the other child is a class (else an internal node)
+//   bits [fb+3, 32)     payload: ADJ & COLD_C: its class; ADJ & !COLD_C: its
+//                       reference minus p (>= 2); !ADJ (both children are
+//                       leaves): left class | right class << cb
+struct Node8 {
+    float thr;
+    uint32_t w;
+};
+static_assert(sizeof(Node8) == 8, "compact node is 8 bytes");
+
 struct BinEntry {
     int64_t node_base;   // first node of the bin in the node array
     int32_t first_tree;
@@ -71,7 +90,9 @@ struct Header {
     int32_t n_used_features, pad0;
     int64_t fmap_offset;    // feature map (packed), 0 for naive
     double expected_depth;  // mean over trees of the cardinality-weighted leaf depth
-    uint8_t pad[256 - 144];
+    int32_t compact_fbits;  // COMPACT: feature bits fb
+    int32_t compact_cbits;  // COMPACT: class bits cb of a two-leaf payload
+    uint8_t pad[256 - 152];
 };
 static_assert(sizeof(Header) == 256, "header is 256 bytes");
 
@@ -109,7 +130,9 @@ struct JobDesc {
     int32_t atomic_votes;      // several tree groups add into the same votes
     int32_t feat_lds;          // 1: observation tile in LDS, 0: read from memory
     int32_t off_top, off_ttab, off_fmap, off_xs, off_votes, off_pool, lds_bytes;
-    int32_t pad;
+    int32_t layout;            // FP_LAYOUT_PACKED or FP_LAYOUT_COMPACT
+    int32_t fbits, cbits;      // COMPACT field widths
+    int32_t pad2;
 };
 
 // One entry of the batched work list: tiles [tile_begin, tile_end) of job
@@ -138,7 +161,7 @@ int resolve_job(const fp_packed* p, const fp_tune* t, const float* X, int64_t n_
 // Default LDS footprint of one workgroup: what keeps two workgroups per CU.
 size_t default_lds_block(const DeviceProps& dp);
 
-int packed_occupancy(int K, int fmode, int threads, size_t lds, int* blocks_per_cu);
+int packed_occupancy(int K, int fmode, bool compact, int threads, size_t lds, int* blocks_per_cu);
 int batched_occupancy(int K, int threads, size_t lds, int* blocks_per_cu);
 
 int launch_fill(int32_t* p, int64_t n, int32_t v, hipStream_t s);

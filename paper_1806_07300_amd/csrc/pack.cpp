@@ -34,6 +34,7 @@
 using fp::BinEntry;
 using fp::Header;
 using fp::Node16;
+using fp::Node8;
 
 // ---------------------------------------------------------------------------
 // errors
@@ -258,14 +259,21 @@ int pack_naive(const fp_forest_view* v, const std::vector<TreeShape>& s, std::ve
     return FP_OK;
 }
 
+int bits_for(int64_t n_values) {  // bits to write 0 .. n_values-1 (at least 1)
+    int b = 1;
+    while ((int64_t)1 << b < n_values) b++;
+    return b;
+}
+
 int pack_packed(const fp_forest_view* v, const std::vector<TreeShape>& s, const fp_pack_opts* o,
                 std::vector<uint8_t>* out, Header* h) {
     const int32_t T = v->n_trees;
     const int32_t B = (o->bin_size <= 0 || o->bin_size > T) ? T : o->bin_size;
     const int32_t D = o->interleave_depth;
-    const bool align_lines = o->line_align != 0;
+    const bool compact = o->layout == FP_LAYOUT_COMPACT;
+    const bool align_lines = o->line_align != 0 && !compact;
     const int32_t n_bins = (T + B - 1) / B;
-    fill_header_common(h, v, s, FP_LAYOUT_PACKED);
+    fill_header_common(h, v, s, compact ? FP_LAYOUT_COMPACT : FP_LAYOUT_PACKED);
 
     // 1) positions of every internal node, bin by bin
     std::vector<std::vector<int32_t>> pos(T);
@@ -278,7 +286,8 @@ int pack_packed(const fp_forest_view* v, const std::vector<TreeShape>& s, const 
         be.first_tree = b * B;
         be.n_trees = std::min(B, T - b * B);
         be.root_base = be.first_tree;
-        node_cursor = (int64_t)align_up((size_t)node_cursor, 8);  // bins start on a 128 B line
+        // bins start on a 128 B line (8 Node16 units, or 16 words of 8 bytes)
+        node_cursor = (int64_t)align_up((size_t)node_cursor, compact ? 16 : 8);
         be.node_base = node_cursor;
         int64_t next = 0;
         for (int32_t j = 0; j < be.n_trees; j++) pos[be.first_tree + j].assign(s[be.first_tree + j].size, -1);
@@ -333,9 +342,9 @@ int pack_packed(const fp_forest_view* v, const std::vector<TreeShape>& s, const 
             return fp_set_error(FP_E2BIG, "bin %d holds %lld nodes (limit %d)", b, (long long)next,
                                 INT32_MAX);
         be.deep_len = (int32_t)(next - be.top_len);
-        node_cursor += next;
+        node_cursor += compact ? 2 * (int64_t)be.top_len + be.deep_len : next;
     }
-    const int64_t n_nodes = node_cursor;
+    const int64_t n_nodes = node_cursor;  // Node16 units, or 8-byte words (COMPACT)
 
     // 2) compacted feature numbering: the columns some split tests, in increasing order
     std::vector<int32_t> remap(v->n_features, -1), fmap;
@@ -354,7 +363,19 @@ int pack_packed(const fp_forest_view* v, const std::vector<TreeShape>& s, const 
     const size_t roots_off = align_up(table_off + sizeof(BinEntry) * (size_t)n_bins, kSectionAlign);
     const size_t fmap_off = align_up(roots_off + sizeof(int32_t) * (size_t)T, kSectionAlign);
     const size_t nodes_off = align_up(fmap_off + sizeof(int32_t) * fmap.size(), kSectionAlign);
-    const size_t total = align_up(nodes_off + sizeof(Node16) * (size_t)n_nodes, kSectionAlign);
+    // COMPACT keeps 16 bytes of slack after the last word: a kernel reads every
+    // deep node together with its successor in one 16-byte load
+    const size_t node_bytes = compact ? 8 * (size_t)n_nodes + 16 : sizeof(Node16) * (size_t)n_nodes;
+    const size_t total = align_up(nodes_off + node_bytes, kSectionAlign);
+    int fb = 0, cb = 0;
+    if (compact) {
+        fb = bits_for((int64_t)fmap.size());
+        cb = bits_for(v->n_classes);
+        const int pb = 29 - fb;
+        if (pb < 2 * cb || pb < bits_for(v->n_classes))
+            return fp_set_error(FP_E2BIG, "compact layout: %d feature bits and %d classes do not fit a 32-bit node word",
+                                fb, v->n_classes);
+    }
     try {
         out->assign(total, 0);
     } catch (const std::bad_alloc&) {
@@ -364,9 +385,12 @@ int pack_packed(const fp_forest_view* v, const std::vector<TreeShape>& s, const 
     memcpy(out->data() + fmap_off, fmap.data(), sizeof(int32_t) * fmap.size());
     int32_t* roots = reinterpret_cast<int32_t*>(out->data() + roots_off);
     Node16* nodes = reinterpret_cast<Node16*>(out->data() + nodes_off);
+    Node8* words = reinterpret_cast<Node8*>(out->data() + nodes_off);
+    const int pb = 29 - fb;
     for (int32_t b = 0; b < n_bins; b++) {
         const BinEntry& be = bins[b];
-        Node16* bn = nodes + be.node_base;
+        Node16* bn = compact ? reinterpret_cast<Node16*>(words + be.node_base) : nodes + be.node_base;
+        Node8* deep = words + be.node_base + 2 * (int64_t)be.top_len;
         for (int32_t j = 0; j < be.n_trees; j++) {
             const int32_t ti = be.first_tree + j;
             const TreeShape& t = s[ti];
@@ -379,11 +403,42 @@ int pack_packed(const fp_forest_view* v, const std::vector<TreeShape>& s, const 
             for (int32_t n : t.bfs) {
                 if (!is_internal(v, t, n)) continue;
                 const int64_t g = t.base + n;
-                Node16& nd = bn[p[n]];
-                nd.thr = v->threshold[g];
-                nd.feat = remap[v->feature[g]];
-                nd.left = ref(v->left[g]);
-                nd.right = ref(v->right[g]);
+                const int32_t self = p[n];
+                if (!compact || self < be.top_len) {
+                    Node16& nd = bn[self];
+                    nd.thr = v->threshold[g];
+                    nd.feat = remap[v->feature[g]];
+                    nd.left = ref(v->left[g]);
+                    nd.right = ref(v->right[g]);
+                    continue;
+                }
+                // compact deep node: the internal child Stat placed at self + 1
+                const int32_t l = v->left[g], r = v->right[g];
+                const bool li = is_internal(v, t, l), ri = is_internal(v, t, r);
+                uint32_t w = (uint32_t)remap[v->feature[g]];
+                uint32_t payload;
+                if (li || ri) {
+                    const int32_t adj = (li && p[l] == self + 1) ? l : r;
+                    const int32_t other = adj == l ? r : l;
+                    if (!is_internal(v, t, adj) || p[adj] != self + 1)
+                        return fp_set_error(FP_ECORRUPT, "internal error: hot child not adjacent in tree %d", ti);
+                    w |= 1u << fb;
+                    if (adj == l) w |= 1u << (fb + 1);
+                    if (is_internal(v, t, other)) {
+                        const int64_t delta = (int64_t)p[other] - self;
+                        if (delta < 2 || delta >= ((int64_t)1 << pb))
+                            return fp_set_error(FP_E2BIG, "compact layout: subtree distance %lld needs more than %d bits",
+                                                (long long)delta, pb);
+                        payload = (uint32_t)delta;
+                    } else {
+                        w |= 1u << (fb + 2);
+                        payload = (uint32_t)v->leaf_class[t.base + other];
+                    }
+                } else {
+                    payload = (uint32_t)v->leaf_class[t.base + l] | ((uint32_t)v->leaf_class[t.base + r] << cb);
+                }
+                w |= payload << (fb + 3);
+                deep[self - be.top_len] = Node8{v->threshold[g], w};
             }
         }
     }
@@ -395,6 +450,8 @@ int pack_packed(const fp_forest_view* v, const std::vector<TreeShape>& s, const 
     h->line_align = align_lines ? 1 : 0;
     h->n_used_features = (int32_t)fmap.size();
     h->fmap_offset = (int64_t)fmap_off;
+    h->compact_fbits = fb;
+    h->compact_cbits = cb;
     h->table_offset = (int64_t)table_off;
     h->roots_offset = (int64_t)roots_off;
     h->nodes_offset = (int64_t)nodes_off;
@@ -421,8 +478,9 @@ int verify_buffer(const uint8_t* bytes, size_t n, std::string* why) {
         return bad("bad forest dimensions");
     if (fnv1a64(bytes + sizeof(Header), n - sizeof(Header)) != h.checksum) return bad("checksum mismatch");
     const int64_t N = h.n_nodes;
+    const int64_t unit = h.layout == FP_LAYOUT_COMPACT ? 8 : (int64_t)sizeof(Node16);
     if (N < 0 || h.nodes_offset < (int64_t)sizeof(Header) || h.nodes_offset % 256 ||
-        h.nodes_offset + N * (int64_t)sizeof(Node16) > (int64_t)n)
+        h.nodes_offset + N * unit > (int64_t)n)
         return bad("node section out of bounds");
     const Node16* nodes = reinterpret_cast<const Node16*>(bytes + h.nodes_offset);
     const int32_t C = h.n_classes;
@@ -449,7 +507,11 @@ int verify_buffer(const uint8_t* bytes, size_t n, std::string* why) {
         }
         return FP_OK;
     }
-    if (h.layout != FP_LAYOUT_PACKED) return bad("unknown layout %d", h.layout);
+    if (h.layout != FP_LAYOUT_PACKED && h.layout != FP_LAYOUT_COMPACT) return bad("unknown layout %d", h.layout);
+    const bool compact = h.layout == FP_LAYOUT_COMPACT;
+    if (compact && (h.nodes_offset + 8 * N + 16 > (int64_t)n || h.compact_fbits < 1 || h.compact_fbits > 26 ||
+                    h.compact_cbits < 1 || 2 * h.compact_cbits > 29 - h.compact_fbits))
+        return bad("compact node section or field widths");
     if (h.n_bins < 1 || h.table_offset + (int64_t)sizeof(BinEntry) * h.n_bins > h.roots_offset ||
         h.roots_offset + (int64_t)sizeof(int32_t) * h.n_trees > h.fmap_offset ||
         h.n_used_features < 1 || h.n_used_features > h.n_features ||
@@ -469,8 +531,9 @@ int verify_buffer(const uint8_t* bytes, size_t n, std::string* why) {
         if (be.first_tree != tree_cursor || be.n_trees < 1 || be.root_base != be.first_tree)
             return bad("bin %d tree range", b);
         tree_cursor += be.n_trees;
-        if (be.top_len < 0 || be.deep_len < 0 || be.node_base < 0 || be.node_base % 8 ||
-            be.node_base + (int64_t)be.top_len + be.deep_len > N)
+        const int64_t units = compact ? 2 * (int64_t)be.top_len + be.deep_len : (int64_t)be.top_len + be.deep_len;
+        if (be.top_len < 0 || be.deep_len < 0 || be.node_base < 0 || be.node_base % (compact ? 16 : 8) ||
+            be.node_base + units > N)
             return bad("bin %d node range", b);
         const int64_t len = (int64_t)be.top_len + be.deep_len;
         max_top = std::max(max_top, be.top_len);
@@ -478,6 +541,34 @@ int verify_buffer(const uint8_t* bytes, size_t n, std::string* why) {
         auto ref_ok = [&](int32_t r, int64_t self) { return r < 0 ? (-(int64_t)r - 1) < C : (r > self && r < len); };
         for (int32_t j = 0; j < be.n_trees; j++)
             if (!ref_ok(roots[be.first_tree + j], -1)) return bad("bin %d root %d", b, j);
+        if (compact) {
+            const Node8* words = reinterpret_cast<const Node8*>(bytes + h.nodes_offset) + be.node_base;
+            const Node16* top = reinterpret_cast<const Node16*>(words);
+            for (int64_t i = 0; i < be.top_len; i++) {
+                const Node16& nd = top[i];
+                if (nd.feat < 0 || nd.feat >= F || !ref_ok(nd.left, i) || !ref_ok(nd.right, i))
+                    return bad("bin %d top node %lld", b, (long long)i);
+            }
+            const int fb = h.compact_fbits, cb = h.compact_cbits;
+            const Node8* deep = words + 2 * (int64_t)be.top_len;
+            for (int64_t i = 0; i < be.deep_len; i++) {
+                const uint32_t w = deep[i].w;
+                const int64_t self = be.top_len + i;
+                const uint32_t pay = w >> (fb + 3);
+                if ((int64_t)(w & ((1u << fb) - 1)) >= F) return bad("bin %d deep node %lld feature", b, (long long)i);
+                if ((w >> fb) & 1) {
+                    if (self + 1 >= len) return bad("bin %d deep node %lld: adjacent child past the bin", b, (long long)i);
+                    if ((w >> (fb + 2)) & 1) {
+                        if ((int64_t)pay >= C) return bad("bin %d deep node %lld class", b, (long long)i);
+                    } else if (pay < 2 || self + (int64_t)pay >= len) {
+                        return bad("bin %d deep node %lld distance", b, (long long)i);
+                    }
+                } else if ((int64_t)(pay & ((1u << cb) - 1)) >= C || (int64_t)(pay >> cb) >= C) {
+                    return bad("bin %d deep node %lld leaf classes", b, (long long)i);
+                }
+            }
+            continue;
+        }
         const Node16* bn = nodes + be.node_base;
         for (int64_t i = 0; i < len; i++) {
             const Node16& nd = bn[i];
@@ -507,9 +598,9 @@ extern "C" int fp_pack_forest(const fp_forest_view* forest, const fp_pack_opts* 
     if (!out) return fp_set_error(FP_EINVAL, "out is NULL");
     *out = nullptr;
     if (!opts) return fp_set_error(FP_EINVAL, "opts is NULL");
-    if (opts->layout != FP_LAYOUT_NAIVE && opts->layout != FP_LAYOUT_PACKED)
+    if (opts->layout != FP_LAYOUT_NAIVE && opts->layout != FP_LAYOUT_PACKED && opts->layout != FP_LAYOUT_COMPACT)
         return fp_set_error(FP_EINVAL, "unknown layout %d", opts->layout);
-    if (opts->layout == FP_LAYOUT_PACKED && (opts->interleave_depth < 0 || opts->interleave_depth > 30))
+    if (opts->layout != FP_LAYOUT_NAIVE && (opts->interleave_depth < 0 || opts->interleave_depth > 30))
         return fp_set_error(FP_EINVAL, "interleave_depth %d outside [0, 30]", opts->interleave_depth);
     try {
         std::vector<fp::TreeShape> shapes;

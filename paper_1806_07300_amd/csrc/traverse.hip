@@ -126,7 +126,9 @@ __device__ int stage_group(const JobDesc& j, int group, unsigned char* smem) {
         const int t = t_lo + tl;
         const int b = t / j.bin_size;
         const BinEntry& be = j.bins[b];
-        ttab[tl] = make_int4(j.roots[t], (int32_t)be.node_base, (b - b_lo) * j.cap, min(be.top_len, j.cap));
+        ttab[tl] = j.layout == FP_LAYOUT_COMPACT
+                       ? make_int4(j.roots[t], (int32_t)be.node_base, be.top_len, 0)
+                       : make_int4(j.roots[t], (int32_t)be.node_base, (b - b_lo) * j.cap, min(be.top_len, j.cap));
     }
     if (!j.feat_lds) {
         int32_t* fmap_l = reinterpret_cast<int32_t*>(smem + j.off_fmap);
@@ -234,16 +236,167 @@ __device__ void run_tile(const JobDesc& j, int nt, int tile, unsigned char* smem
     __syncthreads();
 }
 
+// COMPACT layout walk.  Top nodes (Node16) come from memory (L1/L2); a deep
+// node is fetched with one 16-byte load that also brings its successor, the
+// Stat hot child.  When the walk moves to that successor the lane uses the
+// copy it already holds and issues no load at all.
+typedef uint32_t u32x4_a8 __attribute__((ext_vector_type(4), aligned(8)));
+
+template <int K, int FMODE>
+__device__ void run_tile_compact(const JobDesc& j, int nt, int tile, unsigned char* smem) {
+    const bool feat_lds = FMODE == 2 ? (j.feat_lds != 0) : (FMODE == 1);
+    const int4* ttab = reinterpret_cast<const int4*>(smem + j.off_ttab);
+    const int32_t* fmap_l = reinterpret_cast<const int32_t*>(smem + j.off_fmap);
+    float* xs = reinterpret_cast<float*>(smem + j.off_xs);
+    int32_t* vl = reinterpret_cast<int32_t*>(smem + j.off_votes);
+    int32_t* pool = reinterpret_cast<int32_t*>(smem + j.off_pool);
+    const uint2* words = reinterpret_cast<const uint2*>(j.nodes);
+    const int tid = threadIdx.x, bd = blockDim.x;
+    const int lane = lane_id();
+    const int fb = j.fbits, cb = j.cbits;
+    const uint32_t fmask = (1u << fb) - 1u, cmask = (1u << cb) - 1u;
+
+    const int64_t row0 = (int64_t)tile * j.R;
+    const int rows_here = (int)min<int64_t>(j.R, j.n_rows - row0);
+    if (feat_lds) {
+        const int total = rows_here * j.Fc;
+        for (int i = tid; i < total; i += bd) {
+            const int rr = i / j.Fc, c = i - rr * j.Fc;
+            xs[rr * j.Fcp + c] = j.X[(row0 + rr) * j.ld + j.fmap[c]];
+        }
+    }
+    for (int i = tid; i < rows_here * j.C; i += bd) vl[i] = 0;
+    if (tid == 0) *pool = 0;
+    __syncthreads();
+
+    const int U = rows_here * nt;
+    int32_t ref[K], rowk[K], nb[K], topl[K], sref[K];
+    float sthr[K];
+    uint32_t sw[K];
+#pragma unroll
+    for (int k = 0; k < K; k++) {
+        ref[k] = kDone; rowk[k] = 0; nb[k] = 0; topl[k] = 0; sref[k] = -1; sthr[k] = 0.0f; sw[k] = 0;
+    }
+    bool drained = false;
+    while (true) {
+        if (!drained) {
+#pragma unroll
+            for (int k = 0; k < K; k++) {
+                while (!drained) {
+                    const uint64_t m = __ballot(ref[k] == kDone);
+                    if (m == 0) break;
+                    const int cnt = (int)__popcll(m);
+                    int base = 0;
+                    if (lane == 0) base = atomicAdd(pool, cnt);
+                    base = __builtin_amdgcn_readfirstlane(base);
+                    if (base >= U) { drained = true; break; }
+                    if (ref[k] == kDone) {
+                        const int u = base + bits_below(m);
+                        if (u < U) {
+                            const int r = u % rows_here;
+                            const int4 e = ttab[u / rows_here];
+                            rowk[k] = r; nb[k] = e.y; topl[k] = e.z; sref[k] = -1;
+                            if (e.x < 0) atomicAdd(&vl[r * j.C - e.x - 1], 1);  // the root is a leaf
+                            else ref[k] = e.x;
+                        }
+                    }
+                    if (base + cnt >= U) drained = true;
+                }
+            }
+        }
+        bool live = false;
+#pragma unroll
+        for (int k = 0; k < K; k++) live |= ref[k] >= 0;
+        if (__ballot(live) == 0) break;
+        // loads: a top node (16 B), or a deep node with its successor (16 B), or nothing
+        float thr[K];
+        uint32_t a0[K], a1[K], a2[K];
+        bool deep[K];
+#pragma unroll
+        for (int k = 0; k < K; k++) {
+            deep[k] = false;
+            if (ref[k] < 0) continue;
+            if (ref[k] < topl[k]) {
+                const int4 v = *reinterpret_cast<const int4*>(words + nb[k] + 2 * ref[k]);
+                thr[k] = __int_as_float(v.x); a0[k] = (uint32_t)v.y; a1[k] = (uint32_t)v.z; a2[k] = (uint32_t)v.w;
+            } else if (ref[k] == sref[k]) {
+                deep[k] = true;
+                thr[k] = sthr[k]; a0[k] = sw[k];
+            } else {
+                deep[k] = true;
+                const u32x4_a8 v = *reinterpret_cast<const u32x4_a8*>(words + nb[k] + topl[k] + ref[k]);
+                thr[k] = __uint_as_float(v.x); a0[k] = v.y;
+                sthr[k] = __uint_as_float(v.z); sw[k] = v.w; sref[k] = ref[k] + 1;
+            }
+        }
+#pragma unroll
+        for (int k = 0; k < K; k++) {
+            if (ref[k] < 0) continue;
+            const uint32_t f = deep[k] ? (a0[k] & fmask) : a0[k];
+            const float x = feat_lds ? xs[rowk[k] * j.Fcp + f] : j.X[(row0 + rowk[k]) * j.ld + fmap_l[f]];
+            const bool go_left = x <= thr[k];
+            int32_t nr;
+            if (!deep[k]) {
+                nr = go_left ? (int32_t)a1[k] : (int32_t)a2[k];
+            } else {
+                const uint32_t w = a0[k];
+                const uint32_t pay = w >> (fb + 3);
+                if ((w >> fb) & 1u) {
+                    const bool adj_left = (w >> (fb + 1)) & 1u;
+                    if (go_left == adj_left) nr = ref[k] + 1;
+                    else if ((w >> (fb + 2)) & 1u) nr = -(int32_t)pay - 1;
+                    else nr = ref[k] + (int32_t)pay;
+                } else {
+                    nr = -(int32_t)(go_left ? (pay & cmask) : (pay >> cb)) - 1;
+                }
+            }
+            if (nr < 0) {
+                atomicAdd(&vl[rowk[k] * j.C - nr - 1], 1);
+                nr = kDone;
+            }
+            ref[k] = nr;
+        }
+    }
+    __syncthreads();
+    for (int i = tid; i < rows_here * j.C; i += bd) {
+        int32_t* dst = j.votes + row0 * j.C + i;
+        if (j.atomic_votes) {
+            if (vl[i]) atomicAdd(dst, vl[i]);
+        } else {
+            *dst = vl[i];
+        }
+    }
+    if (!j.atomic_votes && j.cls) {
+        for (int rr = tid; rr < rows_here; rr += bd) {
+            int32_t best = 0, bestv = vl[rr * j.C];
+            for (int c = 1; c < j.C; c++)
+                if (vl[rr * j.C + c] > bestv) { bestv = vl[rr * j.C + c]; best = c; }
+            j.cls[row0 + rr] = best;
+        }
+    }
+    __syncthreads();
+}
+
 // One forest: persistent workgroups, group = blockIdx % G (consecutive
 // workgroups land on different XCDs, so G = 8 gives each XCD its own trees).
-template <int K, int FMODE>
-__global__ __launch_bounds__(1024) void packed_kernel(JobDesc j) {
+// Waves per SIMD the kernel must allow: two 1024-thread workgroups per CU
+// (8 waves per SIMD, at most 64 VGPRs) while the cursors fit in that budget.
+template <int K, bool COMPACT>
+struct MinWaves {
+    static constexpr int value = K <= 4 ? 8 : 4;
+};
+
+template <int K, int FMODE, bool COMPACT>
+__global__ __launch_bounds__(1024, (MinWaves<K, COMPACT>::value)) void packed_kernel(JobDesc j) {
     extern __shared__ __align__(16) unsigned char smem[];
     const int group = blockIdx.x % j.G;
     const int blocks_per_group = gridDim.x / j.G;
     const int nt = stage_group(j, group, smem);
     if (nt == 0) return;  // uniform per block
-    for (int tile = blockIdx.x / j.G; tile < j.n_tiles; tile += blocks_per_group) run_tile<K, FMODE>(j, nt, tile, smem);
+    for (int tile = blockIdx.x / j.G; tile < j.n_tiles; tile += blocks_per_group) {
+        if (COMPACT) run_tile_compact<K, FMODE>(j, nt, tile, smem);
+        else run_tile<K, FMODE>(j, nt, tile, smem);
+    }
 }
 
 // Many forests: persistent workgroups pull work items from a global counter
@@ -269,7 +422,10 @@ __global__ __launch_bounds__(1024) void batched_kernel(const JobDesc* __restrict
             staged_group = w.group;
         }
         if (nt == 0) continue;
-        for (int tile = w.tile_begin; tile < w.tile_end; tile++) run_tile<K, 2>(j, nt, tile, smem);
+        if (j.layout == FP_LAYOUT_COMPACT)
+            for (int tile = w.tile_begin; tile < w.tile_end; tile++) run_tile_compact<K, 2>(j, nt, tile, smem);
+        else
+            for (int tile = w.tile_begin; tile < w.tile_end; tile++) run_tile<K, 2>(j, nt, tile, smem);
     }
 }
 
@@ -317,14 +473,16 @@ int check_launch(const char* what) {
     return FP_OK;
 }
 
-template <int K, int FM>
+template <int K, int FM, bool CP>
 const void* packed_fn() {
-    return reinterpret_cast<const void*>(&packed_kernel<K, FM>);
+    return reinterpret_cast<const void*>(&packed_kernel<K, FM, CP>);
 }
 
-const void* pick_packed(int K, int fmode) {
-#define FP_PICK(KK) \
-    if (K == KK) return fmode == 0 ? packed_fn<KK, 0>() : fmode == 1 ? packed_fn<KK, 1>() : packed_fn<KK, 2>();
+const void* pick_packed(int K, int fmode, bool compact) {
+#define FP_PICK(KK)                                                                                   \
+    if (K == KK)                                                                                      \
+        return compact ? (fmode == 0 ? packed_fn<KK, 0, true>() : packed_fn<KK, 1, true>())           \
+                       : (fmode == 0 ? packed_fn<KK, 0, false>() : packed_fn<KK, 1, false>());
     FP_PICK(1)
     FP_PICK(2)
     FP_PICK(4)
@@ -396,7 +554,8 @@ size_t job_lds_layout(JobDesc* j) {
 int resolve_job(const fp_packed* p, const fp_tune* t, const float* X, int64_t n_rows, int64_t ld, int32_t* votes,
                 int32_t* cls, size_t lds_block, JobDesc* j) {
     const Header& h = p->hdr;
-    if (h.layout != FP_LAYOUT_PACKED) return fp_set_error(FP_EINVAL, "forest is not in the packed layout");
+    if (h.layout != FP_LAYOUT_PACKED && h.layout != FP_LAYOUT_COMPACT)
+        return fp_set_error(FP_EINVAL, "forest is not in a packed layout");
     if (!p->dev) return fp_set_error(FP_ENODEV, "packed forest is not uploaded");
     if (h.n_nodes >= INT32_MAX)
         return fp_set_error(FP_E2BIG, "packed forest has %lld nodes (limit 2^31-1)", (long long)h.n_nodes);
@@ -429,6 +588,9 @@ int resolve_job(const fp_packed* p, const fp_tune* t, const float* X, int64_t n_
     j->trees_per_group = tpg;
     j->n_tiles = (int32_t)((n_rows + R - 1) / R);
     j->atomic_votes = G > 1;
+    j->layout = h.layout;
+    j->fbits = h.compact_fbits;
+    j->cbits = h.compact_cbits;
     // feature_lds: 1 force LDS staging, -1 read features from memory, 0 automatic
     j->feat_lds = t->feature_lds >= 0;
     j->cap = 0;
@@ -443,15 +605,15 @@ int resolve_job(const fp_packed* p, const fp_tune* t, const float* X, int64_t n_
             return fp_set_error(FP_E2BIG, "per-workgroup tables of %zu bytes exceed %zu bytes of LDS", need, lds_block);
     }
     size_t top_nodes = (lds_block - need) / sizeof(Node16);
-    if (t->lds_top_nodes < 0) top_nodes = 0;
+    if (t->lds_top_nodes < 0 || h.layout == FP_LAYOUT_COMPACT) top_nodes = 0;  // COMPACT reads tops from memory
     else if (t->lds_top_nodes > 0) top_nodes = std::min(top_nodes, (size_t)t->lds_top_nodes);
     j->cap = (int32_t)std::min<size_t>(top_nodes / bpg, (size_t)h.max_top_len);
     job_lds_layout(j);
     return FP_OK;
 }
 
-int packed_occupancy(int K, int fmode, int threads, size_t lds, int* blocks_per_cu) {
-    const void* fn = pick_packed(K, fmode);
+int packed_occupancy(int K, int fmode, bool compact, int threads, size_t lds, int* blocks_per_cu) {
+    const void* fn = pick_packed(K, fmode, compact);
     if (!fn) return fp_set_error(FP_EINVAL, "cursors must be 1, 2, 4 or 8");
     int occ = 0;
     hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, fn, threads, lds);
@@ -482,7 +644,7 @@ int launch_argmax(const int32_t* votes, int32_t* cls, int64_t n, int32_t C, hipS
 }
 
 int launch_packed(const JobDesc& j, int K, int threads, int blocks, hipStream_t s) {
-    const void* fn = pick_packed(K, j.feat_lds ? 1 : 0);
+    const void* fn = pick_packed(K, j.feat_lds ? 1 : 0, j.layout == FP_LAYOUT_COMPACT);
     if (!fn) return fp_set_error(FP_EINVAL, "cursors must be 1, 2, 4 or 8");
     JobDesc a = j;
     void* args[] = {&a};
@@ -561,7 +723,7 @@ static int predict_impl(const fp_packed* p, const fp_tune* tune, const float* X,
     rc = fp::resolve_job(p, tune, X, n_rows, ld, votes, cls, lds_block, &j);
     if (rc) return rc;
     int occ = 1;
-    rc = fp::packed_occupancy(K, j.feat_lds, threads, (size_t)j.lds_bytes, &occ);
+    rc = fp::packed_occupancy(K, j.feat_lds, j.layout == FP_LAYOUT_COMPACT, threads, (size_t)j.lds_bytes, &occ);
     if (rc) return rc;
     const int64_t per_group = std::min<int64_t>(j.n_tiles, std::max<int64_t>(1, (int64_t)dp.cus * occ / j.G));
     const int blocks = (int)std::max<int64_t>(1, per_group) * j.G;

@@ -6,7 +6,8 @@ import struct
 
 import numpy as np
 
-HEADER = struct.Struct("<QIi" + "i" * 8 + "q" * 7 + "ii" + "Q" + "ii" + "q" + "d")
+HEADER = struct.Struct("<QIi" + "i" * 8 + "q" * 7 + "ii" + "Q" + "ii" + "q" + "d" + "ii")
+NODE8 = np.dtype([("thr", "<f4"), ("w", "<u4")])
 NODE = np.dtype([("thr", "<f4"), ("feat", "<i4"), ("left", "<i4"), ("right", "<i4")])
 BIN = np.dtype([("node_base", "<i8"), ("first_tree", "<i4"), ("n_trees", "<i4"), ("top_len", "<i4"),
                 ("deep_len", "<i4"), ("root_base", "<i4"), ("pad", "<i4")])
@@ -18,10 +19,14 @@ def decode(buf: np.ndarray) -> dict:
     keys = ["magic", "version", "layout", "n_trees", "n_features", "n_classes", "bin_size",
             "interleave_depth", "n_bins", "max_top_len", "max_bin_trees", "total_bytes", "table_offset",
             "roots_offset", "nodes_offset", "n_nodes", "n_internal", "n_leaves", "max_depth", "line_align",
-            "checksum", "n_used_features", "pad0", "fmap_offset", "expected_depth"]
+            "checksum", "n_used_features", "pad0", "fmap_offset", "expected_depth", "compact_fbits",
+            "compact_cbits"]
     h = dict(zip(keys, f))
-    nodes = np.frombuffer(b, NODE, count=h["n_nodes"], offset=h["nodes_offset"])
-    out = {"h": h, "nodes": nodes}
+    if h["layout"] == 2:
+        nodes = np.frombuffer(b, NODE8, count=h["n_nodes"], offset=h["nodes_offset"])
+    else:
+        nodes = np.frombuffer(b, NODE, count=h["n_nodes"], offset=h["nodes_offset"])
+    out = {"h": h, "nodes": nodes, "raw": b}
     if h["layout"] == 0:
         out["tree_off"] = np.frombuffer(b, "<i8", count=h["n_trees"] + 1, offset=h["table_offset"])
     else:
@@ -34,6 +39,8 @@ def decode(buf: np.ndarray) -> dict:
 def walk(dec: dict, X: np.ndarray) -> np.ndarray:
     """Votes [n, C] obtained by walking the decoded buffer (vectorised over rows)."""
     h = dec["h"]
+    if h["layout"] == 2:
+        return walk_compact(dec, X)
     n, C = X.shape[0], h["n_classes"]
     votes = np.zeros((n, C), np.int32)
     nodes = dec["nodes"]
@@ -62,5 +69,57 @@ def walk(dec: dict, X: np.ndarray) -> np.ndarray:
                 nd = bn[np.where(live, ref, 0)]
                 go_left = X[rows, dec["fmap"][nd["feat"]]] <= nd["thr"]
                 ref = np.where(live, np.where(go_left, nd["left"], nd["right"]), ref)
+            np.add.at(votes, (rows, -ref - 1), 1)
+    return votes
+
+
+def compact_bin(dec: dict, be):
+    """(top Node16 array, deep Node8 array) of one bin of a COMPACT buffer."""
+    h, b = dec["h"], dec["raw"]
+    off = h["nodes_offset"] + 8 * int(be["node_base"])
+    top = np.frombuffer(b, NODE, count=int(be["top_len"]), offset=off)
+    deep = np.frombuffer(b, NODE8, count=int(be["deep_len"]), offset=off + 16 * int(be["top_len"]))
+    return top, deep
+
+
+def decode_node8(h, w):
+    """Fields of compact deep-node words (vectorised)."""
+    fb, cb = h["compact_fbits"], h["compact_cbits"]
+    w = w.astype(np.int64)
+    pay = w >> (fb + 3)
+    return {"feat": w & ((1 << fb) - 1), "adj": (w >> fb) & 1, "adj_left": (w >> (fb + 1)) & 1,
+            "cold_class": (w >> (fb + 2)) & 1, "payload": pay, "lclass": pay & ((1 << cb) - 1), "rclass": pay >> cb}
+
+
+def walk_compact(dec: dict, X: np.ndarray) -> np.ndarray:
+    h = dec["h"]
+    n, C = X.shape[0], h["n_classes"]
+    votes = np.zeros((n, C), np.int32)
+    rows = np.arange(n)
+    for be in dec["bins"]:
+        top, deep = compact_bin(dec, be)
+        tl = int(be["top_len"])
+        fields = decode_node8(h, deep["w"]) if len(deep) else None
+        for j in range(int(be["n_trees"])):
+            ref = np.full(n, dec["roots"][be["root_base"] + j], np.int64)
+            while (ref >= 0).any():
+                live = ref >= 0
+                is_top = live & (ref < tl)
+                is_deep = live & (ref >= tl)
+                new = ref.copy()
+                if is_top.any():
+                    nd = top[np.where(is_top, ref, 0)]
+                    go = X[rows, dec["fmap"][nd["feat"]]] <= nd["thr"]
+                    new = np.where(is_top, np.where(go, nd["left"], nd["right"]), new)
+                if is_deep.any():
+                    i = np.where(is_deep, ref - tl, 0)
+                    f = {k: v[i] for k, v in fields.items()}
+                    go = X[rows, dec["fmap"][f["feat"]]] <= deep["thr"][i]
+                    adj_taken = go == (f["adj_left"] == 1)
+                    nxt_adj = np.where(adj_taken, ref + 1,
+                                       np.where(f["cold_class"] == 1, -f["payload"] - 1, ref + f["payload"]))
+                    nxt_leaf = -np.where(go, f["lclass"], f["rclass"]) - 1
+                    new = np.where(is_deep, np.where(f["adj"] == 1, nxt_adj, nxt_leaf), new)
+                ref = new
             np.add.at(votes, (rows, -ref - 1), 1)
     return votes

@@ -24,6 +24,8 @@ SMALL_SPECS = [  # (trees, features, classes, rows, max_depth, bin, depth, tune)
     (48, 60, 4, 2049, 10, 4, 5, {"rows_per_block": 64, "feature_lds": -1}),
     (1, 5, 2, 300, 8, 1, 0, {"rows_per_block": 1}),
     (57, 9, 10, 3000, 12, 19, 3, {"rows_per_block": 32, "tree_groups": 2, "lds_top_nodes": 40}),
+    (70, 20, 3, 4000, -1, 70, 4, {"rows_per_block": 32, "layout": "compact"}),
+    (30, 50, 7, 777, 12, 8, 2, {"rows_per_block": 16, "tree_groups": 2, "layout": "compact"}),
 ]
 
 
@@ -32,7 +34,9 @@ def make_job(i, spec):
     Xt, yt = synth.gaussian_mixture(3000, F, C, seed=500 + i)
     f = synth.train_forest(Xt, yt, n_trees=T, n_classes=C, mtry=max(1, int(np.sqrt(F))), max_depth=depth, seed=600 + i)
     X, _ = synth.gaussian_mixture(N, F, C, seed=700 + i)
-    p = fp.fp_pack_forest(f, bin_size=B, interleave_depth=D)
+    tune = dict(tune)
+    layout = fp.FP_LAYOUT_COMPACT if tune.pop("layout", None) == "compact" else fp.FP_LAYOUT_PACKED
+    p = fp.fp_pack_forest(f, layout=layout, bin_size=B, interleave_depth=D)
     fp.fp_packed_upload(p)
     if tune:
         fp.fp_packed_set_tune(p, tune)

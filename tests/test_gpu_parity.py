@@ -87,11 +87,21 @@ TUNES = [
 ]
 
 
+@pytest.mark.parametrize("layout", [fp.FP_LAYOUT_PACKED, fp.FP_LAYOUT_COMPACT])
 @pytest.mark.parametrize("tune", TUNES, ids=lambda t: "-".join(f"{k[:4]}{v}" for k, v in t.items()))
-def test_packed_launch_grid(small, tune):
+def test_packed_launch_grid(small, tune, layout):
     f, X, want = small
-    p = upload(f, bin_size=8, interleave_depth=3)
-    assert_same(run(p, X, tune), want, str(tune))
+    p = upload(f, layout=layout, bin_size=8, interleave_depth=3)
+    assert_same(run(p, X, tune), want, f"layout {layout} {tune}")
+
+
+@pytest.mark.parametrize("B", [1, 7, 32])
+@pytest.mark.parametrize("D", [0, 2, 5])
+def test_compact_layout_grid(small, B, D):
+    f, X, want = small
+    p = upload(f, layout=fp.FP_LAYOUT_COMPACT, bin_size=B, interleave_depth=D)
+    for K in (1, 2, 4, 8):
+        assert_same(run(p, X, {"cursors": K, "rows_per_block": 16, "block_threads": 512}), want, f"B={B} D={D} K={K}")
 
 
 @pytest.mark.parametrize("n", [0, 1, 15, 17, 257, 4099])
@@ -126,7 +136,8 @@ def test_strided_rows_and_special_values(small):
                     np.where(bump < 0, np.nextafter(pick, np.float32(-np.inf)), pick))
     X[sel] = pick
     want = oracle.predict(f, X)
-    for kw in ({"layout": fp.FP_LAYOUT_NAIVE}, {"bin_size": 4, "interleave_depth": 5}):
+    for kw in ({"layout": fp.FP_LAYOUT_NAIVE}, {"bin_size": 4, "interleave_depth": 5},
+               {"layout": fp.FP_LAYOUT_COMPACT, "bin_size": 4, "interleave_depth": 2}):
         p = upload(f, **kw)
         assert_same(run(p, X, ld_pad=13), want, f"padded ld {kw}")
         assert_same(run(p, X, {"feature_lds": -1, "rows_per_block": 16}), want, f"global features {kw}")
@@ -144,7 +155,8 @@ def test_degenerate_forests():
     for forest in (g, g.subset([4]), g.subset([0])):
         want = oracle.predict(forest, X)
         for kw in ({"layout": fp.FP_LAYOUT_NAIVE}, {"bin_size": 4, "interleave_depth": 0},
-                   {"bin_size": 1, "interleave_depth": 3}):
+                   {"bin_size": 1, "interleave_depth": 3},
+                   {"layout": fp.FP_LAYOUT_COMPACT, "bin_size": 4, "interleave_depth": 0}):
             assert_same(run(upload(forest, **kw), X, {"rows_per_block": 8, "cursors": 4}), want,
                         f"T={forest.n_trees} {kw}")
 
@@ -158,6 +170,8 @@ def test_image_lite():
     for B, D, tune in ((16, 4, None), (4, 6, {"rows_per_block": 8, "cursors": 4, "tree_groups": 4}),
                        (8, 2, {"feature_lds": -1, "rows_per_block": 32})):
         assert_same(run(upload(f, bin_size=B, interleave_depth=D, line_align=1), X, tune), want, f"B={B} D={D}")
+        assert_same(run(upload(f, layout=fp.FP_LAYOUT_COMPACT, bin_size=B, interleave_depth=D), X, tune), want,
+                    f"compact B={B} D={D}")
 
 
 def test_tabular_lite():
@@ -168,6 +182,8 @@ def test_tabular_lite():
     assert_same(run(upload(f, layout=fp.FP_LAYOUT_NAIVE), X), want, "naive")
     for B, D in ((16, 3), (32, 6)):
         assert_same(run(upload(f, bin_size=B, interleave_depth=D), X), want, f"B={B} D={D}")
+        assert_same(run(upload(f, layout=fp.FP_LAYOUT_COMPACT, bin_size=B, interleave_depth=D), X), want,
+                    f"compact B={B} D={D}")
 
 
 def test_image_full_size_sampled():

@@ -233,3 +233,64 @@ def test_image_forest_packs(tmp_path):
     for B, D in ((8, 4), (3, 6)):
         p = fp.fp_pack_forest(f, bin_size=B, interleave_depth=D, line_align=1)
         assert (walk(decode(fp.fp_packed_host_bytes(p)), X) == votes).all()
+
+
+
+@pytest.mark.parametrize("B", [1, 5, 16, 32])
+@pytest.mark.parametrize("D", [0, 2, 4])
+def test_compact_equals_unpacked(small_forest, small_rows, B, D):
+    p = fp.fp_pack_forest(small_forest, layout=fp.FP_LAYOUT_COMPACT, bin_size=B, interleave_depth=D)
+    dec = decode(fp.fp_packed_host_bytes(p))
+    assert dec["h"]["layout"] == 2
+    votes, _ = oracle.predict(small_forest, small_rows)
+    assert (walk(dec, small_rows) == votes).all()
+    # round trip through the verifier
+    q = fp.fp_packed_from_bytes(fp.fp_packed_host_bytes(p))
+    assert np.array_equal(fp.fp_packed_host_bytes(q), fp.fp_packed_host_bytes(p))
+
+
+def test_compact_layout_invariants():
+    """Every compact deep node's adjacent child is the Stat hot child; the two
+    layouts place every internal node at the same reference."""
+    from packed_format import compact_bin, decode_node8
+    w = synth.image(n_train=6000, n_trees=8)
+    f = w.forest()
+    a = decode(fp.fp_packed_host_bytes(fp.fp_pack_forest(f, bin_size=4, interleave_depth=3)))
+    c = decode(fp.fp_packed_host_bytes(fp.fp_pack_forest(f, layout=fp.FP_LAYOUT_COMPACT, bin_size=4,
+                                                          interleave_depth=3)))
+    assert np.array_equal(a["roots"], c["roots"]) and np.array_equal(a["fmap"], c["fmap"])
+    n_deep = 0
+    for ba, bc in zip(a["bins"], c["bins"]):
+        assert ba["top_len"] == bc["top_len"] and ba["deep_len"] == bc["deep_len"]
+        bn = a["nodes"][ba["node_base"]:ba["node_base"] + ba["top_len"] + ba["deep_len"]]
+        top, deep = compact_bin(c, bc)
+        tl = int(ba["top_len"])
+        assert np.array_equal(top["thr"], bn["thr"][:tl]) and np.array_equal(top["left"], bn["left"][:tl])
+        fl = decode_node8(c["h"], deep["w"])
+        for i in range(len(deep)):
+            nd = bn[tl + i]
+            self = tl + i
+            assert deep["thr"][i] == nd["thr"] and fl["feat"][i] == nd["feat"]
+            l, r = int(nd["left"]), int(nd["right"])
+            if l < 0 and r < 0:
+                assert fl["adj"][i] == 0 and fl["lclass"][i] == -l - 1 and fl["rclass"][i] == -r - 1
+                continue
+            assert fl["adj"][i] == 1
+            adj, other = (l, r) if fl["adj_left"][i] else (r, l)
+            assert adj == self + 1
+            if other < 0:
+                assert fl["cold_class"][i] == 1 and fl["payload"][i] == -other - 1
+            else:
+                assert fl["cold_class"][i] == 0 and self + fl["payload"][i] == other
+            n_deep += 1
+    assert n_deep > 1000
+
+
+def test_compact_rejects_bad_bytes(small_forest):
+    a = fp.fp_packed_host_bytes(fp.fp_pack_forest(small_forest, layout=fp.FP_LAYOUT_COMPACT, bin_size=8,
+                                                  interleave_depth=2))
+    bad = a.copy()
+    bad[len(bad) - 300] ^= 0x10
+    with pytest.raises(fp.FPError) as e:
+        fp.fp_packed_from_bytes(bad)
+    assert e.value.code == fp.FP_ECORRUPT
