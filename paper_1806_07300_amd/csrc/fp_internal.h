@@ -62,6 +62,23 @@ struct Node8 {
 };
 static_assert(sizeof(Node8) == 8, "compact node is 8 bytes");
 
+// BLOCKED layout: after a bin's top region (Node16, references as in COMPACT
+// with r >= top_len naming block r - top_len, entered at slot 0) come 64-byte
+// blocks starting on a 64-byte boundary.  Slot s (0..6) of a block is the
+// heap position of a complete three-level subtree (children of s at 2s+1 and
+// 2s+2).  Node word w: bits [0, fb) feature; then a left code and a right
+// code of (1 + cb) bits each: bit 0 set = class child (class in the other cb
+// bits), clear = internal child (in the block for s < 3, else an exit).
+// Exit e = 2 (s - 3) + side of a bottom slot leads to block
+// child_base + rank[e], rank[e] = bits [4e, 4e + 3) of `ranks`; children of a
+// block are stored together, the one with the most training samples first.
+struct Block64 {
+    uint32_t child_base;  // bin-relative block index of the first child block
+    uint32_t ranks;       // 4 bits per exit: rank in the child group (bit 3: exit used)
+    Node8 slot[7];
+};
+static_assert(sizeof(Block64) == 64, "block is 64 bytes");
+
 struct BinEntry {
     int64_t node_base;   // first node of the bin in the node array
     int32_t first_tree;
@@ -90,8 +107,8 @@ struct Header {
     int32_t n_used_features, pad0;
     int64_t fmap_offset;    // feature map (packed), 0 for naive
     double expected_depth;  // mean over trees of the cardinality-weighted leaf depth
-    int32_t compact_fbits;  // COMPACT: feature bits fb
-    int32_t compact_cbits;  // COMPACT: class bits cb of a two-leaf payload
+    int32_t compact_fbits;  // COMPACT, BLOCKED: feature bits fb of a node word
+    int32_t compact_cbits;  // COMPACT, BLOCKED: class bits cb
     uint8_t pad[256 - 152];
 };
 static_assert(sizeof(Header) == 256, "header is 256 bytes");
@@ -130,8 +147,8 @@ struct JobDesc {
     int32_t atomic_votes;      // several tree groups add into the same votes
     int32_t feat_lds;          // 1: observation tile in LDS, 0: read from memory
     int32_t off_top, off_ttab, off_fmap, off_xs, off_votes, off_pool, lds_bytes;
-    int32_t layout;            // FP_LAYOUT_PACKED or FP_LAYOUT_COMPACT
-    int32_t fbits, cbits;      // COMPACT field widths
+    int32_t layout;            // FP_LAYOUT_PACKED, FP_LAYOUT_COMPACT or FP_LAYOUT_BLOCKED
+    int32_t fbits, cbits;      // COMPACT / BLOCKED field widths
     int32_t pad2;
 };
 
@@ -161,7 +178,7 @@ int resolve_job(const fp_packed* p, const fp_tune* t, const float* X, int64_t n_
 // Default LDS footprint of one workgroup: what keeps two workgroups per CU.
 size_t default_lds_block(const DeviceProps& dp);
 
-int packed_occupancy(int K, int fmode, bool compact, int threads, size_t lds, int* blocks_per_cu);
+int packed_occupancy(int K, int fmode, int layout, int threads, size_t lds, int* blocks_per_cu);
 int batched_occupancy(int K, int threads, size_t lds, int* blocks_per_cu);
 
 int launch_fill(int32_t* p, int64_t n, int32_t v, hipStream_t s);

@@ -35,6 +35,7 @@ using fp::BinEntry;
 using fp::Header;
 using fp::Node16;
 using fp::Node8;
+using fp::Block64;
 
 // ---------------------------------------------------------------------------
 // errors
@@ -259,6 +260,22 @@ int pack_naive(const fp_forest_view* v, const std::vector<TreeShape>& s, std::ve
     return FP_OK;
 }
 
+// Compacted feature numbering: the columns some split tests, in increasing order.
+void feature_map(const fp_forest_view* v, const std::vector<TreeShape>& s, std::vector<int32_t>* remap,
+                 std::vector<int32_t>* fmap) {
+    remap->assign(v->n_features, -1);
+    fmap->clear();
+    for (int32_t ti = 0; ti < v->n_trees; ti++)
+        for (int32_t n : s[ti].bfs)
+            if (is_internal(v, s[ti], n)) (*remap)[v->feature[s[ti].base + n]] = 0;
+    for (int32_t f = 0; f < v->n_features; f++)
+        if ((*remap)[f] == 0) {
+            (*remap)[f] = (int32_t)fmap->size();
+            fmap->push_back(f);
+        }
+    if (fmap->empty()) fmap->push_back(0);  // forest of lone leaves: keep one column
+}
+
 int bits_for(int64_t n_values) {  // bits to write 0 .. n_values-1 (at least 1)
     int b = 1;
     while ((int64_t)1 << b < n_values) b++;
@@ -460,6 +477,167 @@ int pack_packed(const fp_forest_view* v, const std::vector<TreeShape>& s, const 
     return FP_OK;
 }
 
+
+// BLOCKED layout: the PACKED top region, then 64-byte blocks holding complete
+// three-level subtrees (see Block64).  Blocks of one tree's deep subtree are
+// allocated breadth-first; a block's child blocks form one contiguous group,
+// ordered by training cardinality (most visited first, ties in exit order).
+int pack_blocked(const fp_forest_view* v, const std::vector<TreeShape>& s, const fp_pack_opts* o,
+                 std::vector<uint8_t>* out, Header* h) {
+    const int32_t T = v->n_trees;
+    const int32_t B = (o->bin_size <= 0 || o->bin_size > T) ? T : o->bin_size;
+    const int32_t D = o->interleave_depth;
+    const int32_t n_bins = (T + B - 1) / B;
+    fill_header_common(h, v, s, FP_LAYOUT_BLOCKED);
+    std::vector<int32_t> remap, fmap;
+    feature_map(v, s, &remap, &fmap);
+    const int fb = bits_for((int64_t)fmap.size());
+    const int cb = bits_for(v->n_classes);
+    if (fb + 2 * (1 + cb) > 32)
+        return fp_set_error(FP_E2BIG, "blocked layout: %d feature bits and %d classes do not fit a 32-bit node word",
+                            fb, v->n_classes);
+    auto code = [&](const TreeShape& t, int32_t child) -> uint32_t {  // (1 + cb)-bit child code
+        const int64_t g = t.base + child;
+        return v->feature[g] >= 0 ? 0u : 1u | ((uint32_t)v->leaf_class[g] << 1);
+    };
+
+    std::vector<BinEntry> bins(n_bins);
+    std::vector<std::vector<Node16>> tops(n_bins);
+    std::vector<std::vector<Block64>> blocks(n_bins);
+    std::vector<int32_t> roots(T, 0);
+    int32_t max_top = 0;
+    int64_t word_cursor = 0;
+    std::vector<int32_t> pos;
+    for (int32_t b = 0; b < n_bins; b++) {
+        BinEntry& be = bins[b];
+        be.first_tree = b * B;
+        be.n_trees = std::min(B, T - b * B);
+        be.root_base = be.first_tree;
+        std::vector<Block64>& bl = blocks[b];
+        // top positions, level-major
+        std::vector<std::vector<int32_t>> tpos(be.n_trees);
+        int32_t next = 0;
+        for (int32_t j = 0; j < be.n_trees; j++) tpos[j].assign(s[be.first_tree + j].size, -1);
+        for (int32_t d = 0; d <= D; d++)
+            for (int32_t j = 0; j < be.n_trees; j++) {
+                const TreeShape& t = s[be.first_tree + j];
+                for (int32_t n : t.bfs) {
+                    if (t.depth[n] > d) break;
+                    if (t.depth[n] == d && is_internal(v, t, n)) tpos[j][n] = next++;
+                }
+            }
+        be.top_len = next;
+        max_top = std::max(max_top, be.top_len);
+        tops[b].assign(be.top_len, Node16{0.0f, 0, 0, 0});
+        for (int32_t j = 0; j < be.n_trees; j++) {
+            const int32_t ti = be.first_tree + j;
+            const TreeShape& t = s[ti];
+            std::vector<int32_t>& tp = tpos[j];
+            // a deep subtree root gets its own block; BFS over blocks fills it
+            std::deque<std::pair<int32_t, int32_t>> queue;  // (block, subtree root)
+            auto ref_of = [&](int32_t child) -> int32_t {
+                const int64_t g = t.base + child;
+                if (v->feature[g] < 0) return -v->leaf_class[g] - 1;
+                if (tp[child] >= 0) return tp[child];
+                const int32_t blk = (int32_t)bl.size();
+                bl.push_back(Block64{});
+                queue.emplace_back(blk, child);
+                return be.top_len + blk;
+            };
+            roots[ti] = ref_of(0);
+            for (int32_t n : t.bfs) {
+                if (t.depth[n] > D) break;
+                if (!is_internal(v, t, n)) continue;
+                const int64_t g = t.base + n;
+                Node16& nd = tops[b][tp[n]];
+                nd.thr = v->threshold[g];
+                nd.feat = remap[v->feature[g]];
+                nd.left = ref_of(v->left[g]);
+                nd.right = ref_of(v->right[g]);
+            }
+            while (!queue.empty()) {
+                const auto [blk, root] = queue.front();
+                queue.pop_front();
+                int32_t slot_node[7];
+                for (int k = 0; k < 7; k++) slot_node[k] = -1;
+                slot_node[0] = root;
+                struct Exit {
+                    int e;
+                    int32_t node;
+                    int64_t card;
+                };
+                std::vector<Exit> exits;
+                Block64 bk{};
+                for (int k = 0; k < 7; k++) {
+                    const int32_t n = slot_node[k];
+                    if (n < 0) continue;
+                    const int64_t g = t.base + n;
+                    const int32_t ch[2] = {v->left[g], v->right[g]};
+                    uint32_t w = (uint32_t)remap[v->feature[g]];
+                    for (int side = 0; side < 2; side++) {
+                        w |= code(t, ch[side]) << (fb + side * (1 + cb));
+                        if (!is_internal(v, t, ch[side])) continue;
+                        if (k < 3) slot_node[2 * k + 1 + side] = ch[side];
+                        else exits.push_back(Exit{2 * (k - 3) + side, ch[side], t.card[ch[side]]});
+                    }
+                    bk.slot[k] = Node8{v->threshold[g], w};
+                }
+                std::stable_sort(exits.begin(), exits.end(),
+                                 [](const Exit& a, const Exit& c) { return a.card > c.card; });
+                bk.child_base = exits.empty() ? 0u : (uint32_t)bl.size();
+                for (size_t r = 0; r < exits.size(); r++) {
+                    bk.ranks |= (8u | (uint32_t)r) << (4 * exits[r].e);
+                    bl.push_back(Block64{});
+                    queue.emplace_back((int32_t)(bk.child_base + r), exits[r].node);
+                }
+                bl[blk] = bk;
+            }
+        }
+        if ((int64_t)be.top_len + (int64_t)bl.size() > INT32_MAX)
+            return fp_set_error(FP_E2BIG, "bin %d holds too many nodes", b);
+        word_cursor = (int64_t)align_up((size_t)word_cursor, 16);
+        be.node_base = word_cursor;
+        be.deep_len = (int32_t)bl.size();
+        word_cursor += (int64_t)align_up(2 * (size_t)be.top_len, 8) + 8 * (int64_t)bl.size();
+    }
+    const int64_t n_words = word_cursor;
+    const size_t table_off = sizeof(Header);
+    const size_t roots_off = align_up(table_off + sizeof(BinEntry) * (size_t)n_bins, kSectionAlign);
+    const size_t fmap_off = align_up(roots_off + sizeof(int32_t) * (size_t)T, kSectionAlign);
+    const size_t nodes_off = align_up(fmap_off + sizeof(int32_t) * fmap.size(), kSectionAlign);
+    const size_t total = align_up(nodes_off + 8 * (size_t)n_words, kSectionAlign);
+    try {
+        out->assign(total, 0);
+    } catch (const std::bad_alloc&) {
+        return fp_set_error(FP_ENOMEM, "cannot allocate %zu bytes for the packed forest", total);
+    }
+    memcpy(out->data() + table_off, bins.data(), sizeof(BinEntry) * (size_t)n_bins);
+    memcpy(out->data() + roots_off, roots.data(), sizeof(int32_t) * (size_t)T);
+    memcpy(out->data() + fmap_off, fmap.data(), sizeof(int32_t) * fmap.size());
+    uint8_t* words = out->data() + nodes_off;
+    for (int32_t b = 0; b < n_bins; b++) {
+        uint8_t* bb = words + 8 * bins[b].node_base;
+        if (!tops[b].empty()) memcpy(bb, tops[b].data(), sizeof(Node16) * tops[b].size());
+        if (!blocks[b].empty())
+            memcpy(bb + 8 * align_up(2 * (size_t)bins[b].top_len, 8), blocks[b].data(), sizeof(Block64) * blocks[b].size());
+    }
+    h->bin_size = B;
+    h->interleave_depth = D;
+    h->n_bins = n_bins;
+    h->max_top_len = max_top;
+    h->max_bin_trees = B;
+    h->n_used_features = (int32_t)fmap.size();
+    h->fmap_offset = (int64_t)fmap_off;
+    h->compact_fbits = fb;
+    h->compact_cbits = cb;
+    h->table_offset = (int64_t)table_off;
+    h->roots_offset = (int64_t)roots_off;
+    h->nodes_offset = (int64_t)nodes_off;
+    h->n_nodes = n_words;
+    finish(out, h);
+    return FP_OK;
+}
+
 }  // namespace
 
 // ---------------------------------------------------------------------------
@@ -478,7 +656,7 @@ int verify_buffer(const uint8_t* bytes, size_t n, std::string* why) {
         return bad("bad forest dimensions");
     if (fnv1a64(bytes + sizeof(Header), n - sizeof(Header)) != h.checksum) return bad("checksum mismatch");
     const int64_t N = h.n_nodes;
-    const int64_t unit = h.layout == FP_LAYOUT_COMPACT ? 8 : (int64_t)sizeof(Node16);
+    const int64_t unit = h.layout == FP_LAYOUT_COMPACT || h.layout == FP_LAYOUT_BLOCKED ? 8 : (int64_t)sizeof(Node16);
     if (N < 0 || h.nodes_offset < (int64_t)sizeof(Header) || h.nodes_offset % 256 ||
         h.nodes_offset + N * unit > (int64_t)n)
         return bad("node section out of bounds");
@@ -507,11 +685,16 @@ int verify_buffer(const uint8_t* bytes, size_t n, std::string* why) {
         }
         return FP_OK;
     }
-    if (h.layout != FP_LAYOUT_PACKED && h.layout != FP_LAYOUT_COMPACT) return bad("unknown layout %d", h.layout);
+    if (h.layout != FP_LAYOUT_PACKED && h.layout != FP_LAYOUT_COMPACT && h.layout != FP_LAYOUT_BLOCKED)
+        return bad("unknown layout %d", h.layout);
     const bool compact = h.layout == FP_LAYOUT_COMPACT;
+    const bool blocked = h.layout == FP_LAYOUT_BLOCKED;
     if (compact && (h.nodes_offset + 8 * N + 16 > (int64_t)n || h.compact_fbits < 1 || h.compact_fbits > 26 ||
                     h.compact_cbits < 1 || 2 * h.compact_cbits > 29 - h.compact_fbits))
         return bad("compact node section or field widths");
+    if (blocked && (h.nodes_offset + 8 * N > (int64_t)n || h.compact_fbits < 1 || h.compact_cbits < 1 ||
+                    h.compact_fbits + 2 * (1 + h.compact_cbits) > 32))
+        return bad("blocked node section or field widths");
     if (h.n_bins < 1 || h.table_offset + (int64_t)sizeof(BinEntry) * h.n_bins > h.roots_offset ||
         h.roots_offset + (int64_t)sizeof(int32_t) * h.n_trees > h.fmap_offset ||
         h.n_used_features < 1 || h.n_used_features > h.n_features ||
@@ -531,8 +714,11 @@ int verify_buffer(const uint8_t* bytes, size_t n, std::string* why) {
         if (be.first_tree != tree_cursor || be.n_trees < 1 || be.root_base != be.first_tree)
             return bad("bin %d tree range", b);
         tree_cursor += be.n_trees;
-        const int64_t units = compact ? 2 * (int64_t)be.top_len + be.deep_len : (int64_t)be.top_len + be.deep_len;
-        if (be.top_len < 0 || be.deep_len < 0 || be.node_base < 0 || be.node_base % (compact ? 16 : 8) ||
+        const int64_t top_words = blocked ? (2 * (int64_t)be.top_len + 7) / 8 * 8 : 2 * (int64_t)be.top_len;
+        const int64_t units = compact   ? top_words + be.deep_len
+                              : blocked ? top_words + 8 * (int64_t)be.deep_len
+                                        : (int64_t)be.top_len + be.deep_len;
+        if (be.top_len < 0 || be.deep_len < 0 || be.node_base < 0 || be.node_base % (compact || blocked ? 16 : 8) ||
             be.node_base + units > N)
             return bad("bin %d node range", b);
         const int64_t len = (int64_t)be.top_len + be.deep_len;
@@ -541,6 +727,60 @@ int verify_buffer(const uint8_t* bytes, size_t n, std::string* why) {
         auto ref_ok = [&](int32_t r, int64_t self) { return r < 0 ? (-(int64_t)r - 1) < C : (r > self && r < len); };
         for (int32_t j = 0; j < be.n_trees; j++)
             if (!ref_ok(roots[be.first_tree + j], -1)) return bad("bin %d root %d", b, j);
+        if (blocked) {
+            if ((int64_t)be.top_len + be.deep_len > INT32_MAX) return bad("bin %d: too many nodes", b);
+            // top refs: forward top node, a block (entered at its slot 0) or a class
+            auto top_ref_ok = [&](int32_t r, int64_t self) {
+                return r < 0 ? (-(int64_t)r - 1) < C : r < be.top_len ? r > self : r - (int64_t)be.top_len < be.deep_len;
+            };
+            for (int32_t j = 0; j < be.n_trees; j++)
+                if (!top_ref_ok(roots[be.first_tree + j], -1)) return bad("bin %d root %d", b, j);
+            const Node8* words = reinterpret_cast<const Node8*>(bytes + h.nodes_offset) + be.node_base;
+            const Node16* top = reinterpret_cast<const Node16*>(words);
+            for (int64_t i = 0; i < be.top_len; i++) {
+                const Node16& nd = top[i];
+                if (nd.feat < 0 || nd.feat >= F || !top_ref_ok(nd.left, i) || !top_ref_ok(nd.right, i))
+                    return bad("bin %d top node %lld", b, (long long)i);
+            }
+            const int fb = h.compact_fbits, cb = h.compact_cbits;
+            const Block64* blk = reinterpret_cast<const Block64*>(words + top_words);
+            for (int64_t k = 0; k < be.deep_len; k++) {
+                const Block64& bk = blk[k];
+                bool present[7] = {true, false, false, false, false, false, false};
+                uint32_t used_exits = 0;
+                for (int s = 0; s < 7; s++) {
+                    const uint32_t w = bk.slot[s].w;
+                    if (!present[s]) {
+                        if (w != 0 || bk.slot[s].thr != 0.0f) return bad("bin %d block %lld: stray slot %d", b, (long long)k, s);
+                        continue;
+                    }
+                    if ((int64_t)(w & ((1u << fb) - 1)) >= F) return bad("bin %d block %lld slot %d feature", b, (long long)k, s);
+                    if (fb + 2 * (1 + cb) < 32 && (w >> (fb + 2 * (1 + cb))) != 0)
+                        return bad("bin %d block %lld slot %d: stray bits", b, (long long)k, s);
+                    for (int side = 0; side < 2; side++) {
+                        const uint32_t c = (w >> (fb + side * (1 + cb))) & ((2u << cb) - 1);
+                        if (c & 1) {
+                            if ((int64_t)(c >> 1) >= C) return bad("bin %d block %lld slot %d class", b, (long long)k, s);
+                        } else if (c != 0) {
+                            return bad("bin %d block %lld slot %d: internal code with payload", b, (long long)k, s);
+                        } else if (s < 3) {
+                            present[2 * s + 1 + side] = true;
+                        } else {
+                            const int e = 2 * (s - 3) + side;
+                            const uint32_t rk = (bk.ranks >> (4 * e)) & 15;
+                            const int64_t child = (int64_t)bk.child_base + (rk & 7);
+                            if (!(rk & 8) || child <= k || child >= be.deep_len)
+                                return bad("bin %d block %lld exit %d", b, (long long)k, e);
+                            used_exits |= 1u << e;
+                        }
+                    }
+                }
+                for (int e = 0; e < 8; e++)
+                    if (!(used_exits >> e & 1) && ((bk.ranks >> (4 * e)) & 15))
+                        return bad("bin %d block %lld: rank of unused exit %d", b, (long long)k, e);
+            }
+            continue;
+        }
         if (compact) {
             const Node8* words = reinterpret_cast<const Node8*>(bytes + h.nodes_offset) + be.node_base;
             const Node16* top = reinterpret_cast<const Node16*>(words);
@@ -598,7 +838,7 @@ extern "C" int fp_pack_forest(const fp_forest_view* forest, const fp_pack_opts* 
     if (!out) return fp_set_error(FP_EINVAL, "out is NULL");
     *out = nullptr;
     if (!opts) return fp_set_error(FP_EINVAL, "opts is NULL");
-    if (opts->layout != FP_LAYOUT_NAIVE && opts->layout != FP_LAYOUT_PACKED && opts->layout != FP_LAYOUT_COMPACT)
+    if (opts->layout < FP_LAYOUT_NAIVE || opts->layout > FP_LAYOUT_BLOCKED)
         return fp_set_error(FP_EINVAL, "unknown layout %d", opts->layout);
     if (opts->layout != FP_LAYOUT_NAIVE && (opts->interleave_depth < 0 || opts->interleave_depth > 30))
         return fp_set_error(FP_EINVAL, "interleave_depth %d outside [0, 30]", opts->interleave_depth);
@@ -607,8 +847,9 @@ extern "C" int fp_pack_forest(const fp_forest_view* forest, const fp_pack_opts* 
         int rc = fp::validate_view(forest, &shapes);
         if (rc) return rc;
         std::unique_ptr<fp_packed> p(new fp_packed());
-        rc = opts->layout == FP_LAYOUT_NAIVE ? fp::pack_naive(forest, shapes, &p->bytes, &p->hdr)
-                                             : fp::pack_packed(forest, shapes, opts, &p->bytes, &p->hdr);
+        rc = opts->layout == FP_LAYOUT_NAIVE     ? fp::pack_naive(forest, shapes, &p->bytes, &p->hdr)
+             : opts->layout == FP_LAYOUT_BLOCKED ? fp::pack_blocked(forest, shapes, opts, &p->bytes, &p->hdr)
+                                                 : fp::pack_packed(forest, shapes, opts, &p->bytes, &p->hdr);
         if (rc) return rc;
         *out = p.release();
         return FP_OK;

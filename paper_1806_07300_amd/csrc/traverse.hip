@@ -126,9 +126,10 @@ __device__ int stage_group(const JobDesc& j, int group, unsigned char* smem) {
         const int t = t_lo + tl;
         const int b = t / j.bin_size;
         const BinEntry& be = j.bins[b];
-        ttab[tl] = j.layout == FP_LAYOUT_COMPACT
-                       ? make_int4(j.roots[t], (int32_t)be.node_base, be.top_len, 0)
-                       : make_int4(j.roots[t], (int32_t)be.node_base, (b - b_lo) * j.cap, min(be.top_len, j.cap));
+        const int32_t nb = (int32_t)be.node_base;
+        ttab[tl] = j.layout == FP_LAYOUT_COMPACT   ? make_int4(j.roots[t], nb, be.top_len, 0)
+                   : j.layout == FP_LAYOUT_BLOCKED ? make_int4(j.roots[t], nb, be.top_len, nb + (2 * be.top_len + 7) / 8 * 8)
+                                                   : make_int4(j.roots[t], nb, (b - b_lo) * j.cap, min(be.top_len, j.cap));
     }
     if (!j.feat_lds) {
         int32_t* fmap_l = reinterpret_cast<int32_t*>(smem + j.off_fmap);
@@ -377,24 +378,183 @@ __device__ void run_tile_compact(const JobDesc& j, int nt, int tile, unsigned ch
     __syncthreads();
 }
 
+
+// BLOCKED layout walk.  A top node (Node16) is one step per iteration; a
+// block is fetched whole (four 16-byte loads of one 64-byte block, a single
+// cache line) and then walked for up to three levels from registers: slot 0,
+// then slot 1 or 2, then one of slots 3..6, ending in a class or an exit to a
+// child block, which the next iteration fetches.
+struct BlockRegs {
+    uint4 q0, q1, q2, q3;  // child_base, ranks, (thr, w) of slots 0..6
+};
+
+template <int K, int FMODE>
+__device__ void run_tile_blocked(const JobDesc& j, int nt, int tile, unsigned char* smem) {
+    const bool feat_lds = FMODE == 2 ? (j.feat_lds != 0) : (FMODE == 1);
+    const int4* ttab = reinterpret_cast<const int4*>(smem + j.off_ttab);
+    const int32_t* fmap_l = reinterpret_cast<const int32_t*>(smem + j.off_fmap);
+    float* xs = reinterpret_cast<float*>(smem + j.off_xs);
+    int32_t* vl = reinterpret_cast<int32_t*>(smem + j.off_votes);
+    int32_t* pool = reinterpret_cast<int32_t*>(smem + j.off_pool);
+    const uint2* words = reinterpret_cast<const uint2*>(j.nodes);
+    const int tid = threadIdx.x, bd = blockDim.x;
+    const int lane = lane_id();
+    const int fb = j.fbits, cb = j.cbits;
+    const uint32_t fmask = (1u << fb) - 1u, code_mask = (2u << cb) - 1u;
+
+    const int64_t row0 = (int64_t)tile * j.R;
+    const int rows_here = (int)min<int64_t>(j.R, j.n_rows - row0);
+    if (feat_lds) {
+        const int total = rows_here * j.Fc;
+        for (int i = tid; i < total; i += bd) {
+            const int rr = i / j.Fc, c = i - rr * j.Fc;
+            xs[rr * j.Fcp + c] = j.X[(row0 + rr) * j.ld + j.fmap[c]];
+        }
+    }
+    for (int i = tid; i < rows_here * j.C; i += bd) vl[i] = 0;
+    if (tid == 0) *pool = 0;
+    __syncthreads();
+
+    // x <= thr for compacted feature f of cursor row r
+    auto le = [&](int r, uint32_t f, float thr) {
+        const float x = feat_lds ? xs[r * j.Fcp + f] : j.X[(row0 + r) * j.ld + fmap_l[f]];
+        return x <= thr;
+    };
+
+    const int U = rows_here * nt;
+    int32_t ref[K], rowk[K], nb[K], topl[K], bb[K];
+#pragma unroll
+    for (int k = 0; k < K; k++) { ref[k] = kDone; rowk[k] = 0; nb[k] = 0; topl[k] = 0; bb[k] = 0; }
+    bool drained = false;
+    while (true) {
+        if (!drained) {
+#pragma unroll
+            for (int k = 0; k < K; k++) {
+                while (!drained) {
+                    const uint64_t m = __ballot(ref[k] == kDone);
+                    if (m == 0) break;
+                    const int cnt = (int)__popcll(m);
+                    int base = 0;
+                    if (lane == 0) base = atomicAdd(pool, cnt);
+                    base = __builtin_amdgcn_readfirstlane(base);
+                    if (base >= U) { drained = true; break; }
+                    if (ref[k] == kDone) {
+                        const int u = base + bits_below(m);
+                        if (u < U) {
+                            const int r = u % rows_here;
+                            const int4 e = ttab[u / rows_here];
+                            rowk[k] = r; nb[k] = e.y; topl[k] = e.z; bb[k] = e.w;
+                            if (e.x < 0) atomicAdd(&vl[r * j.C - e.x - 1], 1);  // the root is a leaf
+                            else ref[k] = e.x;
+                        }
+                    }
+                    if (base + cnt >= U) drained = true;
+                }
+            }
+        }
+        bool live = false;
+#pragma unroll
+        for (int k = 0; k < K; k++) live |= ref[k] >= 0;
+        if (__ballot(live) == 0) break;
+        BlockRegs g[K];
+#pragma unroll
+        for (int k = 0; k < K; k++) {
+            if (ref[k] < 0) continue;
+            if (ref[k] < topl[k]) {
+                g[k].q0 = *reinterpret_cast<const uint4*>(words + nb[k] + 2 * ref[k]);
+            } else {
+                const uint4* bp = reinterpret_cast<const uint4*>(words + bb[k] + 8 * (ref[k] - topl[k]));
+                g[k].q0 = bp[0]; g[k].q1 = bp[1]; g[k].q2 = bp[2]; g[k].q3 = bp[3];
+            }
+        }
+#pragma unroll
+        for (int k = 0; k < K; k++) {
+            if (ref[k] < 0) continue;
+            const uint4 q0 = g[k].q0;
+            int32_t nr;
+            if (ref[k] < topl[k]) {
+                nr = le(rowk[k], q0.y, __uint_as_float(q0.x)) ? (int32_t)q0.z : (int32_t)q0.w;
+            } else {
+                const uint4 q1 = g[k].q1, q2 = g[k].q2, q3 = g[k].q3;
+                // level 0: slot 0
+                uint32_t w = q0.w;
+                uint32_t side = le(rowk[k], w & fmask, __uint_as_float(q0.z)) ? 0u : 1u;
+                uint32_t c = (w >> (fb + side * (1 + cb))) & code_mask;
+                if (c & 1u) {
+                    nr = -(int32_t)(c >> 1) - 1;
+                } else {
+                    // level 1: slot 1 + side
+                    const uint32_t s1 = side;
+                    w = s1 ? q1.w : q1.y;
+                    float t = __uint_as_float(s1 ? q1.z : q1.x);
+                    side = le(rowk[k], w & fmask, t) ? 0u : 1u;
+                    c = (w >> (fb + side * (1 + cb))) & code_mask;
+                    if (c & 1u) {
+                        nr = -(int32_t)(c >> 1) - 1;
+                    } else {
+                        // level 2: slot 3 + idx, idx = 2 s1 + side
+                        const uint32_t idx = 2 * s1 + side;
+                        const uint4 qq = idx < 2 ? q2 : q3;
+                        w = (idx & 1u) ? qq.w : qq.y;
+                        t = __uint_as_float((idx & 1u) ? qq.z : qq.x);
+                        side = le(rowk[k], w & fmask, t) ? 0u : 1u;
+                        c = (w >> (fb + side * (1 + cb))) & code_mask;
+                        if (c & 1u) {
+                            nr = -(int32_t)(c >> 1) - 1;
+                        } else {
+                            const uint32_t e = 2 * idx + side;
+                            nr = topl[k] + (int32_t)(q0.x + ((q0.y >> (4 * e)) & 7u));
+                        }
+                    }
+                }
+            }
+            if (nr < 0) {
+                atomicAdd(&vl[rowk[k] * j.C - nr - 1], 1);
+                nr = kDone;
+            }
+            ref[k] = nr;
+        }
+    }
+    __syncthreads();
+    for (int i = tid; i < rows_here * j.C; i += bd) {
+        int32_t* dst = j.votes + row0 * j.C + i;
+        if (j.atomic_votes) {
+            if (vl[i]) atomicAdd(dst, vl[i]);
+        } else {
+            *dst = vl[i];
+        }
+    }
+    if (!j.atomic_votes && j.cls) {
+        for (int rr = tid; rr < rows_here; rr += bd) {
+            int32_t best = 0, bestv = vl[rr * j.C];
+            for (int c = 1; c < j.C; c++)
+                if (vl[rr * j.C + c] > bestv) { bestv = vl[rr * j.C + c]; best = c; }
+            j.cls[row0 + rr] = best;
+        }
+    }
+    __syncthreads();
+}
+
 // One forest: persistent workgroups, group = blockIdx % G (consecutive
 // workgroups land on different XCDs, so G = 8 gives each XCD its own trees).
 // Waves per SIMD the kernel must allow: two 1024-thread workgroups per CU
 // (8 waves per SIMD, at most 64 VGPRs) while the cursors fit in that budget.
-template <int K, bool COMPACT>
+// A BLOCKED cursor holds a 64-byte block in 16 registers while it walks it.
+template <int K, int LAYOUT>
 struct MinWaves {
-    static constexpr int value = K <= 4 ? 8 : 4;
+    static constexpr int value = LAYOUT == FP_LAYOUT_BLOCKED ? (K <= 2 ? 8 : K == 4 ? 4 : 2) : (K <= 4 ? 8 : 4);
 };
 
-template <int K, int FMODE, bool COMPACT>
-__global__ __launch_bounds__(1024, (MinWaves<K, COMPACT>::value)) void packed_kernel(JobDesc j) {
+template <int K, int FMODE, int LAYOUT>
+__global__ __launch_bounds__(1024, (MinWaves<K, LAYOUT>::value)) void packed_kernel(JobDesc j) {
     extern __shared__ __align__(16) unsigned char smem[];
     const int group = blockIdx.x % j.G;
     const int blocks_per_group = gridDim.x / j.G;
     const int nt = stage_group(j, group, smem);
     if (nt == 0) return;  // uniform per block
     for (int tile = blockIdx.x / j.G; tile < j.n_tiles; tile += blocks_per_group) {
-        if (COMPACT) run_tile_compact<K, FMODE>(j, nt, tile, smem);
+        if (LAYOUT == FP_LAYOUT_COMPACT) run_tile_compact<K, FMODE>(j, nt, tile, smem);
+        else if (LAYOUT == FP_LAYOUT_BLOCKED) run_tile_blocked<K, FMODE>(j, nt, tile, smem);
         else run_tile<K, FMODE>(j, nt, tile, smem);
     }
 }
@@ -424,6 +584,8 @@ __global__ __launch_bounds__(1024) void batched_kernel(const JobDesc* __restrict
         if (nt == 0) continue;
         if (j.layout == FP_LAYOUT_COMPACT)
             for (int tile = w.tile_begin; tile < w.tile_end; tile++) run_tile_compact<K, 2>(j, nt, tile, smem);
+        else if (j.layout == FP_LAYOUT_BLOCKED)
+            for (int tile = w.tile_begin; tile < w.tile_end; tile++) run_tile_blocked<(K > 2 ? 2 : K), 2>(j, nt, tile, smem);
         else
             for (int tile = w.tile_begin; tile < w.tile_end; tile++) run_tile<K, 2>(j, nt, tile, smem);
     }
@@ -473,16 +635,22 @@ int check_launch(const char* what) {
     return FP_OK;
 }
 
-template <int K, int FM, bool CP>
+template <int K, int FM, int L>
 const void* packed_fn() {
-    return reinterpret_cast<const void*>(&packed_kernel<K, FM, CP>);
+    return reinterpret_cast<const void*>(&packed_kernel<K, FM, L>);
 }
 
-const void* pick_packed(int K, int fmode, bool compact) {
-#define FP_PICK(KK)                                                                                   \
-    if (K == KK)                                                                                      \
-        return compact ? (fmode == 0 ? packed_fn<KK, 0, true>() : packed_fn<KK, 1, true>())           \
-                       : (fmode == 0 ? packed_fn<KK, 0, false>() : packed_fn<KK, 1, false>());
+template <int K, int L>
+const void* packed_fn_fm(int fmode) {
+    return fmode == 0 ? packed_fn<K, 0, L>() : packed_fn<K, 1, L>();
+}
+
+const void* pick_packed(int K, int fmode, int layout) {
+#define FP_PICK(KK)                                                                     \
+    if (K == KK)                                                                        \
+        return layout == FP_LAYOUT_COMPACT   ? packed_fn_fm<KK, FP_LAYOUT_COMPACT>(fmode) \
+               : layout == FP_LAYOUT_BLOCKED ? packed_fn_fm<KK, FP_LAYOUT_BLOCKED>(fmode) \
+                                             : packed_fn_fm<KK, FP_LAYOUT_PACKED>(fmode);
     FP_PICK(1)
     FP_PICK(2)
     FP_PICK(4)
@@ -554,7 +722,7 @@ size_t job_lds_layout(JobDesc* j) {
 int resolve_job(const fp_packed* p, const fp_tune* t, const float* X, int64_t n_rows, int64_t ld, int32_t* votes,
                 int32_t* cls, size_t lds_block, JobDesc* j) {
     const Header& h = p->hdr;
-    if (h.layout != FP_LAYOUT_PACKED && h.layout != FP_LAYOUT_COMPACT)
+    if (h.layout != FP_LAYOUT_PACKED && h.layout != FP_LAYOUT_COMPACT && h.layout != FP_LAYOUT_BLOCKED)
         return fp_set_error(FP_EINVAL, "forest is not in a packed layout");
     if (!p->dev) return fp_set_error(FP_ENODEV, "packed forest is not uploaded");
     if (h.n_nodes >= INT32_MAX)
@@ -605,15 +773,15 @@ int resolve_job(const fp_packed* p, const fp_tune* t, const float* X, int64_t n_
             return fp_set_error(FP_E2BIG, "per-workgroup tables of %zu bytes exceed %zu bytes of LDS", need, lds_block);
     }
     size_t top_nodes = (lds_block - need) / sizeof(Node16);
-    if (t->lds_top_nodes < 0 || h.layout == FP_LAYOUT_COMPACT) top_nodes = 0;  // COMPACT reads tops from memory
+    if (t->lds_top_nodes < 0 || h.layout != FP_LAYOUT_PACKED) top_nodes = 0;  // COMPACT, BLOCKED: tops from memory
     else if (t->lds_top_nodes > 0) top_nodes = std::min(top_nodes, (size_t)t->lds_top_nodes);
     j->cap = (int32_t)std::min<size_t>(top_nodes / bpg, (size_t)h.max_top_len);
     job_lds_layout(j);
     return FP_OK;
 }
 
-int packed_occupancy(int K, int fmode, bool compact, int threads, size_t lds, int* blocks_per_cu) {
-    const void* fn = pick_packed(K, fmode, compact);
+int packed_occupancy(int K, int fmode, int layout, int threads, size_t lds, int* blocks_per_cu) {
+    const void* fn = pick_packed(K, fmode, layout);
     if (!fn) return fp_set_error(FP_EINVAL, "cursors must be 1, 2, 4 or 8");
     int occ = 0;
     hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, fn, threads, lds);
@@ -644,7 +812,7 @@ int launch_argmax(const int32_t* votes, int32_t* cls, int64_t n, int32_t C, hipS
 }
 
 int launch_packed(const JobDesc& j, int K, int threads, int blocks, hipStream_t s) {
-    const void* fn = pick_packed(K, j.feat_lds ? 1 : 0, j.layout == FP_LAYOUT_COMPACT);
+    const void* fn = pick_packed(K, j.feat_lds ? 1 : 0, j.layout);
     if (!fn) return fp_set_error(FP_EINVAL, "cursors must be 1, 2, 4 or 8");
     JobDesc a = j;
     void* args[] = {&a};
@@ -723,7 +891,7 @@ static int predict_impl(const fp_packed* p, const fp_tune* tune, const float* X,
     rc = fp::resolve_job(p, tune, X, n_rows, ld, votes, cls, lds_block, &j);
     if (rc) return rc;
     int occ = 1;
-    rc = fp::packed_occupancy(K, j.feat_lds, j.layout == FP_LAYOUT_COMPACT, threads, (size_t)j.lds_bytes, &occ);
+    rc = fp::packed_occupancy(K, j.feat_lds, j.layout, threads, (size_t)j.lds_bytes, &occ);
     if (rc) return rc;
     const int64_t per_group = std::min<int64_t>(j.n_tiles, std::max<int64_t>(1, (int64_t)dp.cus * occ / j.G));
     const int blocks = (int)std::max<int64_t>(1, per_group) * j.G;

@@ -22,7 +22,7 @@ def decode(buf: np.ndarray) -> dict:
             "checksum", "n_used_features", "pad0", "fmap_offset", "expected_depth", "compact_fbits",
             "compact_cbits"]
     h = dict(zip(keys, f))
-    if h["layout"] == 2:
+    if h["layout"] in (2, 3):
         nodes = np.frombuffer(b, NODE8, count=h["n_nodes"], offset=h["nodes_offset"])
     else:
         nodes = np.frombuffer(b, NODE, count=h["n_nodes"], offset=h["nodes_offset"])
@@ -41,6 +41,8 @@ def walk(dec: dict, X: np.ndarray) -> np.ndarray:
     h = dec["h"]
     if h["layout"] == 2:
         return walk_compact(dec, X)
+    if h["layout"] == 3:
+        return walk_blocked(dec, X)
     n, C = X.shape[0], h["n_classes"]
     votes = np.zeros((n, C), np.int32)
     nodes = dec["nodes"]
@@ -123,3 +125,71 @@ def walk_compact(dec: dict, X: np.ndarray) -> np.ndarray:
                 ref = new
             np.add.at(votes, (rows, -ref - 1), 1)
     return votes
+
+
+BLOCK = np.dtype({"names": ["child_base", "ranks", "slot"],
+                  "formats": ["<u4", "<u4", np.dtype((NODE8, 7))]})
+
+
+def blocked_bin(dec: dict, be):
+    """(top Node16 array, Block64 array) of one bin of a BLOCKED buffer."""
+    h, b = dec["h"], dec["raw"]
+    off = h["nodes_offset"] + 8 * int(be["node_base"])
+    tl = int(be["top_len"])
+    top = np.frombuffer(b, NODE, count=tl, offset=off)
+    blocks = np.frombuffer(b, BLOCK, count=int(be["deep_len"]), offset=off + 8 * ((2 * tl + 7) // 8 * 8))
+    return top, blocks
+
+
+def walk_blocked(dec: dict, X: np.ndarray) -> np.ndarray:
+    """Votes [n, C] from walking a BLOCKED buffer (vectorised over rows)."""
+    h = dec["h"]
+    fb, cb = h["compact_fbits"], h["compact_cbits"]
+    n, C = X.shape[0], h["n_classes"]
+    votes = np.zeros((n, C), np.int32)
+    rows = np.arange(n)
+    fmap = dec["fmap"]
+    for be in dec["bins"]:
+        top, blocks = blocked_bin(dec, be)
+        tl = int(be["top_len"])
+        for j in range(int(be["n_trees"])):
+            ref = np.full(n, dec["roots"][be["root_base"] + j], np.int64)
+            while ((ref >= 0) & (ref < tl)).any():
+                live = (ref >= 0) & (ref < tl)
+                nd = top[np.where(live, ref, 0)]
+                go = X[rows, fmap[nd["feat"]]] <= nd["thr"]
+                ref = np.where(live, np.where(go, nd["left"], nd["right"]), ref)
+            k = np.where(ref >= tl, ref - tl, 0)
+            slot = np.zeros(n, np.int64)
+            live = ref >= tl
+            while live.any():
+                bk = blocks[k]
+                w = bk["slot"]["w"][rows, slot].astype(np.int64)
+                thr = bk["slot"]["thr"][rows, slot]
+                side = np.where(X[rows, fmap[w & ((1 << fb) - 1)]] <= thr, 0, 1)
+                c = (w >> (fb + side * (1 + cb))) & ((2 << cb) - 1)
+                leaf = live & (c & 1 == 1)
+                ref = np.where(leaf, -(c >> 1) - 1, ref)
+                inner = live & ~leaf & (slot < 3)
+                ex = live & ~leaf & (slot >= 3)
+                e = 2 * (slot - 3) + side
+                rank = (bk["ranks"].astype(np.int64) >> (4 * np.where(ex, e, 0))) & 7
+                k = np.where(ex, bk["child_base"].astype(np.int64) + rank, k)
+                slot = np.where(inner, 2 * slot + 1 + side, np.where(ex, 0, slot))
+                live = live & ~leaf
+            np.add.at(votes, (rows, -ref - 1), 1)
+    return votes
+
+
+def reseal(buf: np.ndarray) -> np.ndarray:
+    """Copy of a packed buffer with its header checksum recomputed (FNV-1a
+    over the little-endian 64-bit words after the 256-byte header), so that
+    tests can plant structural faults behind a valid checksum."""
+    out = buf.copy()
+    words = out[256:].view("<u8")
+    h = 0xcbf29ce484222325
+    for v in words.tolist():
+        h = ((h ^ v) * 0x100000001b3) & 0xFFFFFFFFFFFFFFFF
+    pos = struct.calcsize("<QIi" + "i" * 8 + "q" * 7 + "ii")
+    out[pos:pos + 8] = np.frombuffer(struct.pack("<Q", h), np.uint8)
+    return out

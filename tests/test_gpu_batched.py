@@ -26,6 +26,8 @@ SMALL_SPECS = [  # (trees, features, classes, rows, max_depth, bin, depth, tune)
     (57, 9, 10, 3000, 12, 19, 3, {"rows_per_block": 32, "tree_groups": 2, "lds_top_nodes": 40}),
     (70, 20, 3, 4000, -1, 70, 4, {"rows_per_block": 32, "layout": "compact"}),
     (30, 50, 7, 777, 12, 8, 2, {"rows_per_block": 16, "tree_groups": 2, "layout": "compact"}),
+    (45, 16, 4, 2500, -1, 45, 0, {"rows_per_block": 32, "layout": "blocked"}),
+    (26, 33, 9, 999, 14, 5, 3, {"rows_per_block": 8, "tree_groups": 3, "layout": "blocked"}),
 ]
 
 
@@ -35,7 +37,8 @@ def make_job(i, spec):
     f = synth.train_forest(Xt, yt, n_trees=T, n_classes=C, mtry=max(1, int(np.sqrt(F))), max_depth=depth, seed=600 + i)
     X, _ = synth.gaussian_mixture(N, F, C, seed=700 + i)
     tune = dict(tune)
-    layout = fp.FP_LAYOUT_COMPACT if tune.pop("layout", None) == "compact" else fp.FP_LAYOUT_PACKED
+    layout = {"compact": fp.FP_LAYOUT_COMPACT, "blocked": fp.FP_LAYOUT_BLOCKED}.get(tune.pop("layout", None),
+                                                                                fp.FP_LAYOUT_PACKED)
     p = fp.fp_pack_forest(f, layout=layout, bin_size=B, interleave_depth=D)
     fp.fp_packed_upload(p)
     if tune:

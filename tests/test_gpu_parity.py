@@ -87,7 +87,7 @@ TUNES = [
 ]
 
 
-@pytest.mark.parametrize("layout", [fp.FP_LAYOUT_PACKED, fp.FP_LAYOUT_COMPACT])
+@pytest.mark.parametrize("layout", [fp.FP_LAYOUT_PACKED, fp.FP_LAYOUT_COMPACT, fp.FP_LAYOUT_BLOCKED])
 @pytest.mark.parametrize("tune", TUNES, ids=lambda t: "-".join(f"{k[:4]}{v}" for k, v in t.items()))
 def test_packed_launch_grid(small, tune, layout):
     f, X, want = small
@@ -95,13 +95,15 @@ def test_packed_launch_grid(small, tune, layout):
     assert_same(run(p, X, tune), want, f"layout {layout} {tune}")
 
 
+@pytest.mark.parametrize("layout", [fp.FP_LAYOUT_COMPACT, fp.FP_LAYOUT_BLOCKED])
 @pytest.mark.parametrize("B", [1, 7, 32])
 @pytest.mark.parametrize("D", [0, 2, 5])
-def test_compact_layout_grid(small, B, D):
+def test_compact_layout_grid(small, B, D, layout):
     f, X, want = small
-    p = upload(f, layout=fp.FP_LAYOUT_COMPACT, bin_size=B, interleave_depth=D)
+    p = upload(f, layout=layout, bin_size=B, interleave_depth=D)
     for K in (1, 2, 4, 8):
-        assert_same(run(p, X, {"cursors": K, "rows_per_block": 16, "block_threads": 512}), want, f"B={B} D={D} K={K}")
+        assert_same(run(p, X, {"cursors": K, "rows_per_block": 16, "block_threads": 512}), want,
+                    f"layout={layout} B={B} D={D} K={K}")
 
 
 @pytest.mark.parametrize("n", [0, 1, 15, 17, 257, 4099])
@@ -137,7 +139,8 @@ def test_strided_rows_and_special_values(small):
     X[sel] = pick
     want = oracle.predict(f, X)
     for kw in ({"layout": fp.FP_LAYOUT_NAIVE}, {"bin_size": 4, "interleave_depth": 5},
-               {"layout": fp.FP_LAYOUT_COMPACT, "bin_size": 4, "interleave_depth": 2}):
+               {"layout": fp.FP_LAYOUT_COMPACT, "bin_size": 4, "interleave_depth": 2},
+               {"layout": fp.FP_LAYOUT_BLOCKED, "bin_size": 4, "interleave_depth": 1}):
         p = upload(f, **kw)
         assert_same(run(p, X, ld_pad=13), want, f"padded ld {kw}")
         assert_same(run(p, X, {"feature_lds": -1, "rows_per_block": 16}), want, f"global features {kw}")
@@ -156,7 +159,9 @@ def test_degenerate_forests():
         want = oracle.predict(forest, X)
         for kw in ({"layout": fp.FP_LAYOUT_NAIVE}, {"bin_size": 4, "interleave_depth": 0},
                    {"bin_size": 1, "interleave_depth": 3},
-                   {"layout": fp.FP_LAYOUT_COMPACT, "bin_size": 4, "interleave_depth": 0}):
+                   {"layout": fp.FP_LAYOUT_COMPACT, "bin_size": 4, "interleave_depth": 0},
+                   {"layout": fp.FP_LAYOUT_BLOCKED, "bin_size": 4, "interleave_depth": 0},
+                   {"layout": fp.FP_LAYOUT_BLOCKED, "bin_size": 2, "interleave_depth": 2}):
             assert_same(run(upload(forest, **kw), X, {"rows_per_block": 8, "cursors": 4}), want,
                         f"T={forest.n_trees} {kw}")
 
@@ -172,6 +177,8 @@ def test_image_lite():
         assert_same(run(upload(f, bin_size=B, interleave_depth=D, line_align=1), X, tune), want, f"B={B} D={D}")
         assert_same(run(upload(f, layout=fp.FP_LAYOUT_COMPACT, bin_size=B, interleave_depth=D), X, tune), want,
                     f"compact B={B} D={D}")
+        assert_same(run(upload(f, layout=fp.FP_LAYOUT_BLOCKED, bin_size=B, interleave_depth=D), X, tune), want,
+                    f"blocked B={B} D={D}")
 
 
 def test_tabular_lite():
@@ -184,6 +191,8 @@ def test_tabular_lite():
         assert_same(run(upload(f, bin_size=B, interleave_depth=D), X), want, f"B={B} D={D}")
         assert_same(run(upload(f, layout=fp.FP_LAYOUT_COMPACT, bin_size=B, interleave_depth=D), X), want,
                     f"compact B={B} D={D}")
+        assert_same(run(upload(f, layout=fp.FP_LAYOUT_BLOCKED, bin_size=B, interleave_depth=D), X), want,
+                    f"blocked B={B} D={D}")
 
 
 def test_image_full_size_sampled():

@@ -22,7 +22,8 @@ def forests():
     for i, w in enumerate(specs):
         f = w.forest()
         pool, _ = w.predict_rows(20_000)
-        p = fp.fp_pack_forest(f, bin_size=8, interleave_depth=3)
+        layout = (fp.FP_LAYOUT_PACKED, fp.FP_LAYOUT_COMPACT, fp.FP_LAYOUT_BLOCKED)[i]
+        p = fp.fp_pack_forest(f, layout=layout, bin_size=8, interleave_depth=3)
         fp.fp_packed_upload(p)
         if i == 1:
             fp.fp_packed_set_tune(p, {"rows_per_block": 16, "tree_groups": 2})
