@@ -287,7 +287,7 @@ def main():
                         "purity on 60,000 rows, 1,000,000 rows per step",
             "n_rows": n, "n_trees": forest.n_trees, "n_features": F, "n_classes": C,
             "internal_nodes": info["n_internal"],
-            "layout": {0: "naive", 1: "packed", 2: "compact"}[info["layout"]],
+            "layout": {0: "naive", 1: "packed", 2: "compact", 3: "blocked"}[info["layout"]],
             "bin_size": info["bin_size"], "interleave_depth": info["interleave_depth"], "tune": cfg["tune"],
         },
         "naive": {"value": n / (ms_naive / 1e3), "ms_per_step": ms_naive},

@@ -201,7 +201,7 @@ void fp_packed_free(fp_packed *p);
 /*
  * Launch parameters of the traversal kernels (the GPU form of assigning bins
  * to workers, Sec. III, and of Bin+ round-robin evaluation, Sec. III-B).
- *   rows_per_block  observations per workgroup (packed layout; 1..64)
+ *   rows_per_block  observations per workgroup (packed layouts; 1..4096)
  *   cursors         trees a lane walks concurrently, round-robin (1, 2, 4, 8)
  *   tree_groups     bins are split into this many groups, each group handled
  *                   by its own workgroups (votes then merge with atomics);
@@ -211,6 +211,10 @@ void fp_packed_free(fp_packed *p);
  *                   as LDS allows; -1: none)
  *   feature_lds     1: stage the observation tile in LDS (FP_E2BIG if it cannot
  *                   fit); -1: read features from memory; 0: LDS when it fits
+ *   refill_lanes    a wavefront hands its idle cursors new walks once this many
+ *                   of its lanes (1..64) are idle in a cursor slot, or when none
+ *                   is walking; larger values spend fewer instructions on
+ *                   refills and leave lanes idle longer
  * Zero fields mean "library default".  Naive layout uses block_threads only.
  */
 typedef struct fp_tune {
@@ -220,7 +224,8 @@ typedef struct fp_tune {
     int32_t block_threads;
     int32_t lds_top_nodes;
     int32_t feature_lds;
-    int32_t reserved[2];
+    int32_t refill_lanes;
+    int32_t reserved;
 } fp_tune;
 
 /* Store `tune` as the launch parameters fp_predict uses for p (NULL: defaults). */

@@ -149,7 +149,7 @@ struct JobDesc {
     int32_t off_top, off_ttab, off_fmap, off_xs, off_votes, off_pool, lds_bytes;
     int32_t layout;            // FP_LAYOUT_PACKED, FP_LAYOUT_COMPACT or FP_LAYOUT_BLOCKED
     int32_t fbits, cbits;      // COMPACT / BLOCKED field widths
-    int32_t pad2;
+    int32_t refill_min;        // idle lanes of a wavefront that trigger a refill
 };
 
 // One entry of the batched work list: tiles [tile_begin, tile_end) of job

@@ -45,6 +45,7 @@ using fp::WorkItem;
 namespace {
 
 constexpr int32_t kDone = INT32_MIN;
+constexpr int kDefaultRefillLanes = 16;
 
 // ---------------------------------------------------------------------------
 // naive kernel
@@ -104,6 +105,79 @@ __device__ __forceinline__ int lane_id() { return __builtin_amdgcn_mbcnt_hi(~0u,
 __device__ __forceinline__ int bits_below(uint64_t m) {
     return __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
 }
+
+// Unit u of a tile is (tree u / rows, row u % rows).  The division uses a
+// 32-bit reciprocal m = floor((2^32 - 1) / rows): umulhi(u, m) is the
+// quotient or one less for any u < 2^32, so one correction step is exact.
+__device__ __forceinline__ uint32_t div_rows(uint32_t u, uint32_t rows, uint32_t m, uint32_t& rem) {
+    uint32_t q = __umulhi(u, m);
+    uint32_t r = u - q * rows;
+    if (r >= rows) {
+        q += 1;
+        r -= rows;
+    }
+    rem = r;
+    return q;
+}
+
+// Hands the idle cursors of a wavefront new units from the workgroup pool:
+// per cursor slot one LDS atomic by lane 0 reserves as many units as there
+// are idle lanes, and each idle lane takes base + (idle lanes below it).  A
+// slot is refilled only once at least `min_idle` lanes have it idle, or when
+// nothing in the wavefront is live, so most steps skip the refill's
+// instructions.  take(k, row, ttab entry) sets cursor k up and returns its
+// first reference, or kDone after voting when the tree's root is a leaf (the
+// lane then stays idle and takes another unit).
+template <int K, typename Take>
+__device__ __forceinline__ void refill(int32_t (&ref)[K], int32_t* pool, int U, uint32_t rows, uint32_t rmagic,
+                                       const int4* ttab, int min_idle, int lane, bool& drained, Take&& take) {
+    uint64_t live = 0;
+#pragma unroll
+    for (int k = 0; k < K; k++) live |= __ballot(ref[k] >= 0);
+#pragma unroll
+    for (int k = 0; k < K; k++) {
+        while (!drained) {
+            const uint64_t m = __ballot(ref[k] < 0);
+            const int cnt = (int)__popcll(m);
+            if (cnt == 0 || (cnt < min_idle && live != 0)) break;
+            int base = 0;
+            if (lane == 0) base = atomicAdd(pool, cnt);
+            base = __builtin_amdgcn_readfirstlane(base);
+            if (base >= U) {
+                drained = true;
+                break;
+            }
+            if (ref[k] < 0) {
+                const uint32_t u = (uint32_t)(base + bits_below(m));
+                if (u < (uint32_t)U) {
+                    uint32_t r;
+                    const uint32_t t = div_rows(u, rows, rmagic, r);
+                    ref[k] = take(k, (int)r, ttab[t]);
+                }
+            }
+            if (base + cnt >= U) drained = true;
+        }
+    }
+}
+
+// A tile's observations as the walks see them: feature f of tile row r
+// (staged in LDS, or read from memory through the feature map) and the LDS
+// vote counters of row r.  Row offsets use 24-bit multiplies (full rate;
+// rows < 4096 and columns, classes < 2^24).
+struct TileRows {
+    const JobDesc& j;
+    const float* xs;
+    int32_t* vl;
+    const int32_t* fmap_l;
+    int64_t row0;
+    bool feat_lds;
+    __device__ __forceinline__ float x(int r, uint32_t f) const {
+        return feat_lds ? xs[__umul24((uint32_t)r, (uint32_t)j.Fcp) + f] : j.X[(row0 + r) * j.ld + fmap_l[f]];
+    }
+    __device__ __forceinline__ void vote(int r, int32_t cls) const {
+        atomicAdd(&vl[__umul24((uint32_t)r, (uint32_t)j.C) + (uint32_t)cls], 1);
+    }
+};
 
 // Stage the bin tops, the tree table and (when features are read from memory)
 // the feature map of tree group `group`; returns the group's tree count.
@@ -165,40 +239,31 @@ __device__ void run_tile(const JobDesc& j, int nt, int tile, unsigned char* smem
     __syncthreads();
 
     const int U = rows_here * nt;
+    const uint32_t rmagic = 0xFFFFFFFFu / (uint32_t)rows_here;
+    TileRows tr{j, xs, vl, fmap_l, row0, feat_lds};
+    // per cursor: row in the tile, gb = bin base in the node array, lb = the
+    // bin's first top node in LDS, cp = top nodes staged in LDS
     int32_t ref[K], rowk[K], gb[K], lb[K], cp[K];
 #pragma unroll
     for (int k = 0; k < K; k++) { ref[k] = kDone; rowk[k] = 0; gb[k] = 0; lb[k] = 0; cp[k] = 0; }
-    bool drained = false;  // wave-uniform: the pool has no units left
-    while (true) {
-        if (!drained) {
-#pragma unroll
-            for (int k = 0; k < K; k++) {
-                while (!drained) {
-                    const uint64_t m = __ballot(ref[k] == kDone);
-                    if (m == 0) break;
-                    const int cnt = (int)__popcll(m);
-                    int base = 0;
-                    if (lane == 0) base = atomicAdd(pool, cnt);
-                    base = __builtin_amdgcn_readfirstlane(base);
-                    if (base >= U) { drained = true; break; }
-                    if (ref[k] == kDone) {
-                        const int u = base + bits_below(m);
-                        if (u < U) {
-                            const int r = u % rows_here;
-                            const int4 e = ttab[u / rows_here];
-                            rowk[k] = r; gb[k] = e.y; lb[k] = e.z; cp[k] = e.w;
-                            if (e.x < 0) atomicAdd(&vl[r * j.C - e.x - 1], 1);  // the root is a leaf
-                            else ref[k] = e.x;
-                        }
-                    }
-                    if (base + cnt >= U) drained = true;
-                }
-            }
+    auto take = [&](int k, int r, int4 e) -> int32_t {
+        rowk[k] = r; gb[k] = e.y; lb[k] = e.z; cp[k] = e.w;
+        if (e.x < 0) {  // the root is a leaf
+            tr.vote(r, -e.x - 1);
+            return kDone;
         }
+        return e.x;
+    };
+    bool drained = false;
+    while (true) {
+        if (!drained) refill<K>(ref, pool, U, (uint32_t)rows_here, rmagic, ttab, j.refill_min, lane, drained, take);
         bool live = false;
 #pragma unroll
         for (int k = 0; k < K; k++) live |= ref[k] >= 0;
-        if (__ballot(live) == 0) break;
+        if (__ballot(live) == 0) {
+            if (drained) break;
+            continue;
+        }
         Node16 nd[K];
 #pragma unroll
         for (int k = 0; k < K; k++)
@@ -206,11 +271,9 @@ __device__ void run_tile(const JobDesc& j, int nt, int tile, unsigned char* smem
 #pragma unroll
         for (int k = 0; k < K; k++) {
             if (ref[k] >= 0) {
-                const float x = feat_lds ? xs[rowk[k] * j.Fcp + nd[k].feat]
-                                         : j.X[(row0 + rowk[k]) * j.ld + fmap_l[nd[k].feat]];
-                int32_t nr = (x <= nd[k].thr) ? nd[k].left : nd[k].right;
+                int32_t nr = (tr.x(rowk[k], nd[k].feat) <= nd[k].thr) ? nd[k].left : nd[k].right;
                 if (nr < 0) {
-                    atomicAdd(&vl[rowk[k] * j.C - nr - 1], 1);
+                    tr.vote(rowk[k], -nr - 1);
                     nr = kDone;
                 }
                 ref[k] = nr;
@@ -240,7 +303,8 @@ __device__ void run_tile(const JobDesc& j, int nt, int tile, unsigned char* smem
 // COMPACT layout walk.  Top nodes (Node16) come from memory (L1/L2); a deep
 // node is fetched with one 16-byte load that also brings its successor, the
 // Stat hot child.  When the walk moves to that successor the lane uses the
-// copy it already holds and issues no load at all.
+// copy it already holds and issues no load at all.  Each cursor keeps the
+// LDS byte addresses of its row's features and votes, set once per walk.
 typedef uint32_t u32x4_a8 __attribute__((ext_vector_type(4), aligned(8)));
 
 template <int K, int FMODE>
@@ -271,6 +335,10 @@ __device__ void run_tile_compact(const JobDesc& j, int nt, int tile, unsigned ch
     __syncthreads();
 
     const int U = rows_here * nt;
+    const uint32_t rmagic = 0xFFFFFFFFu / (uint32_t)rows_here;
+    TileRows tr{j, xs, vl, fmap_l, row0, feat_lds};
+    // per cursor: row in the tile, nb = bin base (words), topl = top_len,
+    // the successor copy (sref, sthr, sw)
     int32_t ref[K], rowk[K], nb[K], topl[K], sref[K];
     float sthr[K];
     uint32_t sw[K];
@@ -278,37 +346,24 @@ __device__ void run_tile_compact(const JobDesc& j, int nt, int tile, unsigned ch
     for (int k = 0; k < K; k++) {
         ref[k] = kDone; rowk[k] = 0; nb[k] = 0; topl[k] = 0; sref[k] = -1; sthr[k] = 0.0f; sw[k] = 0;
     }
+    auto take = [&](int k, int r, int4 e) -> int32_t {
+        rowk[k] = r; nb[k] = e.y; topl[k] = e.z; sref[k] = -1;
+        if (e.x < 0) {  // the root is a leaf
+            tr.vote(r, -e.x - 1);
+            return kDone;
+        }
+        return e.x;
+    };
     bool drained = false;
     while (true) {
-        if (!drained) {
-#pragma unroll
-            for (int k = 0; k < K; k++) {
-                while (!drained) {
-                    const uint64_t m = __ballot(ref[k] == kDone);
-                    if (m == 0) break;
-                    const int cnt = (int)__popcll(m);
-                    int base = 0;
-                    if (lane == 0) base = atomicAdd(pool, cnt);
-                    base = __builtin_amdgcn_readfirstlane(base);
-                    if (base >= U) { drained = true; break; }
-                    if (ref[k] == kDone) {
-                        const int u = base + bits_below(m);
-                        if (u < U) {
-                            const int r = u % rows_here;
-                            const int4 e = ttab[u / rows_here];
-                            rowk[k] = r; nb[k] = e.y; topl[k] = e.z; sref[k] = -1;
-                            if (e.x < 0) atomicAdd(&vl[r * j.C - e.x - 1], 1);  // the root is a leaf
-                            else ref[k] = e.x;
-                        }
-                    }
-                    if (base + cnt >= U) drained = true;
-                }
-            }
-        }
+        if (!drained) refill<K>(ref, pool, U, (uint32_t)rows_here, rmagic, ttab, j.refill_min, lane, drained, take);
         bool live = false;
 #pragma unroll
         for (int k = 0; k < K; k++) live |= ref[k] >= 0;
-        if (__ballot(live) == 0) break;
+        if (__ballot(live) == 0) {
+            if (drained) break;
+            continue;
+        }
         // loads: a top node (16 B), or a deep node with its successor (16 B), or nothing
         float thr[K];
         uint32_t a0[K], a1[K], a2[K];
@@ -334,8 +389,7 @@ __device__ void run_tile_compact(const JobDesc& j, int nt, int tile, unsigned ch
         for (int k = 0; k < K; k++) {
             if (ref[k] < 0) continue;
             const uint32_t f = deep[k] ? (a0[k] & fmask) : a0[k];
-            const float x = feat_lds ? xs[rowk[k] * j.Fcp + f] : j.X[(row0 + rowk[k]) * j.ld + fmap_l[f]];
-            const bool go_left = x <= thr[k];
+            const bool go_left = tr.x(rowk[k], f) <= thr[k];
             int32_t nr;
             if (!deep[k]) {
                 nr = go_left ? (int32_t)a1[k] : (int32_t)a2[k];
@@ -352,7 +406,7 @@ __device__ void run_tile_compact(const JobDesc& j, int nt, int tile, unsigned ch
                 }
             }
             if (nr < 0) {
-                atomicAdd(&vl[rowk[k] * j.C - nr - 1], 1);
+                tr.vote(rowk[k], -nr - 1);
                 nr = kDone;
             }
             ref[k] = nr;
@@ -377,7 +431,6 @@ __device__ void run_tile_compact(const JobDesc& j, int nt, int tile, unsigned ch
     }
     __syncthreads();
 }
-
 
 // BLOCKED layout walk.  A top node (Node16) is one step per iteration; a
 // block is fetched whole (four 16-byte loads of one 64-byte block, a single
@@ -415,47 +468,33 @@ __device__ void run_tile_blocked(const JobDesc& j, int nt, int tile, unsigned ch
     if (tid == 0) *pool = 0;
     __syncthreads();
 
-    // x <= thr for compacted feature f of cursor row r
-    auto le = [&](int r, uint32_t f, float thr) {
-        const float x = feat_lds ? xs[r * j.Fcp + f] : j.X[(row0 + r) * j.ld + fmap_l[f]];
-        return x <= thr;
-    };
-
     const int U = rows_here * nt;
+    const uint32_t rmagic = 0xFFFFFFFFu / (uint32_t)rows_here;
+    TileRows tr{j, xs, vl, fmap_l, row0, feat_lds};
+    auto le = [&](int r, uint32_t f, float thr) { return tr.x(r, f) <= thr; };
+    // per cursor: row in the tile, nb = bin base, bb = first block of the bin
+    // (words), topl = top_len
     int32_t ref[K], rowk[K], nb[K], topl[K], bb[K];
 #pragma unroll
     for (int k = 0; k < K; k++) { ref[k] = kDone; rowk[k] = 0; nb[k] = 0; topl[k] = 0; bb[k] = 0; }
+    auto take = [&](int k, int r, int4 e) -> int32_t {
+        rowk[k] = r; nb[k] = e.y; topl[k] = e.z; bb[k] = e.w;
+        if (e.x < 0) {  // the root is a leaf
+            tr.vote(r, -e.x - 1);
+            return kDone;
+        }
+        return e.x;
+    };
     bool drained = false;
     while (true) {
-        if (!drained) {
-#pragma unroll
-            for (int k = 0; k < K; k++) {
-                while (!drained) {
-                    const uint64_t m = __ballot(ref[k] == kDone);
-                    if (m == 0) break;
-                    const int cnt = (int)__popcll(m);
-                    int base = 0;
-                    if (lane == 0) base = atomicAdd(pool, cnt);
-                    base = __builtin_amdgcn_readfirstlane(base);
-                    if (base >= U) { drained = true; break; }
-                    if (ref[k] == kDone) {
-                        const int u = base + bits_below(m);
-                        if (u < U) {
-                            const int r = u % rows_here;
-                            const int4 e = ttab[u / rows_here];
-                            rowk[k] = r; nb[k] = e.y; topl[k] = e.z; bb[k] = e.w;
-                            if (e.x < 0) atomicAdd(&vl[r * j.C - e.x - 1], 1);  // the root is a leaf
-                            else ref[k] = e.x;
-                        }
-                    }
-                    if (base + cnt >= U) drained = true;
-                }
-            }
-        }
+        if (!drained) refill<K>(ref, pool, U, (uint32_t)rows_here, rmagic, ttab, j.refill_min, lane, drained, take);
         bool live = false;
 #pragma unroll
         for (int k = 0; k < K; k++) live |= ref[k] >= 0;
-        if (__ballot(live) == 0) break;
+        if (__ballot(live) == 0) {
+            if (drained) break;
+            continue;
+        }
         BlockRegs g[K];
 #pragma unroll
         for (int k = 0; k < K; k++) {
@@ -509,7 +548,7 @@ __device__ void run_tile_blocked(const JobDesc& j, int nt, int tile, unsigned ch
                 }
             }
             if (nr < 0) {
-                atomicAdd(&vl[rowk[k] * j.C - nr - 1], 1);
+                tr.vote(rowk[k], -nr - 1);
                 nr = kDone;
             }
             ref[k] = nr;
@@ -539,10 +578,14 @@ __device__ void run_tile_blocked(const JobDesc& j, int nt, int tile, unsigned ch
 // workgroups land on different XCDs, so G = 8 gives each XCD its own trees).
 // Waves per SIMD the kernel must allow: two 1024-thread workgroups per CU
 // (8 waves per SIMD, at most 64 VGPRs) while the cursors fit in that budget.
-// A BLOCKED cursor holds a 64-byte block in 16 registers while it walks it.
+// COMPACT and BLOCKED cursors carry more state (a BLOCKED one holds a
+// 64-byte block in 16 registers while it walks it).  A 1024-thread workgroup
+// needs 4 waves per SIMD, so no variant gets more than 128 VGPRs.
 template <int K, int LAYOUT>
 struct MinWaves {
-    static constexpr int value = LAYOUT == FP_LAYOUT_BLOCKED ? (K <= 2 ? 8 : K == 4 ? 4 : 2) : (K <= 4 ? 8 : 4);
+    static constexpr int value = LAYOUT == FP_LAYOUT_PACKED   ? (K <= 4 ? 8 : 4)
+                                 : LAYOUT == FP_LAYOUT_COMPACT ? (K <= 2 ? 8 : 4)
+                                                               : (K == 1 ? 8 : 4);
 };
 
 template <int K, int FMODE, int LAYOUT>
@@ -759,6 +802,8 @@ int resolve_job(const fp_packed* p, const fp_tune* t, const float* X, int64_t n_
     j->layout = h.layout;
     j->fbits = h.compact_fbits;
     j->cbits = h.compact_cbits;
+    if (t->refill_lanes < 0 || t->refill_lanes > 64) return fp_set_error(FP_EINVAL, "refill_lanes %d outside [0, 64]", t->refill_lanes);
+    j->refill_min = t->refill_lanes > 0 ? t->refill_lanes : kDefaultRefillLanes;
     // feature_lds: 1 force LDS staging, -1 read features from memory, 0 automatic
     j->feat_lds = t->feature_lds >= 0;
     j->cap = 0;
