@@ -117,12 +117,14 @@ enum {
      * classes and in-tree distances to fit 32 bits (FP_E2BIG otherwise);
      * line_align is ignored. */
     FP_LAYOUT_COMPACT = 2,
-    /* PACKED top levels with the deep region cut into 64-byte blocks, each a
-     * complete three-level subtree (7 node slots + a header): one fetch serves
-     * up to three steps of a walk.  A block's child blocks are stored
-     * together, most-visited first by training cardinality (Stat at block
-     * granularity).  Needs feature and class fields to fit 32 bits
-     * (FP_E2BIG otherwise); line_align is ignored. */
+    /* Every tree cut into 64-byte blocks, each a complete three-level
+     * subtree (7 node slots + a header): one fetch serves up to three steps
+     * of a walk.  A block's child blocks are stored together, most-visited
+     * first by training cardinality (Stat at block granularity).  Bin
+     * interleaving moves to blocks: the blocks whose root node has depth
+     * <= interleave_depth, of all the bin's trees, come first, level-major.
+     * Needs feature and class fields to fit 32 bits (FP_E2BIG otherwise);
+     * line_align is ignored. */
     FP_LAYOUT_BLOCKED = 3
 };
 

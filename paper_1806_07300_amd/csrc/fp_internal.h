@@ -62,9 +62,9 @@ struct Node8 {
 };
 static_assert(sizeof(Node8) == 8, "compact node is 8 bytes");
 
-// BLOCKED layout: after a bin's top region (Node16, references as in COMPACT
-// with r >= top_len naming block r - top_len, entered at slot 0) come 64-byte
-// blocks starting on a 64-byte boundary.  Slot s (0..6) of a block is the
+// BLOCKED layout: a bin is an array of 64-byte blocks (top_len = 0, deep_len
+// = block count); a reference r >= 0 names block r of the bin, entered at
+// slot 0, r < 0 is class -r-1.  Slot s (0..6) of a block is the
 // heap position of a complete three-level subtree (children of s at 2s+1 and
 // 2s+2).  Node word w: bits [0, fb) feature; then a left code and a right
 // code of (1 + cb) bits each: bit 0 set = class child (class in the other cb

@@ -478,10 +478,15 @@ int pack_packed(const fp_forest_view* v, const std::vector<TreeShape>& s, const 
 }
 
 
-// BLOCKED layout: the PACKED top region, then 64-byte blocks holding complete
-// three-level subtrees (see Block64).  Blocks of one tree's deep subtree are
-// allocated breadth-first; a block's child blocks form one contiguous group,
-// ordered by training cardinality (most visited first, ties in exit order).
+// BLOCKED layout: every internal node lives in a 64-byte block holding a
+// complete three-level subtree (see Block64); there is no Node16 region.
+// Each tree's blocks form a tree of their own, built breadth-first; a block's
+// child blocks are one contiguous group ordered by training cardinality
+// (most samples first, ties in exit order).  Bin interleaving works on
+// blocks: the blocks whose root node has depth <= D (block levels
+// 0 .. D / 3) of all the bin's trees come first, level-major and tree-minor;
+// then each tree's remaining blocks, tree by tree, breadth-first.  Both
+// orders keep every child group contiguous and after its parent.
 int pack_blocked(const fp_forest_view* v, const std::vector<TreeShape>& s, const fp_pack_opts* o,
                  std::vector<uint8_t>* out, Header* h) {
     const int32_t T = v->n_trees;
@@ -496,109 +501,104 @@ int pack_blocked(const fp_forest_view* v, const std::vector<TreeShape>& s, const
     if (fb + 2 * (1 + cb) > 32)
         return fp_set_error(FP_E2BIG, "blocked layout: %d feature bits and %d classes do not fit a 32-bit node word",
                             fb, v->n_classes);
-    auto code = [&](const TreeShape& t, int32_t child) -> uint32_t {  // (1 + cb)-bit child code
-        const int64_t g = t.base + child;
-        return v->feature[g] >= 0 ? 0u : 1u | ((uint32_t)v->leaf_class[g] << 1);
+    const int32_t last_interleaved_level = D / 3;
+
+    // One tree's blocks in breadth-first order: the subtree root node of each
+    // block, its level, the bfs index of its first child block and its exits.
+    struct TreeBlocks {
+        std::vector<int32_t> root, level, first_child;
+        std::vector<Block64> body;  // child_base holds the bfs index of the first child until placed
+    };
+    auto build_tree = [&](const TreeShape& t, TreeBlocks* tb) {
+        tb->root.assign(1, 0);
+        tb->level.assign(1, 0);
+        for (size_t q = 0; q < tb->root.size(); q++) {
+            int32_t slot_node[7];
+            for (int k = 0; k < 7; k++) slot_node[k] = -1;
+            slot_node[0] = tb->root[q];
+            struct Exit {
+                int e;
+                int32_t node;
+                int64_t card;
+            };
+            std::vector<Exit> exits;
+            Block64 bk{};
+            for (int k = 0; k < 7; k++) {
+                const int32_t n = slot_node[k];
+                if (n < 0) continue;
+                const int64_t g = t.base + n;
+                const int32_t ch[2] = {v->left[g], v->right[g]};
+                uint32_t w = (uint32_t)remap[v->feature[g]];
+                for (int side = 0; side < 2; side++) {
+                    const int64_t gc = t.base + ch[side];
+                    const uint32_t c = v->feature[gc] >= 0 ? 0u : 1u | ((uint32_t)v->leaf_class[gc] << 1);
+                    w |= c << (fb + side * (1 + cb));
+                    if (v->feature[gc] < 0) continue;
+                    if (k < 3) slot_node[2 * k + 1 + side] = ch[side];
+                    else exits.push_back(Exit{2 * (k - 3) + side, ch[side], t.card[ch[side]]});
+                }
+                bk.slot[k] = Node8{v->threshold[g], w};
+            }
+            std::stable_sort(exits.begin(), exits.end(), [](const Exit& a, const Exit& c) { return a.card > c.card; });
+            bk.child_base = (uint32_t)tb->root.size();  // bfs index of the first child, rewritten when placed
+            for (size_t r = 0; r < exits.size(); r++) {
+                bk.ranks |= (8u | (uint32_t)r) << (4 * exits[r].e);
+                tb->root.push_back(exits[r].node);
+                tb->level.push_back(tb->level[q] + 1);
+            }
+            tb->body.push_back(bk);
+        }
     };
 
     std::vector<BinEntry> bins(n_bins);
-    std::vector<std::vector<Node16>> tops(n_bins);
     std::vector<std::vector<Block64>> blocks(n_bins);
     std::vector<int32_t> roots(T, 0);
-    int32_t max_top = 0;
     int64_t word_cursor = 0;
-    std::vector<int32_t> pos;
     for (int32_t b = 0; b < n_bins; b++) {
         BinEntry& be = bins[b];
         be.first_tree = b * B;
         be.n_trees = std::min(B, T - b * B);
         be.root_base = be.first_tree;
+        be.top_len = 0;
+        std::vector<TreeBlocks> tb(be.n_trees);
+        for (int32_t j = 0; j < be.n_trees; j++) {
+            const TreeShape& t = s[be.first_tree + j];
+            if (v->feature[t.base] >= 0) build_tree(t, &tb[j]);
+        }
+        // final position of every (tree, bfs index)
+        std::vector<std::vector<int64_t>> pos(be.n_trees);
+        int64_t next = 0;
+        for (int32_t j = 0; j < be.n_trees; j++) pos[j].assign(tb[j].root.size(), -1);
+        for (int32_t L = 0; L <= last_interleaved_level; L++)
+            for (int32_t j = 0; j < be.n_trees; j++)
+                for (size_t q = 0; q < tb[j].root.size(); q++)
+                    if (tb[j].level[q] == L) pos[j][q] = next++;
+        for (int32_t j = 0; j < be.n_trees; j++)
+            for (size_t q = 0; q < tb[j].root.size(); q++)
+                if (pos[j][q] < 0) pos[j][q] = next++;
+        if (next > INT32_MAX) return fp_set_error(FP_E2BIG, "bin %d holds too many blocks", b);
         std::vector<Block64>& bl = blocks[b];
-        // top positions, level-major
-        std::vector<std::vector<int32_t>> tpos(be.n_trees);
-        int32_t next = 0;
-        for (int32_t j = 0; j < be.n_trees; j++) tpos[j].assign(s[be.first_tree + j].size, -1);
-        for (int32_t d = 0; d <= D; d++)
-            for (int32_t j = 0; j < be.n_trees; j++) {
-                const TreeShape& t = s[be.first_tree + j];
-                for (int32_t n : t.bfs) {
-                    if (t.depth[n] > d) break;
-                    if (t.depth[n] == d && is_internal(v, t, n)) tpos[j][n] = next++;
-                }
-            }
-        be.top_len = next;
-        max_top = std::max(max_top, be.top_len);
-        tops[b].assign(be.top_len, Node16{0.0f, 0, 0, 0});
+        bl.assign((size_t)next, Block64{});
         for (int32_t j = 0; j < be.n_trees; j++) {
             const int32_t ti = be.first_tree + j;
             const TreeShape& t = s[ti];
-            std::vector<int32_t>& tp = tpos[j];
-            // a deep subtree root gets its own block; BFS over blocks fills it
-            std::deque<std::pair<int32_t, int32_t>> queue;  // (block, subtree root)
-            auto ref_of = [&](int32_t child) -> int32_t {
-                const int64_t g = t.base + child;
-                if (v->feature[g] < 0) return -v->leaf_class[g] - 1;
-                if (tp[child] >= 0) return tp[child];
-                const int32_t blk = (int32_t)bl.size();
-                bl.push_back(Block64{});
-                queue.emplace_back(blk, child);
-                return be.top_len + blk;
-            };
-            roots[ti] = ref_of(0);
-            for (int32_t n : t.bfs) {
-                if (t.depth[n] > D) break;
-                if (!is_internal(v, t, n)) continue;
-                const int64_t g = t.base + n;
-                Node16& nd = tops[b][tp[n]];
-                nd.thr = v->threshold[g];
-                nd.feat = remap[v->feature[g]];
-                nd.left = ref_of(v->left[g]);
-                nd.right = ref_of(v->right[g]);
+            if (v->feature[t.base] < 0) {
+                roots[ti] = -v->leaf_class[t.base] - 1;
+                continue;
             }
-            while (!queue.empty()) {
-                const auto [blk, root] = queue.front();
-                queue.pop_front();
-                int32_t slot_node[7];
-                for (int k = 0; k < 7; k++) slot_node[k] = -1;
-                slot_node[0] = root;
-                struct Exit {
-                    int e;
-                    int32_t node;
-                    int64_t card;
-                };
-                std::vector<Exit> exits;
-                Block64 bk{};
-                for (int k = 0; k < 7; k++) {
-                    const int32_t n = slot_node[k];
-                    if (n < 0) continue;
-                    const int64_t g = t.base + n;
-                    const int32_t ch[2] = {v->left[g], v->right[g]};
-                    uint32_t w = (uint32_t)remap[v->feature[g]];
-                    for (int side = 0; side < 2; side++) {
-                        w |= code(t, ch[side]) << (fb + side * (1 + cb));
-                        if (!is_internal(v, t, ch[side])) continue;
-                        if (k < 3) slot_node[2 * k + 1 + side] = ch[side];
-                        else exits.push_back(Exit{2 * (k - 3) + side, ch[side], t.card[ch[side]]});
-                    }
-                    bk.slot[k] = Node8{v->threshold[g], w};
-                }
-                std::stable_sort(exits.begin(), exits.end(),
-                                 [](const Exit& a, const Exit& c) { return a.card > c.card; });
-                bk.child_base = exits.empty() ? 0u : (uint32_t)bl.size();
-                for (size_t r = 0; r < exits.size(); r++) {
-                    bk.ranks |= (8u | (uint32_t)r) << (4 * exits[r].e);
-                    bl.push_back(Block64{});
-                    queue.emplace_back((int32_t)(bk.child_base + r), exits[r].node);
-                }
-                bl[blk] = bk;
+            roots[ti] = (int32_t)pos[j][0];
+            for (size_t q = 0; q < tb[j].root.size(); q++) {
+                Block64 bk = tb[j].body[q];
+                const uint32_t first = bk.child_base;
+                bk.child_base = first < tb[j].root.size() ? (uint32_t)pos[j][first] : 0u;
+                if (bk.ranks == 0) bk.child_base = 0;
+                bl[(size_t)pos[j][q]] = bk;
             }
         }
-        if ((int64_t)be.top_len + (int64_t)bl.size() > INT32_MAX)
-            return fp_set_error(FP_E2BIG, "bin %d holds too many nodes", b);
         word_cursor = (int64_t)align_up((size_t)word_cursor, 16);
         be.node_base = word_cursor;
         be.deep_len = (int32_t)bl.size();
-        word_cursor += (int64_t)align_up(2 * (size_t)be.top_len, 8) + 8 * (int64_t)bl.size();
+        word_cursor += 8 * (int64_t)bl.size();
     }
     const int64_t n_words = word_cursor;
     const size_t table_off = sizeof(Header);
@@ -615,16 +615,13 @@ int pack_blocked(const fp_forest_view* v, const std::vector<TreeShape>& s, const
     memcpy(out->data() + roots_off, roots.data(), sizeof(int32_t) * (size_t)T);
     memcpy(out->data() + fmap_off, fmap.data(), sizeof(int32_t) * fmap.size());
     uint8_t* words = out->data() + nodes_off;
-    for (int32_t b = 0; b < n_bins; b++) {
-        uint8_t* bb = words + 8 * bins[b].node_base;
-        if (!tops[b].empty()) memcpy(bb, tops[b].data(), sizeof(Node16) * tops[b].size());
+    for (int32_t b = 0; b < n_bins; b++)
         if (!blocks[b].empty())
-            memcpy(bb + 8 * align_up(2 * (size_t)bins[b].top_len, 8), blocks[b].data(), sizeof(Block64) * blocks[b].size());
-    }
+            memcpy(words + 8 * bins[b].node_base, blocks[b].data(), sizeof(Block64) * blocks[b].size());
     h->bin_size = B;
     h->interleave_depth = D;
     h->n_bins = n_bins;
-    h->max_top_len = max_top;
+    h->max_top_len = 0;
     h->max_bin_trees = B;
     h->n_used_features = (int32_t)fmap.size();
     h->fmap_offset = (int64_t)fmap_off;
@@ -714,9 +711,8 @@ int verify_buffer(const uint8_t* bytes, size_t n, std::string* why) {
         if (be.first_tree != tree_cursor || be.n_trees < 1 || be.root_base != be.first_tree)
             return bad("bin %d tree range", b);
         tree_cursor += be.n_trees;
-        const int64_t top_words = blocked ? (2 * (int64_t)be.top_len + 7) / 8 * 8 : 2 * (int64_t)be.top_len;
-        const int64_t units = compact   ? top_words + be.deep_len
-                              : blocked ? top_words + 8 * (int64_t)be.deep_len
+        const int64_t units = compact   ? 2 * (int64_t)be.top_len + be.deep_len
+                              : blocked ? 8 * (int64_t)be.deep_len
                                         : (int64_t)be.top_len + be.deep_len;
         if (be.top_len < 0 || be.deep_len < 0 || be.node_base < 0 || be.node_base % (compact || blocked ? 16 : 8) ||
             be.node_base + units > N)
@@ -728,22 +724,14 @@ int verify_buffer(const uint8_t* bytes, size_t n, std::string* why) {
         for (int32_t j = 0; j < be.n_trees; j++)
             if (!ref_ok(roots[be.first_tree + j], -1)) return bad("bin %d root %d", b, j);
         if (blocked) {
-            if ((int64_t)be.top_len + be.deep_len > INT32_MAX) return bad("bin %d: too many nodes", b);
-            // top refs: forward top node, a block (entered at its slot 0) or a class
-            auto top_ref_ok = [&](int32_t r, int64_t self) {
-                return r < 0 ? (-(int64_t)r - 1) < C : r < be.top_len ? r > self : r - (int64_t)be.top_len < be.deep_len;
-            };
-            for (int32_t j = 0; j < be.n_trees; j++)
-                if (!top_ref_ok(roots[be.first_tree + j], -1)) return bad("bin %d root %d", b, j);
-            const Node8* words = reinterpret_cast<const Node8*>(bytes + h.nodes_offset) + be.node_base;
-            const Node16* top = reinterpret_cast<const Node16*>(words);
-            for (int64_t i = 0; i < be.top_len; i++) {
-                const Node16& nd = top[i];
-                if (nd.feat < 0 || nd.feat >= F || !top_ref_ok(nd.left, i) || !top_ref_ok(nd.right, i))
-                    return bad("bin %d top node %lld", b, (long long)i);
+            if (be.top_len != 0) return bad("bin %d: blocked layout with a top region", b);
+            for (int32_t j = 0; j < be.n_trees; j++) {
+                const int32_t r = roots[be.first_tree + j];
+                if (r < 0 ? (-(int64_t)r - 1) >= C : r >= be.deep_len) return bad("bin %d root %d", b, j);
             }
+            const Node8* words = reinterpret_cast<const Node8*>(bytes + h.nodes_offset) + be.node_base;
             const int fb = h.compact_fbits, cb = h.compact_cbits;
-            const Block64* blk = reinterpret_cast<const Block64*>(words + top_words);
+            const Block64* blk = reinterpret_cast<const Block64*>(words);
             for (int64_t k = 0; k < be.deep_len; k++) {
                 const Block64& bk = blk[k];
                 bool present[7] = {true, false, false, false, false, false, false};

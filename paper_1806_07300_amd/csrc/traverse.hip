@@ -202,7 +202,7 @@ __device__ int stage_group(const JobDesc& j, int group, unsigned char* smem) {
         const BinEntry& be = j.bins[b];
         const int32_t nb = (int32_t)be.node_base;
         ttab[tl] = j.layout == FP_LAYOUT_COMPACT   ? make_int4(j.roots[t], nb, be.top_len, 0)
-                   : j.layout == FP_LAYOUT_BLOCKED ? make_int4(j.roots[t], nb, be.top_len, nb + (2 * be.top_len + 7) / 8 * 8)
+                   : j.layout == FP_LAYOUT_BLOCKED ? make_int4(j.roots[t], nb, 0, 0)
                                                    : make_int4(j.roots[t], nb, (b - b_lo) * j.cap, min(be.top_len, j.cap));
     }
     if (!j.feat_lds) {
@@ -432,15 +432,15 @@ __device__ void run_tile_compact(const JobDesc& j, int nt, int tile, unsigned ch
     __syncthreads();
 }
 
-// BLOCKED layout walk.  A top node (Node16) is one step per iteration; a
-// block is fetched whole (four 16-byte loads of one 64-byte block, a single
-// cache line) and then walked for up to three levels from registers: slot 0,
-// then slot 1 or 2, then one of slots 3..6, ending in a class or an exit to a
-// child block, which the next iteration fetches.
 struct BlockRegs {
     uint4 q0, q1, q2, q3;  // child_base, ranks, (thr, w) of slots 0..6
 };
 
+// BLOCKED layout walk.  Every reference is a block of the bin (or a class).
+// A block is fetched whole -- four 16-byte loads of one 64-byte line -- and
+// walked for up to three levels from registers: slot 0, then slot 1 or 2,
+// then one of slots 3..6, ending in a class or an exit to a child block,
+// which the next iteration fetches.
 template <int K, int FMODE>
 __device__ void run_tile_blocked(const JobDesc& j, int nt, int tile, unsigned char* smem) {
     const bool feat_lds = FMODE == 2 ? (j.feat_lds != 0) : (FMODE == 1);
@@ -470,17 +470,23 @@ __device__ void run_tile_blocked(const JobDesc& j, int nt, int tile, unsigned ch
 
     const int U = rows_here * nt;
     const uint32_t rmagic = 0xFFFFFFFFu / (uint32_t)rows_here;
-    TileRows tr{j, xs, vl, fmap_l, row0, feat_lds};
-    auto le = [&](int r, uint32_t f, float thr) { return tr.x(r, f) <= thr; };
-    // per cursor: row in the tile, nb = bin base, bb = first block of the bin
-    // (words), topl = top_len
-    int32_t ref[K], rowk[K], nb[K], topl[K], bb[K];
+    // x <= thr for compacted feature f; xrow = the row's first feature in the
+    // LDS tile (or its row in the tile when features stay in memory)
+    auto le = [&](int32_t xrow, uint32_t f, float thr) {
+        const float x = feat_lds ? xs[xrow + (int32_t)f] : j.X[(row0 + xrow) * j.ld + fmap_l[f]];
+        return x <= thr;
+    };
+    // per cursor: xrow, vrow = the row's first vote counter, bb = the bin's
+    // first block (words)
+    int32_t ref[K], xrow[K], vrow[K], bb[K];
 #pragma unroll
-    for (int k = 0; k < K; k++) { ref[k] = kDone; rowk[k] = 0; nb[k] = 0; topl[k] = 0; bb[k] = 0; }
+    for (int k = 0; k < K; k++) { ref[k] = kDone; xrow[k] = 0; vrow[k] = 0; bb[k] = 0; }
     auto take = [&](int k, int r, int4 e) -> int32_t {
-        rowk[k] = r; nb[k] = e.y; topl[k] = e.z; bb[k] = e.w;
+        xrow[k] = feat_lds ? (int32_t)__umul24((uint32_t)r, (uint32_t)j.Fcp) : r;
+        vrow[k] = (int32_t)__umul24((uint32_t)r, (uint32_t)j.C);
+        bb[k] = e.y;
         if (e.x < 0) {  // the root is a leaf
-            tr.vote(r, -e.x - 1);
+            atomicAdd(&vl[vrow[k] - e.x - 1], 1);
             return kDone;
         }
         return e.x;
@@ -499,56 +505,47 @@ __device__ void run_tile_blocked(const JobDesc& j, int nt, int tile, unsigned ch
 #pragma unroll
         for (int k = 0; k < K; k++) {
             if (ref[k] < 0) continue;
-            if (ref[k] < topl[k]) {
-                g[k].q0 = *reinterpret_cast<const uint4*>(words + nb[k] + 2 * ref[k]);
-            } else {
-                const uint4* bp = reinterpret_cast<const uint4*>(words + bb[k] + 8 * (ref[k] - topl[k]));
-                g[k].q0 = bp[0]; g[k].q1 = bp[1]; g[k].q2 = bp[2]; g[k].q3 = bp[3];
-            }
+            const uint4* bp = reinterpret_cast<const uint4*>(words + bb[k] + 8 * ref[k]);
+            g[k].q0 = bp[0]; g[k].q1 = bp[1]; g[k].q2 = bp[2]; g[k].q3 = bp[3];
         }
 #pragma unroll
         for (int k = 0; k < K; k++) {
             if (ref[k] < 0) continue;
-            const uint4 q0 = g[k].q0;
+            const uint4 q0 = g[k].q0, q1 = g[k].q1, q2 = g[k].q2, q3 = g[k].q3;
             int32_t nr;
-            if (ref[k] < topl[k]) {
-                nr = le(rowk[k], q0.y, __uint_as_float(q0.x)) ? (int32_t)q0.z : (int32_t)q0.w;
+            // level 0: slot 0
+            uint32_t w = q0.w;
+            uint32_t side = le(xrow[k], w & fmask, __uint_as_float(q0.z)) ? 0u : 1u;
+            uint32_t c = (w >> (fb + side * (1 + cb))) & code_mask;
+            if (c & 1u) {
+                nr = -(int32_t)(c >> 1) - 1;
             } else {
-                const uint4 q1 = g[k].q1, q2 = g[k].q2, q3 = g[k].q3;
-                // level 0: slot 0
-                uint32_t w = q0.w;
-                uint32_t side = le(rowk[k], w & fmask, __uint_as_float(q0.z)) ? 0u : 1u;
-                uint32_t c = (w >> (fb + side * (1 + cb))) & code_mask;
+                // level 1: slot 1 + side
+                const uint32_t s1 = side;
+                w = s1 ? q1.w : q1.y;
+                float t = __uint_as_float(s1 ? q1.z : q1.x);
+                side = le(xrow[k], w & fmask, t) ? 0u : 1u;
+                c = (w >> (fb + side * (1 + cb))) & code_mask;
                 if (c & 1u) {
                     nr = -(int32_t)(c >> 1) - 1;
                 } else {
-                    // level 1: slot 1 + side
-                    const uint32_t s1 = side;
-                    w = s1 ? q1.w : q1.y;
-                    float t = __uint_as_float(s1 ? q1.z : q1.x);
-                    side = le(rowk[k], w & fmask, t) ? 0u : 1u;
+                    // level 2: slot 3 + idx, idx = 2 s1 + side
+                    const uint32_t idx = 2 * s1 + side;
+                    const uint4 qq = idx < 2 ? q2 : q3;
+                    w = (idx & 1u) ? qq.w : qq.y;
+                    t = __uint_as_float((idx & 1u) ? qq.z : qq.x);
+                    side = le(xrow[k], w & fmask, t) ? 0u : 1u;
                     c = (w >> (fb + side * (1 + cb))) & code_mask;
                     if (c & 1u) {
                         nr = -(int32_t)(c >> 1) - 1;
                     } else {
-                        // level 2: slot 3 + idx, idx = 2 s1 + side
-                        const uint32_t idx = 2 * s1 + side;
-                        const uint4 qq = idx < 2 ? q2 : q3;
-                        w = (idx & 1u) ? qq.w : qq.y;
-                        t = __uint_as_float((idx & 1u) ? qq.z : qq.x);
-                        side = le(rowk[k], w & fmask, t) ? 0u : 1u;
-                        c = (w >> (fb + side * (1 + cb))) & code_mask;
-                        if (c & 1u) {
-                            nr = -(int32_t)(c >> 1) - 1;
-                        } else {
-                            const uint32_t e = 2 * idx + side;
-                            nr = topl[k] + (int32_t)(q0.x + ((q0.y >> (4 * e)) & 7u));
-                        }
+                        const uint32_t e = 2 * idx + side;
+                        nr = (int32_t)(q0.x + ((q0.y >> (4 * e)) & 7u));
                     }
                 }
             }
             if (nr < 0) {
-                tr.vote(rowk[k], -nr - 1);
+                atomicAdd(&vl[vrow[k] - nr - 1], 1);
                 nr = kDone;
             }
             ref[k] = nr;
@@ -583,7 +580,7 @@ __device__ void run_tile_blocked(const JobDesc& j, int nt, int tile, unsigned ch
 // needs 4 waves per SIMD, so no variant gets more than 128 VGPRs.
 template <int K, int LAYOUT>
 struct MinWaves {
-    static constexpr int value = LAYOUT == FP_LAYOUT_PACKED   ? (K <= 4 ? 8 : 4)
+    static constexpr int value = LAYOUT == FP_LAYOUT_PACKED    ? (K <= 4 ? 8 : 4)
                                  : LAYOUT == FP_LAYOUT_COMPACT ? (K <= 2 ? 8 : 4)
                                                                : (K == 1 ? 8 : 4);
 };

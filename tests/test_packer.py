@@ -312,85 +312,74 @@ def test_blocked_layout_invariants():
     """Each block holds a complete three-level subtree of one tree (slot s has
     its children at 2s+1 and 2s+2); every internal node is stored exactly once;
     a block's child blocks are contiguous, after it, and in descending order of
-    training cardinality; the top region equals the PACKED layout's."""
+    training cardinality; blocks whose root has depth <= D come first,
+    level-major and tree-minor (Bin at block granularity)."""
     from packed_format import blocked_bin
     w = synth.image(n_train=6000, n_trees=8)
     f = w.forest()
-    a = decode(fp.fp_packed_host_bytes(fp.fp_pack_forest(f, bin_size=4, interleave_depth=3)))
-    c = decode(fp.fp_packed_host_bytes(fp.fp_pack_forest(f, layout=fp.FP_LAYOUT_BLOCKED, bin_size=4,
-                                                          interleave_depth=3)))
-    h = c["h"]
-    fb, cb = h["compact_fbits"], h["compact_cbits"]
-    assert np.array_equal(a["fmap"], c["fmap"])
-    n_block_nodes = 0
-    for ba, bc in zip(a["bins"], c["bins"]):
-        tl = int(bc["top_len"])
-        assert ba["top_len"] == tl
-        top, blocks = blocked_bin(c, bc)
-        assert bc["node_base"] % 16 == 0
-        bn = a["nodes"][ba["node_base"]:ba["node_base"] + tl]
-        assert np.array_equal(top["thr"], bn["thr"]) and np.array_equal(top["feat"], bn["feat"])
-        for side in ("left", "right"):  # refs into the top region or to classes agree
-            same = (bn[side] < tl)
-            assert np.array_equal(top[side][same], bn[side][same])
-            assert (top[side][~same] >= tl).all()
-        seen_blocks = set()
-        for j in range(int(bc["n_trees"])):
-            t = int(bc["first_tree"]) + j
-            off = f.tree_node_offset[t]
-            stack = [(int(c["roots"][bc["root_base"] + j]), 0, "top")]
-            while stack:
-                ref, orig, kind = stack.pop()
-                if ref < 0:
-                    assert f.feature[off + orig] < 0 and -ref - 1 == f.leaf_class[off + orig]
+    for B, D in ((4, 3), (8, 0), (3, 7)):
+        c = decode(fp.fp_packed_host_bytes(fp.fp_pack_forest(f, layout=fp.FP_LAYOUT_BLOCKED, bin_size=B,
+                                                              interleave_depth=D)))
+        h = c["h"]
+        fb, cb = h["compact_fbits"], h["compact_cbits"]
+        n_block_nodes = 0
+        for bc in c["bins"]:
+            assert bc["top_len"] == 0 and bc["node_base"] % 16 == 0
+            _, blocks = blocked_bin(c, bc)
+            owner = {}  # block -> (tree j, block level)
+            for j in range(int(bc["n_trees"])):
+                t = int(bc["first_tree"]) + j
+                off = f.tree_node_offset[t]
+                root = int(c["roots"][bc["root_base"] + j])
+                if root < 0:
+                    assert f.feature[off] < 0 and -root - 1 == f.leaf_class[off]
                     continue
-                assert f.feature[off + orig] >= 0
-                if ref < tl:
-                    nd = top[ref]
-                    assert nd["thr"] == f.threshold[off + orig]
-                    stack.append((int(nd["left"]), f.left[off + orig], "top"))
-                    stack.append((int(nd["right"]), f.right[off + orig], "top"))
-                    continue
-                k = ref - tl
-                assert k not in seen_blocks
-                seen_blocks.add(k)
-                bk = blocks[k]
-                slot_orig = {0: orig}
-                exits = []
-                for s in range(7):
-                    if s not in slot_orig:
-                        assert bk["slot"]["w"][s] == 0 and bk["slot"]["thr"][s] == 0
-                        continue
-                    o = slot_orig[s]
-                    wd = int(bk["slot"]["w"][s])
-                    assert c["fmap"][wd & ((1 << fb) - 1)] == f.feature[off + o]
-                    assert bk["slot"]["thr"][s] == f.threshold[off + o]
-                    n_block_nodes += 1
-                    for side, ch in enumerate((f.left[off + o], f.right[off + o])):
-                        code = (wd >> (fb + side * (1 + cb))) & ((2 << cb) - 1)
-                        if f.feature[off + ch] < 0:
-                            assert code == 1 | (f.leaf_class[off + ch] << 1)
-                        elif s < 3:
-                            assert code == 0
-                            slot_orig[2 * s + 1 + side] = ch
-                        else:
-                            assert code == 0
-                            e = 2 * (s - 3) + side
-                            rank = (int(bk["ranks"]) >> (4 * e)) & 15
-                            assert rank & 8
-                            exits.append((rank & 7, ch))
-                exits.sort()
-                assert [r for r, _ in exits] == list(range(len(exits)))
-                cards = [f.cardinality[off + ch] for _, ch in exits]
-                assert cards == sorted(cards, reverse=True)
-                for r, ch in exits:
-                    child = int(bk["child_base"]) + r
-                    assert child > k
-                    stack.append((tl + child, ch, "block"))
-        assert seen_blocks == set(range(int(bc["deep_len"])))
-    n_internal = int((f.feature >= 0).sum())
-    n_top = int(sum(int(b["top_len"]) for b in c["bins"]))
-    assert n_block_nodes + n_top == n_internal and n_block_nodes > 1000
+                stack = [(root, 0, 0)]
+                while stack:
+                    k, orig, level = stack.pop()
+                    assert k not in owner
+                    owner[k] = (j, level)
+                    assert f.depth[off + orig] == 3 * level
+                    bk = blocks[k]
+                    slot_orig = {0: orig}
+                    exits = []
+                    for s in range(7):
+                        if s not in slot_orig:
+                            assert bk["slot"]["w"][s] == 0 and bk["slot"]["thr"][s] == 0
+                            continue
+                        o = slot_orig[s]
+                        wd = int(bk["slot"]["w"][s])
+                        assert c["fmap"][wd & ((1 << fb) - 1)] == f.feature[off + o]
+                        assert bk["slot"]["thr"][s] == f.threshold[off + o]
+                        n_block_nodes += 1
+                        for side, ch in enumerate((f.left[off + o], f.right[off + o])):
+                            code = (wd >> (fb + side * (1 + cb))) & ((2 << cb) - 1)
+                            if f.feature[off + ch] < 0:
+                                assert code == 1 | (f.leaf_class[off + ch] << 1)
+                            elif s < 3:
+                                assert code == 0
+                                slot_orig[2 * s + 1 + side] = ch
+                            else:
+                                assert code == 0
+                                rank = (int(bk["ranks"]) >> (4 * (2 * (s - 3) + side))) & 15
+                                assert rank & 8
+                                exits.append((rank & 7, ch))
+                    exits.sort()
+                    assert [r for r, _ in exits] == list(range(len(exits)))
+                    cards = [f.cardinality[off + ch] for _, ch in exits]
+                    assert cards == sorted(cards, reverse=True)
+                    for r, ch in exits:
+                        child = int(bk["child_base"]) + r
+                        assert child > k
+                        stack.append((child, ch, level + 1))
+            assert set(owner) == set(range(int(bc["deep_len"])))
+            # interleaved prefix: level-major, tree-minor; then tree by tree
+            order = [owner[k] for k in range(int(bc["deep_len"]))]
+            n_front = sum(1 for _, lv in order if lv <= D // 3)
+            front, rest = order[:n_front], order[n_front:]
+            assert all(lv <= D // 3 for _, lv in front) and front == sorted(front, key=lambda x: (x[1], x[0]))
+            assert all(lv > D // 3 for _, lv in rest) and [j for j, _ in rest] == sorted(j for j, _ in rest)
+        assert n_block_nodes == int((f.feature >= 0).sum())
 
 
 def test_blocked_rejects_bad_bytes(small_forest):
@@ -415,7 +404,7 @@ def test_blocked_verifier_catches_structural_faults(small_forest):
     fb, cb = h["compact_fbits"], h["compact_cbits"]
     base = h["nodes_offset"] + 8 * (int(be["node_base"]) + (2 * int(be["top_len"]) + 7) // 8 * 8)
     blocks = np.frombuffer(good.tobytes(), BLOCK, count=int(be["deep_len"]), offset=base)
-    k = int(np.nonzero(blocks["ranks"])[0][1])  # a block past the first with an exit
+    k = int(np.nonzero(blocks["ranks"])[0][8])  # a block with exits, at least 8 blocks in
     kl = int(np.nonzero(blocks["slot"]["w"][:, 6] == 0)[0][0])  # a block whose last slot is empty
 
     def planted(offset, dtype, value):
