@@ -204,7 +204,8 @@ void fp_packed_free(fp_packed *p);
  * Launch parameters of the traversal kernels (the GPU form of assigning bins
  * to workers, Sec. III, and of Bin+ round-robin evaluation, Sec. III-B).
  *   rows_per_block  observations per workgroup (packed layouts; 1..4096)
- *   cursors         trees a lane walks concurrently, round-robin (1, 2, 4, 8)
+ *   cursors         trees a lane walks concurrently, round-robin (1, 2, 4, 8);
+ *                   BLOCKED walks one block per lane and ignores it
  *   tree_groups     bins are split into this many groups, each group handled
  *                   by its own workgroups (votes then merge with atomics);
  *                   0: one group
@@ -256,10 +257,11 @@ int fp_predict_tuned(const fp_packed *p, const fp_tune *tune, const float *X_dev
 /*
  * Sec. III-A chooses the stripe width B and the interleave depth D with a
  * design experiment on the target processor (Fig. 2).  fp_autotune runs that
- * experiment on the GPU: it packs the forest with candidate (B, D), times
- * candidate launch mappings (observations per workgroup, cursors per lane,
- * workgroup size, tree groups) on a sample of the caller's rows with HIP
- * events, and returns the fastest combination.  Votes are never changed by
+ * experiment on the GPU: it packs the forest with candidate layouts (PACKED,
+ * COMPACT, BLOCKED) and (B, D), times candidate launch mappings
+ * (observations per workgroup, cursors per lane, workgroup size, tree
+ * groups, refill lanes) on a sample of the caller's rows with HIP events,
+ * and returns the fastest combination.  Votes are never changed by
  * any candidate.  Results are cached per (forest fingerprint, sample size,
  * options) for the life of the process.
  *
@@ -282,7 +284,7 @@ typedef struct fp_autotune_opts {
 } fp_autotune_opts;
 
 typedef struct fp_autotune_result {
-    fp_pack_opts pack;      /* best layout (PACKED or COMPACT), bin size, interleave depth */
+    fp_pack_opts pack;      /* best layout (PACKED, COMPACT or BLOCKED), bin size, interleave depth */
     fp_tune tune;           /* best launch parameters */
     double best_ms;         /* time of one launch over the sample, best candidate */
     double default_ms;      /* same, library defaults (B = T, D = 4) */

@@ -192,10 +192,12 @@ extern "C" int fp_autotune(const fp_forest_view* forest, const float* X, int64_t
                 }
         // pass 2: packing (layout, bin size, interleave depth)
         std::set<std::tuple<int, int, int>> tried{{FP_LAYOUT_PACKED, T, 4}};
-        for (int L : {FP_LAYOUT_PACKED, FP_LAYOUT_COMPACT})
+        for (int L : {FP_LAYOUT_PACKED, FP_LAYOUT_COMPACT, FP_LAYOUT_BLOCKED})
             for (int B : {T, 64, 16}) {
                 if (B > T) continue;
                 for (int D = 0; D <= std::min(7, max_depth); D++) {
+                    // BLOCKED interleaves whole blocks (three levels): only D / 3 matters
+                    if (L == FP_LAYOUT_BLOCKED && D % 3) continue;
                     if (!tried.insert(std::make_tuple(L, B, D)).second) continue;
                     rc = use_pack(L, B, D);
                     if (rc == FP_E2BIG) continue;  // the compact encoding does not fit this forest
@@ -224,6 +226,14 @@ extern "C" int fp_autotune(const fp_forest_view* forest, const float* X, int64_t
                 rc = try_tune(t);
                 if (rc) return rc;
             }
+        // pass 4: how many idle lanes a wavefront waits for before refilling
+        const fp_tune mapped = best_t;
+        for (int rl : {4, 8, 32, 48}) {
+            fp_tune t = mapped;
+            t.refill_lanes = rl;
+            rc = try_tune(t);
+            if (rc) return rc;
+        }
         out->pack = fp_pack_opts{best_L, best_B, best_D, 0};
         out->tune = best_t;
         out->best_ms = best;

@@ -160,6 +160,37 @@ __device__ __forceinline__ void refill(int32_t (&ref)[K], int32_t* pool, int U, 
     }
 }
 
+// Copies the used feature columns of tile rows [row0, row0 + rows) into LDS
+// (row-major, row stride Fcp), clears the tile's vote counters and the unit
+// pool, then synchronises.  Element i = r * Fc + c goes to thread i mod
+// blockDim, which steps (r, c) and the row pointer incrementally.
+__device__ __forceinline__ void stage_tile(const JobDesc& j, float* xs, int32_t* vl, int32_t* pool, int64_t row0,
+                                           int rows, bool feat_lds) {
+    const int tid = threadIdx.x, bd = blockDim.x;
+    if (feat_lds) {
+        const int Fc = j.Fc;
+        const int dq = bd / Fc, dc = bd - dq * Fc;
+        int r = tid / Fc, c = tid - r * Fc;
+        const float* xrow = j.X + (row0 + r) * j.ld;
+        const int64_t dld = (int64_t)dq * j.ld;
+#pragma unroll 4
+        while (r < rows) {
+            xs[r * j.Fcp + c] = xrow[j.fmap[c]];
+            r += dq;
+            xrow += dld;
+            c += dc;
+            if (c >= Fc) {
+                c -= Fc;
+                r += 1;
+                xrow += j.ld;
+            }
+        }
+    }
+    for (int i = tid; i < rows * j.C; i += bd) vl[i] = 0;
+    if (tid == 0) *pool = 0;
+    __syncthreads();
+}
+
 // A tile's observations as the walks see them: feature f of tile row r
 // (staged in LDS, or read from memory through the feature map) and the LDS
 // vote counters of row r.  Row offsets use 24-bit multiplies (full rate;
@@ -227,16 +258,7 @@ __device__ void run_tile(const JobDesc& j, int nt, int tile, unsigned char* smem
 
     const int64_t row0 = (int64_t)tile * j.R;
     const int rows_here = (int)min<int64_t>(j.R, j.n_rows - row0);
-    if (feat_lds) {
-        const int total = rows_here * j.Fc;
-        for (int i = tid; i < total; i += bd) {
-            const int rr = i / j.Fc, c = i - rr * j.Fc;
-            xs[rr * j.Fcp + c] = j.X[(row0 + rr) * j.ld + j.fmap[c]];
-        }
-    }
-    for (int i = tid; i < rows_here * j.C; i += bd) vl[i] = 0;
-    if (tid == 0) *pool = 0;
-    __syncthreads();
+    stage_tile(j, xs, vl, pool, row0, rows_here, feat_lds);
 
     const int U = rows_here * nt;
     const uint32_t rmagic = 0xFFFFFFFFu / (uint32_t)rows_here;
@@ -323,16 +345,7 @@ __device__ void run_tile_compact(const JobDesc& j, int nt, int tile, unsigned ch
 
     const int64_t row0 = (int64_t)tile * j.R;
     const int rows_here = (int)min<int64_t>(j.R, j.n_rows - row0);
-    if (feat_lds) {
-        const int total = rows_here * j.Fc;
-        for (int i = tid; i < total; i += bd) {
-            const int rr = i / j.Fc, c = i - rr * j.Fc;
-            xs[rr * j.Fcp + c] = j.X[(row0 + rr) * j.ld + j.fmap[c]];
-        }
-    }
-    for (int i = tid; i < rows_here * j.C; i += bd) vl[i] = 0;
-    if (tid == 0) *pool = 0;
-    __syncthreads();
+    stage_tile(j, xs, vl, pool, row0, rows_here, feat_lds);
 
     const int U = rows_here * nt;
     const uint32_t rmagic = 0xFFFFFFFFu / (uint32_t)rows_here;
@@ -454,19 +467,11 @@ __device__ void run_tile_blocked(const JobDesc& j, int nt, int tile, unsigned ch
     const int lane = lane_id();
     const int fb = j.fbits, cb = j.cbits;
     const uint32_t fmask = (1u << fb) - 1u, code_mask = (2u << cb) - 1u;
+    const uint32_t sh_l = (uint32_t)fb, sh_r = (uint32_t)(fb + 1 + cb);  // where the left / right codes start
 
     const int64_t row0 = (int64_t)tile * j.R;
     const int rows_here = (int)min<int64_t>(j.R, j.n_rows - row0);
-    if (feat_lds) {
-        const int total = rows_here * j.Fc;
-        for (int i = tid; i < total; i += bd) {
-            const int rr = i / j.Fc, c = i - rr * j.Fc;
-            xs[rr * j.Fcp + c] = j.X[(row0 + rr) * j.ld + j.fmap[c]];
-        }
-    }
-    for (int i = tid; i < rows_here * j.C; i += bd) vl[i] = 0;
-    if (tid == 0) *pool = 0;
-    __syncthreads();
+    stage_tile(j, xs, vl, pool, row0, rows_here, feat_lds);
 
     const int U = rows_here * nt;
     const uint32_t rmagic = 0xFFFFFFFFu / (uint32_t)rows_here;
@@ -513,6 +518,33 @@ __device__ void run_tile_blocked(const JobDesc& j, int nt, int tile, unsigned ch
             if (ref[k] < 0) continue;
             const uint4 q0 = g[k].q0, q1 = g[k].q1, q2 = g[k].q2, q3 = g[k].q3;
             int32_t nr;
+            if (feat_lds) {
+                // All seven split tests at once (absent slots are zero words:
+                // feature 0, harmless), packed into a mask of sides (bit s set
+                // = slot s goes right); the path through the three levels then
+                // reads the mask, so the seven LDS reads issue together, ahead
+                // of any branch: one LDS round trip per block.
+                const uint32_t wv[7] = {q0.w, q1.y, q1.w, q2.y, q2.w, q3.y, q3.w};
+                const uint32_t tv[7] = {q0.z, q1.x, q1.z, q2.x, q2.z, q3.x, q3.z};
+                uint32_t gm = 0;
+#pragma unroll
+                for (int sl = 0; sl < 7; sl++)
+                    gm |= (xs[xrow[k] + (int32_t)(wv[sl] & fmask)] <= __uint_as_float(tv[sl]) ? 0u : 1u) << sl;
+                const uint32_t side0 = gm & 1u;
+                const uint32_t c0 = (wv[0] >> (side0 ? sh_r : sh_l)) & code_mask;
+                const uint32_t side1 = (gm >> (1 + side0)) & 1u;
+                const uint32_t w1 = side0 ? wv[2] : wv[1];
+                const uint32_t c1 = (w1 >> (side1 ? sh_r : sh_l)) & code_mask;
+                const uint32_t idx = 2 * side0 + side1;
+                const uint32_t side2 = (gm >> (3 + idx)) & 1u;
+                const uint32_t w2 = side0 ? (side1 ? wv[6] : wv[5]) : (side1 ? wv[4] : wv[3]);
+                const uint32_t c2 = (w2 >> (side2 ? sh_r : sh_l)) & code_mask;
+                const uint32_t e = 2 * idx + side2;
+                int32_t r = (int32_t)(q0.x + ((q0.y >> (4 * e)) & 7u));
+                r = (c2 & 1u) ? ~(int32_t)(c2 >> 1) : r;
+                r = (c1 & 1u) ? ~(int32_t)(c1 >> 1) : r;
+                nr = (c0 & 1u) ? ~(int32_t)(c0 >> 1) : r;
+            } else {
             // level 0: slot 0
             uint32_t w = q0.w;
             uint32_t side = le(xrow[k], w & fmask, __uint_as_float(q0.z)) ? 0u : 1u;
@@ -543,6 +575,7 @@ __device__ void run_tile_blocked(const JobDesc& j, int nt, int tile, unsigned ch
                         nr = (int32_t)(q0.x + ((q0.y >> (4 * e)) & 7u));
                     }
                 }
+            }
             }
             if (nr < 0) {
                 atomicAdd(&vl[vrow[k] - nr - 1], 1);
@@ -625,7 +658,7 @@ __global__ __launch_bounds__(1024) void batched_kernel(const JobDesc* __restrict
         if (j.layout == FP_LAYOUT_COMPACT)
             for (int tile = w.tile_begin; tile < w.tile_end; tile++) run_tile_compact<K, 2>(j, nt, tile, smem);
         else if (j.layout == FP_LAYOUT_BLOCKED)
-            for (int tile = w.tile_begin; tile < w.tile_end; tile++) run_tile_blocked<(K > 2 ? 2 : K), 2>(j, nt, tile, smem);
+            for (int tile = w.tile_begin; tile < w.tile_end; tile++) run_tile_blocked<1, 2>(j, nt, tile, smem);
         else
             for (int tile = w.tile_begin; tile < w.tile_end; tile++) run_tile<K, 2>(j, nt, tile, smem);
     }
@@ -685,12 +718,16 @@ const void* packed_fn_fm(int fmode) {
     return fmode == 0 ? packed_fn<K, 0, L>() : packed_fn<K, 1, L>();
 }
 
+// A BLOCKED walk keeps one block in flight per lane whatever `cursors` says:
+// a second block's 16 registers halve the waves a SIMD holds, which costs more
+// than the overlap gains.
 const void* pick_packed(int K, int fmode, int layout) {
+    if (K != 1 && K != 2 && K != 4 && K != 8) return nullptr;
+    if (layout == FP_LAYOUT_BLOCKED) return packed_fn_fm<1, FP_LAYOUT_BLOCKED>(fmode);
 #define FP_PICK(KK)                                                                     \
     if (K == KK)                                                                        \
-        return layout == FP_LAYOUT_COMPACT   ? packed_fn_fm<KK, FP_LAYOUT_COMPACT>(fmode) \
-               : layout == FP_LAYOUT_BLOCKED ? packed_fn_fm<KK, FP_LAYOUT_BLOCKED>(fmode) \
-                                             : packed_fn_fm<KK, FP_LAYOUT_PACKED>(fmode);
+        return layout == FP_LAYOUT_COMPACT ? packed_fn_fm<KK, FP_LAYOUT_COMPACT>(fmode) \
+                                           : packed_fn_fm<KK, FP_LAYOUT_PACKED>(fmode);
     FP_PICK(1)
     FP_PICK(2)
     FP_PICK(4)

@@ -128,6 +128,38 @@ def test_batched_workload_64_forests():
         jobs.append({"forest": f, "X": X, "Xd": Xd, "packed": p, "votes": votes, "cls": cls})
     plan = fp.fp_plan_create([(j["packed"], j["Xd"], j["votes"], j["cls"]) for j in jobs],
                              block_threads=threads, cursors=cursors)
+    # timing for the record: the graph replay vs every forest's naive-layout launch in turn
+    rows = sum(len(j["X"]) for j in jobs)
+    fp.fp_predict_batched(plan)
+    torch.cuda.synchronize()
+    t0, t1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    t0.record()
+    for _ in range(5):
+        fp.fp_predict_batched(plan)
+    t1.record()
+    torch.cuda.synchronize()
+    ms = t0.elapsed_time(t1) / 5
+    naive = [fp.fp_pack_forest(j["forest"], layout=fp.FP_LAYOUT_NAIVE) for j in jobs]
+    for q in naive:
+        fp.fp_packed_upload(q)
+    nv = [torch.empty_like(j["votes"]) for j in jobs]
+    nc = [torch.empty_like(j["cls"]) for j in jobs]
+    run_naive = lambda: [fp.fp_predict_tuned(q, {"block_threads": 256}, j["Xd"], v, c)
+                         for q, j, v, c in zip(naive, jobs, nv, nc)]
+    run_naive()
+    torch.cuda.synchronize()
+    t0.record()
+    run_naive()
+    t1.record()
+    torch.cuda.synchronize()
+    ms_naive = t0.elapsed_time(t1)
+    layouts = [fp.fp_packed_info_get(j["packed"])["layout"] for j in jobs]
+    print(f"\n[batched] 64 forests, {rows} rows: one graph launch {ms:.3f} ms = {rows / ms / 1e3:.2f} M obs/s; "
+          f"naive layout, 64 launches {ms_naive:.3f} ms = {rows / ms_naive / 1e3:.2f} M obs/s "
+          f"({ms_naive / ms:.2f}x); layouts chosen {np.bincount(layouts, minlength=4).tolist()}", flush=True)
+    for i, j in enumerate(jobs):
+        if len(j["X"]):
+            assert torch.equal(nv[i], j["votes"]), f"forest {i}: naive votes differ"
     rng = np.random.default_rng(3)
     for replay in range(2):
         for j in jobs:

@@ -1,7 +1,7 @@
 """The full-size tabular workload (28 features, 1,024 trees grown on 1,000,000
-rows, 10,000,000 rows predicted, packed bins of 16 trees) on the GPU, checked
-against the CPU checker on sampled rows and against the naive layout on every
-row.  Training the forest takes minutes of host CPU, so the test runs only
+rows, 10,000,000 rows predicted, bins of 16 trees, PACKED and BLOCKED layouts)
+on the GPU, checked against the CPU checker on sampled rows and against the
+naive layout on every row.  Training the forest takes minutes of host CPU, so the test runs only
 with FP_FULL_TABULAR=1 (it prints training progress)."""
 import os
 import time
@@ -35,9 +35,14 @@ def test_tabular_full_size():
     Xd = torch.from_numpy(X).cuda()
     n = len(X)
     out = {}
-    for name, kw, tune in (("packed", {"bin_size": 16, "interleave_depth": 3},
-                            {"rows_per_block": 32, "cursors": 4, "block_threads": 1024}),
-                           ("naive", {"layout": fp.FP_LAYOUT_NAIVE}, {"block_threads": 256})):
+    runs = (("packed", {"bin_size": 16, "interleave_depth": 3},
+             {"rows_per_block": 32, "cursors": 4, "block_threads": 1024}),
+            ("blocked", {"layout": fp.FP_LAYOUT_BLOCKED, "bin_size": 16, "interleave_depth": 3},
+             {"rows_per_block": 256, "cursors": 1, "block_threads": 1024, "refill_lanes": 32}),
+            ("blocked-r64", {"layout": fp.FP_LAYOUT_BLOCKED, "bin_size": 16, "interleave_depth": 3},
+             {"rows_per_block": 64, "cursors": 1, "block_threads": 1024, "refill_lanes": 32}),
+            ("naive", {"layout": fp.FP_LAYOUT_NAIVE}, {"block_threads": 256}))
+    for name, kw, tune in runs:
         p = fp.fp_pack_forest(f, **kw)
         fp.fp_packed_upload(p)
         votes = torch.empty((n, 2), dtype=torch.int32, device="cuda")
@@ -56,7 +61,8 @@ def test_tabular_full_size():
         del p
     v, c = out["packed"]
     assert (v.sum(1) == f.n_trees).all()
-    assert np.array_equal(v, out["naive"][0]) and np.array_equal(c, out["naive"][1])
+    for name in ("packed", "blocked", "blocked-r64"):
+        assert np.array_equal(out[name][0], out["naive"][0]) and np.array_equal(out[name][1], out["naive"][1]), name
     rows = np.unique(np.concatenate([[0, n - 1], np.random.default_rng(11).integers(0, n, 10_000)]))
     wv, wc = oracle.predict(f, X[rows])
     assert np.array_equal(v[rows], wv) and np.array_equal(c[rows], wc)
