@@ -117,12 +117,14 @@ enum {
      * classes and in-tree distances to fit 32 bits (FP_E2BIG otherwise);
      * line_align is ignored. */
     FP_LAYOUT_COMPACT = 2,
-    /* Every tree cut into 64-byte blocks, each a complete three-level
-     * subtree (7 node slots + a header): one fetch serves up to three steps
-     * of a walk.  A block's child blocks are stored together, most-visited
-     * first by training cardinality (Stat at block granularity).  Bin
-     * interleaving moves to blocks: the blocks whose root node has depth
-     * <= interleave_depth, of all the bin's trees, come first, level-major.
+    /* Every tree cut into blocks, each a complete three-level subtree (7
+     * node slots + a header): one fetch serves up to three steps of a walk.
+     * A block takes 48 bytes when a node's feature and child codes fit 19
+     * bits (feature bits + 2 x (1 + max(class bits, 3))), else 64 bytes.
+     * A block's child blocks are stored together, most-visited first by
+     * training cardinality (Stat at block granularity).  Bin interleaving
+     * moves to blocks: the blocks whose root node has depth <=
+     * interleave_depth, of all the bin's trees, come first, level-major.
      * Needs feature and class fields to fit 32 bits (FP_E2BIG otherwise);
      * line_align is ignored. */
     FP_LAYOUT_BLOCKED = 3

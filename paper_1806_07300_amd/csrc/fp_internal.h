@@ -32,7 +32,7 @@ namespace fp {
 // internal children are tree-local ids.
 // ---------------------------------------------------------------------------
 constexpr uint64_t kMagic = 0x314B4341504D5046ull;  // "FPMPACK1"
-constexpr uint32_t kFormatVersion = 2;
+constexpr uint32_t kFormatVersion = 3;
 constexpr size_t kSectionAlign = 256;
 
 struct alignas(16) Node16 {
@@ -79,6 +79,21 @@ struct Block64 {
 };
 static_assert(sizeof(Block64) == 64, "block is 64 bytes");
 
+// The 48-byte form of a BLOCKED block, used when a node word fits 19 bits.
+// Bits [19 s, 19 s + 19) of words[0..4] (136 bits) are the word of slot s:
+// feature in bits [0, fb), then a left and a right code of (1 + P) bits,
+// P = max(cb, 3): bit 0 set = class child (class in the other P bits); clear
+// = internal child, whose other P bits are 0 for s < 3 (the child is slot
+// 2s+1+side) and the exit rank for s >= 3 (the child is block child_base +
+// rank).  Bits [8, 32) of words[4] hold child_base; thr[s] follows.
+struct Block48 {
+    uint32_t words[5];
+    float thr[7];
+};
+static_assert(sizeof(Block48) == 48, "block is 48 bytes");
+constexpr int kBlock48WordBits = 19;
+constexpr uint32_t kBlock48MaxChildBase = (1u << 24) - 1;
+
 struct BinEntry {
     int64_t node_base;   // first node of the bin in the node array
     int32_t first_tree;
@@ -109,7 +124,9 @@ struct Header {
     double expected_depth;  // mean over trees of the cardinality-weighted leaf depth
     int32_t compact_fbits;  // COMPACT, BLOCKED: feature bits fb of a node word
     int32_t compact_cbits;  // COMPACT, BLOCKED: class bits cb
-    uint8_t pad[256 - 152];
+    int32_t block_bytes;    // BLOCKED: 48 or 64
+    int32_t pad1;
+    uint8_t pad[256 - 160];
 };
 static_assert(sizeof(Header) == 256, "header is 256 bytes");
 
@@ -150,6 +167,8 @@ struct JobDesc {
     int32_t layout;            // FP_LAYOUT_PACKED, FP_LAYOUT_COMPACT or FP_LAYOUT_BLOCKED
     int32_t fbits, cbits;      // COMPACT / BLOCKED field widths
     int32_t refill_min;        // idle lanes of a wavefront that trigger a refill
+    int32_t block_bytes;       // BLOCKED: 48 or 64
+    int32_t pad3;
 };
 
 // One entry of the batched work list: tiles [tile_begin, tile_end) of job

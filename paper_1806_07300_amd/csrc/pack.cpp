@@ -35,6 +35,7 @@ using fp::BinEntry;
 using fp::Header;
 using fp::Node16;
 using fp::Node8;
+using fp::Block48;
 using fp::Block64;
 
 // ---------------------------------------------------------------------------
@@ -478,8 +479,9 @@ int pack_packed(const fp_forest_view* v, const std::vector<TreeShape>& s, const 
 }
 
 
-// BLOCKED layout: every internal node lives in a 64-byte block holding a
-// complete three-level subtree (see Block64); there is no Node16 region.
+// BLOCKED layout: every internal node lives in a block holding a complete
+// three-level subtree (Block48 when a node word fits 19 bits, else Block64);
+// there is no Node16 region.
 // Each tree's blocks form a tree of their own, built breadth-first; a block's
 // child blocks are one contiguous group ordered by training cardinality
 // (most samples first, ties in exit order).  Bin interleaving works on
@@ -502,12 +504,28 @@ int pack_blocked(const fp_forest_view* v, const std::vector<TreeShape>& s, const
         return fp_set_error(FP_E2BIG, "blocked layout: %d feature bits and %d classes do not fit a 32-bit node word",
                             fb, v->n_classes);
     const int32_t last_interleaved_level = D / 3;
+    const int P = std::max(cb, 3);
+    // 48-byte blocks when a node word fits 19 bits and every bin has fewer
+    // than 2^24 blocks (checked below; the packing restarts in 64-byte form)
+    bool use48 = fb + 2 * (1 + P) <= kBlock48WordBits;
 
     // One tree's blocks in breadth-first order: the subtree root node of each
-    // block, its level, the bfs index of its first child block and its exits.
+    // block, its level, and its slots; child blocks are found by bfs index.
+    struct Slot {
+        bool present = false;
+        float thr = 0.0f;
+        uint32_t feat = 0;
+        uint32_t kind[2] = {0, 0};  // 0 internal, 1 class
+        uint32_t pay[2] = {0, 0};   // class, or exit rank of a bottom slot
+    };
+    struct BlockIR {
+        Slot slot[7];
+        uint32_t first_child = 0;  // bfs index of the first child block
+        uint32_t n_children = 0;
+    };
     struct TreeBlocks {
-        std::vector<int32_t> root, level, first_child;
-        std::vector<Block64> body;  // child_base holds the bfs index of the first child until placed
+        std::vector<int32_t> root, level;
+        std::vector<BlockIR> body;
     };
     auto build_tree = [&](const TreeShape& t, TreeBlocks* tb) {
         tb->root.assign(1, 0);
@@ -517,43 +535,90 @@ int pack_blocked(const fp_forest_view* v, const std::vector<TreeShape>& s, const
             for (int k = 0; k < 7; k++) slot_node[k] = -1;
             slot_node[0] = tb->root[q];
             struct Exit {
-                int e;
+                int slot, side;
                 int32_t node;
                 int64_t card;
             };
             std::vector<Exit> exits;
-            Block64 bk{};
+            BlockIR bk;
             for (int k = 0; k < 7; k++) {
                 const int32_t n = slot_node[k];
                 if (n < 0) continue;
                 const int64_t g = t.base + n;
                 const int32_t ch[2] = {v->left[g], v->right[g]};
-                uint32_t w = (uint32_t)remap[v->feature[g]];
+                Slot& sl = bk.slot[k];
+                sl.present = true;
+                sl.thr = v->threshold[g];
+                sl.feat = (uint32_t)remap[v->feature[g]];
                 for (int side = 0; side < 2; side++) {
                     const int64_t gc = t.base + ch[side];
-                    const uint32_t c = v->feature[gc] >= 0 ? 0u : 1u | ((uint32_t)v->leaf_class[gc] << 1);
-                    w |= c << (fb + side * (1 + cb));
-                    if (v->feature[gc] < 0) continue;
-                    if (k < 3) slot_node[2 * k + 1 + side] = ch[side];
-                    else exits.push_back(Exit{2 * (k - 3) + side, ch[side], t.card[ch[side]]});
+                    if (v->feature[gc] < 0) {
+                        sl.kind[side] = 1;
+                        sl.pay[side] = (uint32_t)v->leaf_class[gc];
+                    } else if (k < 3) {
+                        slot_node[2 * k + 1 + side] = ch[side];
+                    } else {
+                        exits.push_back(Exit{k, side, ch[side], t.card[ch[side]]});
+                    }
                 }
-                bk.slot[k] = Node8{v->threshold[g], w};
             }
             std::stable_sort(exits.begin(), exits.end(), [](const Exit& a, const Exit& c) { return a.card > c.card; });
-            bk.child_base = (uint32_t)tb->root.size();  // bfs index of the first child, rewritten when placed
+            bk.first_child = (uint32_t)tb->root.size();
+            bk.n_children = (uint32_t)exits.size();
             for (size_t r = 0; r < exits.size(); r++) {
-                bk.ranks |= (8u | (uint32_t)r) << (4 * exits[r].e);
+                bk.slot[exits[r].slot].pay[exits[r].side] = (uint32_t)r;
                 tb->root.push_back(exits[r].node);
                 tb->level.push_back(tb->level[q] + 1);
             }
             tb->body.push_back(bk);
         }
     };
+    // encoders: child_base is the final index of the block's first child
+    auto encode64 = [&](const BlockIR& bk, uint32_t child_base, Block64* out) {
+        *out = Block64{};
+        out->child_base = bk.n_children ? child_base : 0u;
+        for (int k = 0; k < 7; k++) {
+            const Slot& sl = bk.slot[k];
+            if (!sl.present) continue;
+            uint32_t w = sl.feat;
+            for (int side = 0; side < 2; side++) {
+                const uint32_t c = sl.kind[side] ? 1u | (sl.pay[side] << 1) : 0u;
+                w |= c << (fb + side * (1 + cb));
+                if (!sl.kind[side] && k >= 3) out->ranks |= (8u | sl.pay[side]) << (4 * (2 * (k - 3) + side));
+            }
+            out->slot[k] = Node8{sl.thr, w};
+        }
+    };
+    auto encode48 = [&](const BlockIR& bk, uint32_t child_base, Block48* out) {
+        *out = Block48{};
+        uint64_t bits[3] = {0, 0, 0};  // 136 bits of words, little-endian
+        for (int k = 0; k < 7; k++) {
+            const Slot& sl = bk.slot[k];
+            if (!sl.present) continue;
+            uint64_t w = sl.feat;
+            for (int side = 0; side < 2; side++) {
+                const uint64_t c = sl.kind[side] ? 1u | (sl.pay[side] << 1) : (uint64_t)sl.pay[side] << 1;
+                w |= c << (fb + side * (1 + P));
+            }
+            const int o = kBlock48WordBits * k;
+            bits[o / 64] |= w << (o % 64);
+            if (o % 64 + kBlock48WordBits > 64) bits[o / 64 + 1] |= w >> (64 - o % 64);
+            out->thr[k] = sl.thr;
+        }
+        out->words[0] = (uint32_t)bits[0];
+        out->words[1] = (uint32_t)(bits[0] >> 32);
+        out->words[2] = (uint32_t)bits[1];
+        out->words[3] = (uint32_t)(bits[1] >> 32);
+        out->words[4] = ((uint32_t)bits[2] & 0xFFu) | ((bk.n_children ? child_base : 0u) << 8);
+    };
 
     std::vector<BinEntry> bins(n_bins);
-    std::vector<std::vector<Block64>> blocks(n_bins);
+    std::vector<std::vector<uint8_t>> blocks(n_bins);
     std::vector<int32_t> roots(T, 0);
     int64_t word_cursor = 0;
+restart:
+    const int64_t block_words = use48 ? 6 : 8;  // 8-byte words per block
+    word_cursor = 0;
     for (int32_t b = 0; b < n_bins; b++) {
         BinEntry& be = bins[b];
         be.first_tree = b * B;
@@ -577,8 +642,12 @@ int pack_blocked(const fp_forest_view* v, const std::vector<TreeShape>& s, const
             for (size_t q = 0; q < tb[j].root.size(); q++)
                 if (pos[j][q] < 0) pos[j][q] = next++;
         if (next > INT32_MAX) return fp_set_error(FP_E2BIG, "bin %d holds too many blocks", b);
-        std::vector<Block64>& bl = blocks[b];
-        bl.assign((size_t)next, Block64{});
+        if (use48 && next > (int64_t)kBlock48MaxChildBase) {
+            use48 = false;
+            goto restart;
+        }
+        std::vector<uint8_t>& bl = blocks[b];
+        bl.assign((size_t)next * 8 * block_words, 0);
         for (int32_t j = 0; j < be.n_trees; j++) {
             const int32_t ti = be.first_tree + j;
             const TreeShape& t = s[ti];
@@ -588,17 +657,17 @@ int pack_blocked(const fp_forest_view* v, const std::vector<TreeShape>& s, const
             }
             roots[ti] = (int32_t)pos[j][0];
             for (size_t q = 0; q < tb[j].root.size(); q++) {
-                Block64 bk = tb[j].body[q];
-                const uint32_t first = bk.child_base;
-                bk.child_base = first < tb[j].root.size() ? (uint32_t)pos[j][first] : 0u;
-                if (bk.ranks == 0) bk.child_base = 0;
-                bl[(size_t)pos[j][q]] = bk;
+                const BlockIR& bk = tb[j].body[q];
+                const uint32_t child_base = bk.n_children ? (uint32_t)pos[j][bk.first_child] : 0u;
+                uint8_t* dst = bl.data() + (size_t)pos[j][q] * 8 * block_words;
+                if (use48) encode48(bk, child_base, reinterpret_cast<Block48*>(dst));
+                else encode64(bk, child_base, reinterpret_cast<Block64*>(dst));
             }
         }
         word_cursor = (int64_t)align_up((size_t)word_cursor, 16);
         be.node_base = word_cursor;
-        be.deep_len = (int32_t)bl.size();
-        word_cursor += 8 * (int64_t)bl.size();
+        be.deep_len = (int32_t)next;
+        word_cursor += block_words * next;
     }
     const int64_t n_words = word_cursor;
     const size_t table_off = sizeof(Header);
@@ -616,8 +685,7 @@ int pack_blocked(const fp_forest_view* v, const std::vector<TreeShape>& s, const
     memcpy(out->data() + fmap_off, fmap.data(), sizeof(int32_t) * fmap.size());
     uint8_t* words = out->data() + nodes_off;
     for (int32_t b = 0; b < n_bins; b++)
-        if (!blocks[b].empty())
-            memcpy(words + 8 * bins[b].node_base, blocks[b].data(), sizeof(Block64) * blocks[b].size());
+        if (!blocks[b].empty()) memcpy(words + 8 * bins[b].node_base, blocks[b].data(), blocks[b].size());
     h->bin_size = B;
     h->interleave_depth = D;
     h->n_bins = n_bins;
@@ -627,6 +695,7 @@ int pack_blocked(const fp_forest_view* v, const std::vector<TreeShape>& s, const
     h->fmap_offset = (int64_t)fmap_off;
     h->compact_fbits = fb;
     h->compact_cbits = cb;
+    h->block_bytes = use48 ? 48 : 64;
     h->table_offset = (int64_t)table_off;
     h->roots_offset = (int64_t)roots_off;
     h->nodes_offset = (int64_t)nodes_off;
@@ -690,8 +759,11 @@ int verify_buffer(const uint8_t* bytes, size_t n, std::string* why) {
                     h.compact_cbits < 1 || 2 * h.compact_cbits > 29 - h.compact_fbits))
         return bad("compact node section or field widths");
     if (blocked && (h.nodes_offset + 8 * N > (int64_t)n || h.compact_fbits < 1 || h.compact_cbits < 1 ||
-                    h.compact_fbits + 2 * (1 + h.compact_cbits) > 32))
+                    h.compact_fbits + 2 * (1 + h.compact_cbits) > 32 || (h.block_bytes != 48 && h.block_bytes != 64) ||
+                    (h.block_bytes == 48 &&
+                     h.compact_fbits + 2 * (1 + std::max(h.compact_cbits, 3)) > fp::kBlock48WordBits)))
         return bad("blocked node section or field widths");
+    const int64_t block_words = h.block_bytes == 48 ? 6 : 8;
     if (h.n_bins < 1 || h.table_offset + (int64_t)sizeof(BinEntry) * h.n_bins > h.roots_offset ||
         h.roots_offset + (int64_t)sizeof(int32_t) * h.n_trees > h.fmap_offset ||
         h.n_used_features < 1 || h.n_used_features > h.n_features ||
@@ -712,7 +784,7 @@ int verify_buffer(const uint8_t* bytes, size_t n, std::string* why) {
             return bad("bin %d tree range", b);
         tree_cursor += be.n_trees;
         const int64_t units = compact   ? 2 * (int64_t)be.top_len + be.deep_len
-                              : blocked ? 8 * (int64_t)be.deep_len
+                              : blocked ? block_words * (int64_t)be.deep_len
                                         : (int64_t)be.top_len + be.deep_len;
         if (be.top_len < 0 || be.deep_len < 0 || be.node_base < 0 || be.node_base % (compact || blocked ? 16 : 8) ||
             be.node_base + units > N)
@@ -731,6 +803,53 @@ int verify_buffer(const uint8_t* bytes, size_t n, std::string* why) {
             }
             const Node8* words = reinterpret_cast<const Node8*>(bytes + h.nodes_offset) + be.node_base;
             const int fb = h.compact_fbits, cb = h.compact_cbits;
+            if (h.block_bytes == 48) {
+                const int P = std::max(cb, 3);
+                const Block48* blk = reinterpret_cast<const Block48*>(words);
+                for (int64_t k = 0; k < be.deep_len; k++) {
+                    const Block48& bk = blk[k];
+                    const uint64_t lo = (uint64_t)bk.words[0] | (uint64_t)bk.words[1] << 32;
+                    const uint64_t mid = (uint64_t)bk.words[2] | (uint64_t)bk.words[3] << 32;
+                    const uint64_t hi = bk.words[4] & 0xFFu;
+                    auto word_of = [&](int sl) -> uint32_t {
+                        const int o = fp::kBlock48WordBits * sl;
+                        const uint64_t a = o < 64 ? lo : o < 128 ? mid : hi;
+                        const uint64_t c = o < 64 ? mid : hi;
+                        uint64_t w = a >> (o % 64);
+                        if (o % 64 + fp::kBlock48WordBits > 64) w |= c << (64 - o % 64);
+                        return (uint32_t)(w & ((1u << fp::kBlock48WordBits) - 1));
+                    };
+                    const int64_t child_base = bk.words[4] >> 8;
+                    if ((hi >> (7 * fp::kBlock48WordBits - 128)) != 0) return bad("bin %d block %lld: stray bits", b, (long long)k);
+                    bool present[7] = {true, false, false, false, false, false, false};
+                    int64_t n_exits = 0;
+                    for (int sl = 0; sl < 7; sl++) {
+                        const uint32_t w = word_of(sl);
+                        if (!present[sl]) {
+                            if (w != 0 || bk.thr[sl] != 0.0f) return bad("bin %d block %lld: stray slot %d", b, (long long)k, sl);
+                            continue;
+                        }
+                        if ((int64_t)(w & ((1u << fb) - 1)) >= F) return bad("bin %d block %lld slot %d feature", b, (long long)k, sl);
+                        if ((w >> (fb + 2 * (1 + P))) != 0) return bad("bin %d block %lld slot %d: stray bits", b, (long long)k, sl);
+                        for (int side = 0; side < 2; side++) {
+                            const uint32_t c = (w >> (fb + side * (1 + P))) & ((2u << P) - 1);
+                            if (c & 1) {
+                                if ((int64_t)(c >> 1) >= C) return bad("bin %d block %lld slot %d class", b, (long long)k, sl);
+                            } else if (sl < 3) {
+                                if (c != 0) return bad("bin %d block %lld slot %d: internal code with payload", b, (long long)k, sl);
+                                present[2 * sl + 1 + side] = true;
+                            } else {
+                                const int64_t rank = c >> 1;
+                                if (rank > 7 || child_base + rank <= k || child_base + rank >= be.deep_len)
+                                    return bad("bin %d block %lld exit of slot %d", b, (long long)k, sl);
+                                n_exits++;
+                            }
+                        }
+                    }
+                    if (n_exits == 0 && child_base != 0) return bad("bin %d block %lld: child base without exits", b, (long long)k);
+                }
+                continue;
+            }
             const Block64* blk = reinterpret_cast<const Block64*>(words);
             for (int64_t k = 0; k < be.deep_len; k++) {
                 const Block64& bk = blk[k];

@@ -191,6 +191,34 @@ __device__ __forceinline__ void stage_tile(const JobDesc& j, float* xs, int32_t*
     __syncthreads();
 }
 
+// After the walks of a tile: stores its vote counters (or adds them into the
+// global votes when several tree groups share the rows), then the class of
+// each row (lowest class on ties) when this workgroup saw every tree.
+__device__ __forceinline__ void write_tile(const JobDesc& j, const int32_t* vl, int64_t row0, int rows) {
+    const int tid = threadIdx.x, bd = blockDim.x;
+    __syncthreads();
+    for (int i = tid; i < rows * j.C; i += bd) {
+        int32_t* dst = j.votes + row0 * j.C + i;
+        if (j.atomic_votes) {
+            if (vl[i]) atomicAdd(dst, vl[i]);
+        } else {
+            *dst = vl[i];
+        }
+    }
+    if (!j.atomic_votes && j.cls) {
+        for (int rr = tid; rr < rows; rr += bd) {
+            int32_t best = 0, bestv = vl[rr * j.C];
+            for (int c = 1; c < j.C; c++)
+                if (vl[rr * j.C + c] > bestv) {
+                    bestv = vl[rr * j.C + c];
+                    best = c;
+                }
+            j.cls[row0 + rr] = best;
+        }
+    }
+    __syncthreads();
+}
+
 // A tile's observations as the walks see them: feature f of tile row r
 // (staged in LDS, or read from memory through the feature map) and the LDS
 // vote counters of row r.  Row offsets use 24-bit multiplies (full rate;
@@ -253,7 +281,6 @@ __device__ void run_tile(const JobDesc& j, int nt, int tile, unsigned char* smem
     float* xs = reinterpret_cast<float*>(smem + j.off_xs);
     int32_t* vl = reinterpret_cast<int32_t*>(smem + j.off_votes);
     int32_t* pool = reinterpret_cast<int32_t*>(smem + j.off_pool);
-    const int tid = threadIdx.x, bd = blockDim.x;
     const int lane = lane_id();
 
     const int64_t row0 = (int64_t)tile * j.R;
@@ -302,24 +329,7 @@ __device__ void run_tile(const JobDesc& j, int nt, int tile, unsigned char* smem
             }
         }
     }
-    __syncthreads();
-    for (int i = tid; i < rows_here * j.C; i += bd) {
-        int32_t* dst = j.votes + row0 * j.C + i;
-        if (j.atomic_votes) {
-            if (vl[i]) atomicAdd(dst, vl[i]);
-        } else {
-            *dst = vl[i];
-        }
-    }
-    if (!j.atomic_votes && j.cls) {
-        for (int rr = tid; rr < rows_here; rr += bd) {
-            int32_t best = 0, bestv = vl[rr * j.C];
-            for (int c = 1; c < j.C; c++)
-                if (vl[rr * j.C + c] > bestv) { bestv = vl[rr * j.C + c]; best = c; }
-            j.cls[row0 + rr] = best;
-        }
-    }
-    __syncthreads();
+    write_tile(j, vl, row0, rows_here);
 }
 
 // COMPACT layout walk.  Top nodes (Node16) come from memory (L1/L2); a deep
@@ -338,7 +348,6 @@ __device__ void run_tile_compact(const JobDesc& j, int nt, int tile, unsigned ch
     int32_t* vl = reinterpret_cast<int32_t*>(smem + j.off_votes);
     int32_t* pool = reinterpret_cast<int32_t*>(smem + j.off_pool);
     const uint2* words = reinterpret_cast<const uint2*>(j.nodes);
-    const int tid = threadIdx.x, bd = blockDim.x;
     const int lane = lane_id();
     const int fb = j.fbits, cb = j.cbits;
     const uint32_t fmask = (1u << fb) - 1u, cmask = (1u << cb) - 1u;
@@ -425,36 +434,62 @@ __device__ void run_tile_compact(const JobDesc& j, int nt, int tile, unsigned ch
             ref[k] = nr;
         }
     }
-    __syncthreads();
-    for (int i = tid; i < rows_here * j.C; i += bd) {
-        int32_t* dst = j.votes + row0 * j.C + i;
-        if (j.atomic_votes) {
-            if (vl[i]) atomicAdd(dst, vl[i]);
-        } else {
-            *dst = vl[i];
-        }
-    }
-    if (!j.atomic_votes && j.cls) {
-        for (int rr = tid; rr < rows_here; rr += bd) {
-            int32_t best = 0, bestv = vl[rr * j.C];
-            for (int c = 1; c < j.C; c++)
-                if (vl[rr * j.C + c] > bestv) { bestv = vl[rr * j.C + c]; best = c; }
-            j.cls[row0 + rr] = best;
-        }
-    }
-    __syncthreads();
+    write_tile(j, vl, row0, rows_here);
 }
 
-struct BlockRegs {
-    uint4 q0, q1, q2, q3;  // child_base, ranks, (thr, w) of slots 0..6
+// A fetched block as the walk sees it: the word and threshold of each slot,
+// the first child block, and how to read a child code.
+struct BlockView {
+    uint32_t w[7], t[7];
+    uint32_t child_base, ranks;
 };
 
+// Fetches block `ref` of the bin starting at word bb: three (48-byte form) or
+// four (64-byte form) 16-byte loads of one line, issued back to back.
+template <bool B48>
+__device__ __forceinline__ void fetch_block(const uint2* words, int32_t bb, int32_t ref, uint4 (&q)[4]) {
+    const uint4* bp = reinterpret_cast<const uint4*>(words + bb + (B48 ? 6 : 8) * ref);
+    q[0] = bp[0];
+    q[1] = bp[1];
+    q[2] = bp[2];
+    if (!B48) q[3] = bp[3];
+}
+
+// Unpacks a fetched block (Block48: 19-bit words at fixed offsets of the first
+// 136 bits; Block64: (thr, word) pairs after the header).
+template <bool B48>
+__device__ __forceinline__ BlockView view_block(const uint4 (&q)[4]) {
+    BlockView b;
+    if (B48) {
+        const uint32_t r[5] = {q[0].x, q[0].y, q[0].z, q[0].w, q[1].x};
+        constexpr uint32_t M = (1u << fp::kBlock48WordBits) - 1u;
+#pragma unroll
+        for (int sl = 0; sl < 7; sl++) {
+            const int o = fp::kBlock48WordBits * sl;
+            b.w[sl] = __builtin_amdgcn_alignbit(r[o / 32 + 1 < 5 ? o / 32 + 1 : 4], r[o / 32], o % 32) & M;
+        }
+        b.t[0] = q[1].y; b.t[1] = q[1].z; b.t[2] = q[1].w;
+        b.t[3] = q[2].x; b.t[4] = q[2].y; b.t[5] = q[2].z; b.t[6] = q[2].w;
+        b.child_base = r[4] >> 8;
+        b.ranks = 0;
+    } else {
+        b.child_base = q[0].x; b.ranks = q[0].y;
+        b.t[0] = q[0].z; b.w[0] = q[0].w;
+        b.t[1] = q[1].x; b.w[1] = q[1].y; b.t[2] = q[1].z; b.w[2] = q[1].w;
+        b.t[3] = q[2].x; b.w[3] = q[2].y; b.t[4] = q[2].z; b.w[4] = q[2].w;
+        b.t[5] = q[3].x; b.w[5] = q[3].y; b.t[6] = q[3].z; b.w[6] = q[3].w;
+    }
+    return b;
+}
+
 // BLOCKED layout walk.  Every reference is a block of the bin (or a class).
-// A block is fetched whole -- four 16-byte loads of one 64-byte line -- and
-// walked for up to three levels from registers: slot 0, then slot 1 or 2,
-// then one of slots 3..6, ending in a class or an exit to a child block,
-// which the next iteration fetches.
-template <int K, int FMODE>
+// A block is fetched whole and walked for up to three levels from registers:
+// slot 0, then slot 1 or 2, then one of slots 3..6, ending in a class or an
+// exit to a child block, which the next iteration fetches.  With the row's
+// features in LDS all seven split tests are read in one LDS round trip and
+// the path is resolved from a mask of sides by selects (no divergence inside
+// a block).
+template <int K, int FMODE, bool B48>
 __device__ void run_tile_blocked(const JobDesc& j, int nt, int tile, unsigned char* smem) {
     const bool feat_lds = FMODE == 2 ? (j.feat_lds != 0) : (FMODE == 1);
     const int4* ttab = reinterpret_cast<const int4*>(smem + j.off_ttab);
@@ -463,11 +498,11 @@ __device__ void run_tile_blocked(const JobDesc& j, int nt, int tile, unsigned ch
     int32_t* vl = reinterpret_cast<int32_t*>(smem + j.off_votes);
     int32_t* pool = reinterpret_cast<int32_t*>(smem + j.off_pool);
     const uint2* words = reinterpret_cast<const uint2*>(j.nodes);
-    const int tid = threadIdx.x, bd = blockDim.x;
     const int lane = lane_id();
-    const int fb = j.fbits, cb = j.cbits;
-    const uint32_t fmask = (1u << fb) - 1u, code_mask = (2u << cb) - 1u;
-    const uint32_t sh_l = (uint32_t)fb, sh_r = (uint32_t)(fb + 1 + cb);  // where the left / right codes start
+    const int fb = j.fbits;
+    const int cw = 1 + (B48 ? max(j.cbits, 3) : j.cbits);  // bits of one child code
+    const uint32_t fmask = (1u << fb) - 1u, code_mask = (1u << cw) - 1u;
+    const uint32_t sh_l = (uint32_t)fb, sh_r = (uint32_t)(fb + cw);  // where the left / right codes start
 
     const int64_t row0 = (int64_t)tile * j.R;
     const int rows_here = (int)min<int64_t>(j.R, j.n_rows - row0);
@@ -480,6 +515,11 @@ __device__ void run_tile_blocked(const JobDesc& j, int nt, int tile, unsigned ch
     auto le = [&](int32_t xrow, uint32_t f, float thr) {
         const float x = feat_lds ? xs[xrow + (int32_t)f] : j.X[(row0 + xrow) * j.ld + fmap_l[f]];
         return x <= thr;
+    };
+    // the block an exit leaves to: rank from the code (48-byte form) or the table
+    auto exit_to = [&](const BlockView& b, uint32_t e, uint32_t code) -> int32_t {
+        const uint32_t rank = B48 ? (code >> 1) : ((b.ranks >> (4 * e)) & 7u);
+        return (int32_t)(b.child_base + rank);
     };
     // per cursor: xrow, vrow = the row's first vote counter, bb = the bin's
     // first block (words)
@@ -506,76 +546,59 @@ __device__ void run_tile_blocked(const JobDesc& j, int nt, int tile, unsigned ch
             if (drained) break;
             continue;
         }
-        BlockRegs g[K];
+        uint4 q[K][4];
+#pragma unroll
+        for (int k = 0; k < K; k++)
+            if (ref[k] >= 0) fetch_block<B48>(words, bb[k], ref[k], q[k]);
 #pragma unroll
         for (int k = 0; k < K; k++) {
             if (ref[k] < 0) continue;
-            const uint4* bp = reinterpret_cast<const uint4*>(words + bb[k] + 8 * ref[k]);
-            g[k].q0 = bp[0]; g[k].q1 = bp[1]; g[k].q2 = bp[2]; g[k].q3 = bp[3];
-        }
-#pragma unroll
-        for (int k = 0; k < K; k++) {
-            if (ref[k] < 0) continue;
-            const uint4 q0 = g[k].q0, q1 = g[k].q1, q2 = g[k].q2, q3 = g[k].q3;
+            const BlockView b = view_block<B48>(q[k]);
             int32_t nr;
             if (feat_lds) {
-                // All seven split tests at once (absent slots are zero words:
-                // feature 0, harmless), packed into a mask of sides (bit s set
-                // = slot s goes right); the path through the three levels then
-                // reads the mask, so the seven LDS reads issue together, ahead
-                // of any branch: one LDS round trip per block.
-                const uint32_t wv[7] = {q0.w, q1.y, q1.w, q2.y, q2.w, q3.y, q3.w};
-                const uint32_t tv[7] = {q0.z, q1.x, q1.z, q2.x, q2.z, q3.x, q3.z};
+                // all seven split tests (absent slots are zero words: feature
+                // 0, harmless) packed into a mask of sides, bit s set = slot s
+                // goes right; the path reads the mask, so the seven LDS reads
+                // issue together, ahead of any branch
                 uint32_t gm = 0;
 #pragma unroll
                 for (int sl = 0; sl < 7; sl++)
-                    gm |= (xs[xrow[k] + (int32_t)(wv[sl] & fmask)] <= __uint_as_float(tv[sl]) ? 0u : 1u) << sl;
+                    gm |= (xs[xrow[k] + (int32_t)(b.w[sl] & fmask)] <= __uint_as_float(b.t[sl]) ? 0u : 1u) << sl;
                 const uint32_t side0 = gm & 1u;
-                const uint32_t c0 = (wv[0] >> (side0 ? sh_r : sh_l)) & code_mask;
+                const uint32_t c0 = (b.w[0] >> (side0 ? sh_r : sh_l)) & code_mask;
                 const uint32_t side1 = (gm >> (1 + side0)) & 1u;
-                const uint32_t w1 = side0 ? wv[2] : wv[1];
+                const uint32_t w1 = side0 ? b.w[2] : b.w[1];
                 const uint32_t c1 = (w1 >> (side1 ? sh_r : sh_l)) & code_mask;
                 const uint32_t idx = 2 * side0 + side1;
                 const uint32_t side2 = (gm >> (3 + idx)) & 1u;
-                const uint32_t w2 = side0 ? (side1 ? wv[6] : wv[5]) : (side1 ? wv[4] : wv[3]);
+                const uint32_t w2 = side0 ? (side1 ? b.w[6] : b.w[5]) : (side1 ? b.w[4] : b.w[3]);
                 const uint32_t c2 = (w2 >> (side2 ? sh_r : sh_l)) & code_mask;
-                const uint32_t e = 2 * idx + side2;
-                int32_t r = (int32_t)(q0.x + ((q0.y >> (4 * e)) & 7u));
+                int32_t r = exit_to(b, 2 * idx + side2, c2);
                 r = (c2 & 1u) ? ~(int32_t)(c2 >> 1) : r;
                 r = (c1 & 1u) ? ~(int32_t)(c1 >> 1) : r;
                 nr = (c0 & 1u) ? ~(int32_t)(c0 >> 1) : r;
             } else {
-            // level 0: slot 0
-            uint32_t w = q0.w;
-            uint32_t side = le(xrow[k], w & fmask, __uint_as_float(q0.z)) ? 0u : 1u;
-            uint32_t c = (w >> (fb + side * (1 + cb))) & code_mask;
-            if (c & 1u) {
-                nr = -(int32_t)(c >> 1) - 1;
-            } else {
-                // level 1: slot 1 + side
-                const uint32_t s1 = side;
-                w = s1 ? q1.w : q1.y;
-                float t = __uint_as_float(s1 ? q1.z : q1.x);
-                side = le(xrow[k], w & fmask, t) ? 0u : 1u;
-                c = (w >> (fb + side * (1 + cb))) & code_mask;
+                // features from memory: one level at a time
+                uint32_t side = le(xrow[k], b.w[0] & fmask, __uint_as_float(b.t[0])) ? 0u : 1u;
+                uint32_t c = (b.w[0] >> (side ? sh_r : sh_l)) & code_mask;
                 if (c & 1u) {
-                    nr = -(int32_t)(c >> 1) - 1;
+                    nr = ~(int32_t)(c >> 1);
                 } else {
-                    // level 2: slot 3 + idx, idx = 2 s1 + side
-                    const uint32_t idx = 2 * s1 + side;
-                    const uint4 qq = idx < 2 ? q2 : q3;
-                    w = (idx & 1u) ? qq.w : qq.y;
-                    t = __uint_as_float((idx & 1u) ? qq.z : qq.x);
-                    side = le(xrow[k], w & fmask, t) ? 0u : 1u;
-                    c = (w >> (fb + side * (1 + cb))) & code_mask;
+                    const uint32_t s1 = side;
+                    const uint32_t w1 = s1 ? b.w[2] : b.w[1];
+                    side = le(xrow[k], w1 & fmask, __uint_as_float(s1 ? b.t[2] : b.t[1])) ? 0u : 1u;
+                    c = (w1 >> (side ? sh_r : sh_l)) & code_mask;
                     if (c & 1u) {
-                        nr = -(int32_t)(c >> 1) - 1;
+                        nr = ~(int32_t)(c >> 1);
                     } else {
-                        const uint32_t e = 2 * idx + side;
-                        nr = (int32_t)(q0.x + ((q0.y >> (4 * e)) & 7u));
+                        const uint32_t idx = 2 * s1 + side;
+                        const uint32_t w2 = s1 ? (side ? b.w[6] : b.w[5]) : (side ? b.w[4] : b.w[3]);
+                        const uint32_t t2 = s1 ? (side ? b.t[6] : b.t[5]) : (side ? b.t[4] : b.t[3]);
+                        side = le(xrow[k], w2 & fmask, __uint_as_float(t2)) ? 0u : 1u;
+                        c = (w2 >> (side ? sh_r : sh_l)) & code_mask;
+                        nr = (c & 1u) ? ~(int32_t)(c >> 1) : exit_to(b, 2 * idx + side, c);
                     }
                 }
-            }
             }
             if (nr < 0) {
                 atomicAdd(&vl[vrow[k] - nr - 1], 1);
@@ -584,24 +607,7 @@ __device__ void run_tile_blocked(const JobDesc& j, int nt, int tile, unsigned ch
             ref[k] = nr;
         }
     }
-    __syncthreads();
-    for (int i = tid; i < rows_here * j.C; i += bd) {
-        int32_t* dst = j.votes + row0 * j.C + i;
-        if (j.atomic_votes) {
-            if (vl[i]) atomicAdd(dst, vl[i]);
-        } else {
-            *dst = vl[i];
-        }
-    }
-    if (!j.atomic_votes && j.cls) {
-        for (int rr = tid; rr < rows_here; rr += bd) {
-            int32_t best = 0, bestv = vl[rr * j.C];
-            for (int c = 1; c < j.C; c++)
-                if (vl[rr * j.C + c] > bestv) { bestv = vl[rr * j.C + c]; best = c; }
-            j.cls[row0 + rr] = best;
-        }
-    }
-    __syncthreads();
+    write_tile(j, vl, row0, rows_here);
 }
 
 // One forest: persistent workgroups, group = blockIdx % G (consecutive
@@ -627,7 +633,8 @@ __global__ __launch_bounds__(1024, (MinWaves<K, LAYOUT>::value)) void packed_ker
     if (nt == 0) return;  // uniform per block
     for (int tile = blockIdx.x / j.G; tile < j.n_tiles; tile += blocks_per_group) {
         if (LAYOUT == FP_LAYOUT_COMPACT) run_tile_compact<K, FMODE>(j, nt, tile, smem);
-        else if (LAYOUT == FP_LAYOUT_BLOCKED) run_tile_blocked<K, FMODE>(j, nt, tile, smem);
+        else if (LAYOUT == FP_LAYOUT_BLOCKED && j.block_bytes == 48) run_tile_blocked<K, FMODE, true>(j, nt, tile, smem);
+        else if (LAYOUT == FP_LAYOUT_BLOCKED) run_tile_blocked<K, FMODE, false>(j, nt, tile, smem);
         else run_tile<K, FMODE>(j, nt, tile, smem);
     }
 }
@@ -658,7 +665,10 @@ __global__ __launch_bounds__(1024) void batched_kernel(const JobDesc* __restrict
         if (j.layout == FP_LAYOUT_COMPACT)
             for (int tile = w.tile_begin; tile < w.tile_end; tile++) run_tile_compact<K, 2>(j, nt, tile, smem);
         else if (j.layout == FP_LAYOUT_BLOCKED)
-            for (int tile = w.tile_begin; tile < w.tile_end; tile++) run_tile_blocked<1, 2>(j, nt, tile, smem);
+            for (int tile = w.tile_begin; tile < w.tile_end; tile++) {
+                if (j.block_bytes == 48) run_tile_blocked<1, 2, true>(j, nt, tile, smem);
+                else run_tile_blocked<1, 2, false>(j, nt, tile, smem);
+            }
         else
             for (int tile = w.tile_begin; tile < w.tile_end; tile++) run_tile<K, 2>(j, nt, tile, smem);
     }
@@ -836,6 +846,7 @@ int resolve_job(const fp_packed* p, const fp_tune* t, const float* X, int64_t n_
     j->layout = h.layout;
     j->fbits = h.compact_fbits;
     j->cbits = h.compact_cbits;
+    j->block_bytes = h.block_bytes;
     if (t->refill_lanes < 0 || t->refill_lanes > 64) return fp_set_error(FP_EINVAL, "refill_lanes %d outside [0, 64]", t->refill_lanes);
     j->refill_min = t->refill_lanes > 0 ? t->refill_lanes : kDefaultRefillLanes;
     // feature_lds: 1 force LDS staging, -1 read features from memory, 0 automatic

@@ -6,7 +6,7 @@ import struct
 
 import numpy as np
 
-HEADER = struct.Struct("<QIi" + "i" * 8 + "q" * 7 + "ii" + "Q" + "ii" + "q" + "d" + "ii")
+HEADER = struct.Struct("<QIi" + "i" * 8 + "q" * 7 + "ii" + "Q" + "ii" + "q" + "d" + "ii" + "ii")
 NODE8 = np.dtype([("thr", "<f4"), ("w", "<u4")])
 NODE = np.dtype([("thr", "<f4"), ("feat", "<i4"), ("left", "<i4"), ("right", "<i4")])
 BIN = np.dtype([("node_base", "<i8"), ("first_tree", "<i4"), ("n_trees", "<i4"), ("top_len", "<i4"),
@@ -20,7 +20,7 @@ def decode(buf: np.ndarray) -> dict:
             "interleave_depth", "n_bins", "max_top_len", "max_bin_trees", "total_bytes", "table_offset",
             "roots_offset", "nodes_offset", "n_nodes", "n_internal", "n_leaves", "max_depth", "line_align",
             "checksum", "n_used_features", "pad0", "fmap_offset", "expected_depth", "compact_fbits",
-            "compact_cbits"]
+            "compact_cbits", "block_bytes", "pad1"]
     h = dict(zip(keys, f))
     if h["layout"] in (2, 3):
         nodes = np.frombuffer(b, NODE8, count=h["n_nodes"], offset=h["nodes_offset"])
@@ -129,52 +129,86 @@ def walk_compact(dec: dict, X: np.ndarray) -> np.ndarray:
 
 BLOCK = np.dtype({"names": ["child_base", "ranks", "slot"],
                   "formats": ["<u4", "<u4", np.dtype((NODE8, 7))]})
+BLOCK48 = np.dtype([("words", "<u4", 5), ("thr", "<f4", 7)])
+WORD48_BITS = 19
 
 
 def blocked_bin(dec: dict, be):
-    """(top Node16 array, Block64 array) of one bin of a BLOCKED buffer."""
+    """(top Node16 array (empty), raw block array) of one bin of a BLOCKED buffer."""
     h, b = dec["h"], dec["raw"]
     off = h["nodes_offset"] + 8 * int(be["node_base"])
     tl = int(be["top_len"])
     top = np.frombuffer(b, NODE, count=tl, offset=off)
-    blocks = np.frombuffer(b, BLOCK, count=int(be["deep_len"]), offset=off + 8 * ((2 * tl + 7) // 8 * 8))
+    dt = BLOCK48 if h["block_bytes"] == 48 else BLOCK
+    blocks = np.frombuffer(b, dt, count=int(be["deep_len"]), offset=off + 8 * ((2 * tl + 7) // 8 * 8))
     return top, blocks
+
+
+def block_fields(h, blocks):
+    """Either block form as plain arrays: child_base [n], thr [n, 7],
+    word [n, 7], feat [n, 7], kind [n, 7, 2] (1 = class), pay [n, 7, 2]
+    (class, or exit rank of a bottom slot's internal child)."""
+    fb, cb = h["compact_fbits"], h["compact_cbits"]
+    n = len(blocks)
+    if h["block_bytes"] == 48:
+        P = max(cb, 3)
+        big = np.zeros(n, object)
+        wd = blocks["words"].astype(object)
+        for i in range(5):
+            big = big + (wd[:, i] << (32 * i))
+        word = np.zeros((n, 7), np.int64)
+        for sl in range(7):
+            word[:, sl] = [int((v >> (WORD48_BITS * sl)) & ((1 << WORD48_BITS) - 1)) for v in big]
+        child_base = (blocks["words"][:, 4].astype(np.int64) >> 8)
+        thr = blocks["thr"]
+        cw = 1 + P
+    else:
+        word = blocks["slot"]["w"].astype(np.int64)
+        child_base = blocks["child_base"].astype(np.int64)
+        thr = blocks["slot"]["thr"]
+        cw = 1 + cb
+    feat = word & ((1 << fb) - 1)
+    kind = np.zeros((n, 7, 2), np.int64)
+    pay = np.zeros((n, 7, 2), np.int64)
+    for side in range(2):
+        c = (word >> (fb + side * cw)) & ((1 << cw) - 1)
+        kind[:, :, side] = c & 1
+        pay[:, :, side] = c >> 1
+    if h["block_bytes"] != 48:  # exit ranks live in the ranks table
+        ranks = blocks["ranks"].astype(np.int64)
+        for sl in range(3, 7):
+            for side in range(2):
+                e = 2 * (sl - 3) + side
+                internal = kind[:, sl, side] == 0
+                pay[:, sl, side] = np.where(internal, (ranks >> (4 * e)) & 7, pay[:, sl, side])
+    return {"child_base": child_base, "thr": thr, "word": word, "feat": feat, "kind": kind, "pay": pay}
 
 
 def walk_blocked(dec: dict, X: np.ndarray) -> np.ndarray:
     """Votes [n, C] from walking a BLOCKED buffer (vectorised over rows)."""
     h = dec["h"]
-    fb, cb = h["compact_fbits"], h["compact_cbits"]
     n, C = X.shape[0], h["n_classes"]
     votes = np.zeros((n, C), np.int32)
     rows = np.arange(n)
     fmap = dec["fmap"]
     for be in dec["bins"]:
-        top, blocks = blocked_bin(dec, be)
-        tl = int(be["top_len"])
+        _, blocks = blocked_bin(dec, be)
+        bf = block_fields(h, blocks) if len(blocks) else None
         for j in range(int(be["n_trees"])):
             ref = np.full(n, dec["roots"][be["root_base"] + j], np.int64)
-            while ((ref >= 0) & (ref < tl)).any():
-                live = (ref >= 0) & (ref < tl)
-                nd = top[np.where(live, ref, 0)]
-                go = X[rows, fmap[nd["feat"]]] <= nd["thr"]
-                ref = np.where(live, np.where(go, nd["left"], nd["right"]), ref)
-            k = np.where(ref >= tl, ref - tl, 0)
+            k = np.where(ref >= 0, ref, 0)
             slot = np.zeros(n, np.int64)
-            live = ref >= tl
+            live = ref >= 0
             while live.any():
-                bk = blocks[k]
-                w = bk["slot"]["w"][rows, slot].astype(np.int64)
-                thr = bk["slot"]["thr"][rows, slot]
-                side = np.where(X[rows, fmap[w & ((1 << fb) - 1)]] <= thr, 0, 1)
-                c = (w >> (fb + side * (1 + cb))) & ((2 << cb) - 1)
-                leaf = live & (c & 1 == 1)
-                ref = np.where(leaf, -(c >> 1) - 1, ref)
+                f = bf["feat"][k, slot]
+                side = np.where(X[rows, fmap[f]] <= bf["thr"][k, slot], 0, 1)
+                kind = bf["kind"][k, slot, side]
+                pay = bf["pay"][k, slot, side]
+                leaf = live & (kind == 1)
+                ref = np.where(leaf, -pay - 1, ref)
                 inner = live & ~leaf & (slot < 3)
                 ex = live & ~leaf & (slot >= 3)
-                e = 2 * (slot - 3) + side
-                rank = (bk["ranks"].astype(np.int64) >> (4 * np.where(ex, e, 0))) & 7
-                k = np.where(ex, bk["child_base"].astype(np.int64) + rank, k)
+                k = np.where(ex, bf["child_base"][k] + pay, k)
                 slot = np.where(inner, 2 * slot + 1 + side, np.where(ex, 0, slot))
                 live = live & ~leaf
             np.add.at(votes, (rows, -ref - 1), 1)

@@ -308,24 +308,35 @@ def test_blocked_equals_unpacked(small_forest, small_rows, B, D):
     assert np.array_equal(fp.fp_packed_host_bytes(q), fp.fp_packed_host_bytes(p))
 
 
-def test_blocked_layout_invariants():
+def wide_forest():
+    """A forest whose node words need the 64-byte block form (11 feature bits,
+    12 classes)."""
+    X, y = synth.gaussian_mixture(3000, 1100, 12, seed=77)
+    return synth.train_forest(X, y, n_trees=6, n_classes=12, mtry=300, max_depth=14, seed=78), X
+
+
+@pytest.mark.parametrize("which", ["image48", "wide64"])
+def test_blocked_layout_invariants(which):
     """Each block holds a complete three-level subtree of one tree (slot s has
     its children at 2s+1 and 2s+2); every internal node is stored exactly once;
     a block's child blocks are contiguous, after it, and in descending order of
     training cardinality; blocks whose root has depth <= D come first,
     level-major and tree-minor (Bin at block granularity)."""
-    from packed_format import blocked_bin
-    w = synth.image(n_train=6000, n_trees=8)
-    f = w.forest()
+    from packed_format import blocked_bin, block_fields
+    if which == "image48":
+        f = synth.image(n_train=6000, n_trees=8).forest()
+    else:
+        f, _ = wide_forest()
     for B, D in ((4, 3), (8, 0), (3, 7)):
         c = decode(fp.fp_packed_host_bytes(fp.fp_pack_forest(f, layout=fp.FP_LAYOUT_BLOCKED, bin_size=B,
                                                               interleave_depth=D)))
         h = c["h"]
-        fb, cb = h["compact_fbits"], h["compact_cbits"]
+        assert h["block_bytes"] == (48 if which == "image48" else 64)
         n_block_nodes = 0
         for bc in c["bins"]:
             assert bc["top_len"] == 0 and bc["node_base"] % 16 == 0
             _, blocks = blocked_bin(c, bc)
+            bf = block_fields(h, blocks)
             owner = {}  # block -> (tree j, block level)
             for j in range(int(bc["n_trees"])):
                 t = int(bc["first_tree"]) + j
@@ -340,36 +351,32 @@ def test_blocked_layout_invariants():
                     assert k not in owner
                     owner[k] = (j, level)
                     assert f.depth[off + orig] == 3 * level
-                    bk = blocks[k]
                     slot_orig = {0: orig}
                     exits = []
-                    for s in range(7):
-                        if s not in slot_orig:
-                            assert bk["slot"]["w"][s] == 0 and bk["slot"]["thr"][s] == 0
+                    for sl in range(7):
+                        if sl not in slot_orig:
+                            assert bf["word"][k, sl] == 0 and bf["thr"][k, sl] == 0
                             continue
-                        o = slot_orig[s]
-                        wd = int(bk["slot"]["w"][s])
-                        assert c["fmap"][wd & ((1 << fb) - 1)] == f.feature[off + o]
-                        assert bk["slot"]["thr"][s] == f.threshold[off + o]
+                        o = slot_orig[sl]
+                        assert c["fmap"][bf["feat"][k, sl]] == f.feature[off + o]
+                        assert bf["thr"][k, sl] == f.threshold[off + o]
                         n_block_nodes += 1
                         for side, ch in enumerate((f.left[off + o], f.right[off + o])):
-                            code = (wd >> (fb + side * (1 + cb))) & ((2 << cb) - 1)
+                            kind, pay = bf["kind"][k, sl, side], bf["pay"][k, sl, side]
                             if f.feature[off + ch] < 0:
-                                assert code == 1 | (f.leaf_class[off + ch] << 1)
-                            elif s < 3:
-                                assert code == 0
-                                slot_orig[2 * s + 1 + side] = ch
+                                assert kind == 1 and pay == f.leaf_class[off + ch]
+                            elif sl < 3:
+                                assert kind == 0 and pay == 0
+                                slot_orig[2 * sl + 1 + side] = ch
                             else:
-                                assert code == 0
-                                rank = (int(bk["ranks"]) >> (4 * (2 * (s - 3) + side))) & 15
-                                assert rank & 8
-                                exits.append((rank & 7, ch))
+                                assert kind == 0
+                                exits.append((int(pay), ch))
                     exits.sort()
                     assert [r for r, _ in exits] == list(range(len(exits)))
                     cards = [f.cardinality[off + ch] for _, ch in exits]
                     assert cards == sorted(cards, reverse=True)
                     for r, ch in exits:
-                        child = int(bk["child_base"]) + r
+                        child = int(bf["child_base"][k]) + r
                         assert child > k
                         stack.append((child, ch, level + 1))
             assert set(owner) == set(range(int(bc["deep_len"])))
@@ -380,6 +387,16 @@ def test_blocked_layout_invariants():
             assert all(lv <= D // 3 for _, lv in front) and front == sorted(front, key=lambda x: (x[1], x[0]))
             assert all(lv > D // 3 for _, lv in rest) and [j for j, _ in rest] == sorted(j for j, _ in rest)
         assert n_block_nodes == int((f.feature >= 0).sum())
+
+
+def test_blocked_wide_equals_unpacked():
+    f, X = wide_forest()
+    votes, _ = oracle.predict(f, X[:500])
+    for B, D in ((6, 3), (2, 0)):
+        p = fp.fp_pack_forest(f, layout=fp.FP_LAYOUT_BLOCKED, bin_size=B, interleave_depth=D)
+        dec = decode(fp.fp_packed_host_bytes(p))
+        assert dec["h"]["block_bytes"] == 64
+        assert (walk(dec, X[:500]) == votes).all()
 
 
 def test_blocked_rejects_bad_bytes(small_forest):
@@ -393,33 +410,43 @@ def test_blocked_rejects_bad_bytes(small_forest):
 
 
 def test_blocked_verifier_catches_structural_faults(small_forest):
-    """Faults planted behind a valid checksum: a backward exit, a stray slot,
-    a class out of range, an exit without a rank."""
-    from packed_format import BLOCK, reseal
-    p = fp.fp_pack_forest(small_forest, layout=fp.FP_LAYOUT_BLOCKED, bin_size=4, interleave_depth=1)
-    good = fp.fp_packed_host_bytes(p)
-    assert np.array_equal(fp.fp_packed_host_bytes(fp.fp_packed_from_bytes(reseal(good))), good)
-    dec = decode(good)
-    h, be = dec["h"], dec["bins"][0]
-    fb, cb = h["compact_fbits"], h["compact_cbits"]
-    base = h["nodes_offset"] + 8 * (int(be["node_base"]) + (2 * int(be["top_len"]) + 7) // 8 * 8)
-    blocks = np.frombuffer(good.tobytes(), BLOCK, count=int(be["deep_len"]), offset=base)
-    k = int(np.nonzero(blocks["ranks"])[0][8])  # a block with exits, at least 8 blocks in
-    kl = int(np.nonzero(blocks["slot"]["w"][:, 6] == 0)[0][0])  # a block whose last slot is empty
+    """Faults planted behind a valid checksum, in both block forms: a backward
+    exit, a stray slot, a class out of range, a missing exit rank / child base."""
+    from packed_format import BLOCK, BLOCK48, reseal
+    wide, _ = wide_forest()
+    for f in (small_forest, wide):
+        p = fp.fp_pack_forest(f, layout=fp.FP_LAYOUT_BLOCKED, bin_size=4, interleave_depth=1)
+        good = fp.fp_packed_host_bytes(p)
+        assert np.array_equal(fp.fp_packed_host_bytes(fp.fp_packed_from_bytes(reseal(good))), good)
+        dec = decode(good)
+        h, be = dec["h"], dec["bins"][0]
+        base = h["nodes_offset"] + 8 * int(be["node_base"])
+        faults = []
 
-    def planted(offset, dtype, value):
-        bad = good.copy()
-        bad[offset:offset + 4] = np.frombuffer(np.array([value], dtype).tobytes(), np.uint8)
-        return reseal(bad)
+        def planted(offset, value):
+            bad = good.copy()
+            bad[offset:offset + 4] = np.frombuffer(np.array([value], "<u4").tobytes(), np.uint8)
+            return reseal(bad)
 
-    faults = [
-        planted(base + 64 * k, "<u4", 0),  # child_base 0: exit points backward
-        planted(base + 64 * kl + 8 + 6 * 8 + 4, "<u4", 1),  # word in an absent slot
-        planted(base + 64 * k + 8 + 4, "<u4",
-                int(blocks["slot"]["w"][k, 0]) | (((h["n_classes"] << 1) | 1) << fb)),  # class C
-        planted(base + 64 * k + 4, "<u4", 0),  # exits lose their ranks
-    ]
-    for i, bad in enumerate(faults):
-        with pytest.raises(fp.FPError) as e:
-            fp.fp_packed_from_bytes(bad)
-        assert e.value.code == fp.FP_ECORRUPT, i
+        if h["block_bytes"] == 48:
+            blocks = np.frombuffer(good.tobytes(), BLOCK48, count=int(be["deep_len"]), offset=base)
+            cb = blocks["words"][:, 4] >> 8
+            k = int(np.nonzero(cb > 8)[0][8])  # a block with exits, 8 blocks in
+            faults.append(planted(base + 48 * k + 16, int(blocks["words"][k, 4]) & 0xFF))  # child base 0
+            kl = int(np.nonzero(blocks["thr"][:, 6] == 0)[0][0])  # last slot empty
+            faults.append(planted(base + 48 * kl + 20 + 24, 0x3F800000))  # a threshold in an absent slot
+            faults.append(planted(base + 48 * k, int(blocks["words"][k, 0]) | (((h["n_classes"] << 1) | 1)
+                                                                                << h["compact_fbits"])))
+        else:
+            blocks = np.frombuffer(good.tobytes(), BLOCK, count=int(be["deep_len"]), offset=base)
+            k = int(np.nonzero(blocks["ranks"])[0][8])
+            kl = int(np.nonzero(blocks["slot"]["w"][:, 6] == 0)[0][0])
+            faults.append(planted(base + 64 * k, 0))  # child_base 0: exit points backward
+            faults.append(planted(base + 64 * kl + 8 + 6 * 8 + 4, 1))  # word in an absent slot
+            faults.append(planted(base + 64 * k + 8 + 4, int(blocks["slot"]["w"][k, 0]) |
+                                  (((h["n_classes"] << 1) | 1) << h["compact_fbits"])))
+            faults.append(planted(base + 64 * k + 4, 0))  # exits lose their ranks
+        for i, bad in enumerate(faults):
+            with pytest.raises(fp.FPError) as e:
+                fp.fp_packed_from_bytes(bad)
+            assert e.value.code == fp.FP_ECORRUPT, (h["block_bytes"], i)
