@@ -220,6 +220,9 @@ void fp_packed_free(fp_packed *p);
  *                   of its lanes (1..64) are idle in a cursor slot, or when none
  *                   is walking; larger values spend fewer instructions on
  *                   refills and leave lanes idle longer
+ *   lds_bytes       LDS one workgroup may use (0: half of a CU's, so that two
+ *                   workgroups share a CU; capped at the device's per-block
+ *                   limit); more LDS fits more observations per tile
  * Zero fields mean "library default".  Naive layout uses block_threads only.
  */
 typedef struct fp_tune {
@@ -230,7 +233,7 @@ typedef struct fp_tune {
     int32_t lds_top_nodes;
     int32_t feature_lds;
     int32_t refill_lanes;
-    int32_t reserved;
+    int32_t lds_bytes;
 } fp_tune;
 
 /* Store `tune` as the launch parameters fp_predict uses for p (NULL: defaults). */

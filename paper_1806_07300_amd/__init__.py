@@ -58,7 +58,7 @@ class fp_packed_info(ctypes.Structure):
 class fp_tune(ctypes.Structure):
     _fields_ = [("rows_per_block", _i32), ("cursors", _i32), ("tree_groups", _i32),
                 ("block_threads", _i32), ("lds_top_nodes", _i32), ("feature_lds", _i32),
-                ("refill_lanes", _i32), ("reserved", _i32)]
+                ("refill_lanes", _i32), ("lds_bytes", _i32)]
 
 
 TUNE_FIELDS = [f for f, _ in fp_tune._fields_ if f != "reserved"]

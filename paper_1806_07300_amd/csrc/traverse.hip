@@ -250,10 +250,14 @@ __device__ int stage_group(const JobDesc& j, int group, unsigned char* smem) {
     int4* ttab = reinterpret_cast<int4*>(smem + j.off_ttab);
     const int t_lo = j.bins[b_lo].first_tree;
     const int nt = j.bins[b_hi - 1].first_tree + j.bins[b_hi - 1].n_trees - t_lo;
+    // PACKED: the bin's top nodes; BLOCKED: its first blocks (roots first), as
+    // 16-byte pieces; cap pieces per bin
+    const int bw = j.block_bytes / 16;
     for (int i = tid; i < (b_hi - b_lo) * j.cap; i += bd) {
         const int bl = i / j.cap, k = i - bl * j.cap;
         const BinEntry& be = j.bins[b_lo + bl];
-        if (k < be.top_len) top[i] = j.nodes[be.node_base + k];
+        const int32_t have = j.layout == FP_LAYOUT_BLOCKED ? be.deep_len * bw : be.top_len;
+        if (k < have) top[i] = j.nodes[(j.layout == FP_LAYOUT_BLOCKED ? be.node_base / 2 : be.node_base) + k];
     }
     for (int tl = tid; tl < nt; tl += bd) {
         const int t = t_lo + tl;
@@ -261,7 +265,8 @@ __device__ int stage_group(const JobDesc& j, int group, unsigned char* smem) {
         const BinEntry& be = j.bins[b];
         const int32_t nb = (int32_t)be.node_base;
         ttab[tl] = j.layout == FP_LAYOUT_COMPACT   ? make_int4(j.roots[t], nb, be.top_len, 0)
-                   : j.layout == FP_LAYOUT_BLOCKED ? make_int4(j.roots[t], nb, 0, 0)
+                   : j.layout == FP_LAYOUT_BLOCKED ? make_int4(j.roots[t], nb, (b - b_lo) * j.cap,
+                                                               min(be.deep_len, j.cap / max(bw, 1)))
                                                    : make_int4(j.roots[t], nb, (b - b_lo) * j.cap, min(be.top_len, j.cap));
     }
     if (!j.feat_lds) {
@@ -445,14 +450,25 @@ struct BlockView {
 };
 
 // Fetches block `ref` of the bin starting at word bb: three (48-byte form) or
-// four (64-byte form) 16-byte loads of one line, issued back to back.
+// four (64-byte form) 16-byte loads of one line, issued back to back; the
+// bin's first `ns` blocks come from their LDS copy at piece lb instead.
 template <bool B48>
-__device__ __forceinline__ void fetch_block(const uint2* words, int32_t bb, int32_t ref, uint4 (&q)[4]) {
-    const uint4* bp = reinterpret_cast<const uint4*>(words + bb + (B48 ? 6 : 8) * ref);
-    q[0] = bp[0];
-    q[1] = bp[1];
-    q[2] = bp[2];
-    if (!B48) q[3] = bp[3];
+__device__ __forceinline__ void fetch_block(const uint2* words, const uint4* lds, int32_t bb, int32_t lb, int32_t ns,
+                                            int32_t ref, uint4 (&q)[4]) {
+    constexpr int bw = B48 ? 3 : 4;
+    if (ref < ns) {
+        const uint4* lp = lds + lb + bw * ref;
+        q[0] = lp[0];
+        q[1] = lp[1];
+        q[2] = lp[2];
+        if (!B48) q[3] = lp[3];
+    } else {
+        const uint4* bp = reinterpret_cast<const uint4*>(words + bb + 2 * bw * ref);
+        q[0] = bp[0];
+        q[1] = bp[1];
+        q[2] = bp[2];
+        if (!B48) q[3] = bp[3];
+    }
 }
 
 // Unpacks a fetched block (Block48: 19-bit words at fixed offsets of the first
@@ -521,15 +537,16 @@ __device__ void run_tile_blocked(const JobDesc& j, int nt, int tile, unsigned ch
         const uint32_t rank = B48 ? (code >> 1) : ((b.ranks >> (4 * e)) & 7u);
         return (int32_t)(b.child_base + rank);
     };
+    const uint4* lds_blocks = reinterpret_cast<const uint4*>(smem + j.off_top);
     // per cursor: xrow, vrow = the row's first vote counter, bb = the bin's
-    // first block (words)
-    int32_t ref[K], xrow[K], vrow[K], bb[K];
+    // first block (words), lb / ns = its LDS copy (first piece, blocks held)
+    int32_t ref[K], xrow[K], vrow[K], bb[K], lb[K], ns[K];
 #pragma unroll
-    for (int k = 0; k < K; k++) { ref[k] = kDone; xrow[k] = 0; vrow[k] = 0; bb[k] = 0; }
+    for (int k = 0; k < K; k++) { ref[k] = kDone; xrow[k] = 0; vrow[k] = 0; bb[k] = 0; lb[k] = 0; ns[k] = 0; }
     auto take = [&](int k, int r, int4 e) -> int32_t {
         xrow[k] = feat_lds ? (int32_t)__umul24((uint32_t)r, (uint32_t)j.Fcp) : r;
         vrow[k] = (int32_t)__umul24((uint32_t)r, (uint32_t)j.C);
-        bb[k] = e.y;
+        bb[k] = e.y; lb[k] = e.z; ns[k] = e.w;
         if (e.x < 0) {  // the root is a leaf
             atomicAdd(&vl[vrow[k] - e.x - 1], 1);
             return kDone;
@@ -549,7 +566,7 @@ __device__ void run_tile_blocked(const JobDesc& j, int nt, int tile, unsigned ch
         uint4 q[K][4];
 #pragma unroll
         for (int k = 0; k < K; k++)
-            if (ref[k] >= 0) fetch_block<B48>(words, bb[k], ref[k], q[k]);
+            if (ref[k] >= 0) fetch_block<B48>(words, lds_blocks, bb[k], lb[k], ns[k], ref[k], q[k]);
 #pragma unroll
         for (int k = 0; k < K; k++) {
             if (ref[k] < 0) continue;
@@ -806,6 +823,10 @@ size_t job_lds_layout(JobDesc* j) {
     return o;
 }
 
+const BinEntry* bins_host(const fp_packed* p) {
+    return reinterpret_cast<const BinEntry*>(p->bytes.data() + p->hdr.table_offset);
+}
+
 int resolve_job(const fp_packed* p, const fp_tune* t, const float* X, int64_t n_rows, int64_t ld, int32_t* votes,
                 int32_t* cls, size_t lds_block, JobDesc* j) {
     const Header& h = p->hdr;
@@ -862,10 +883,20 @@ int resolve_job(const fp_packed* p, const fp_tune* t, const float* X, int64_t n_
         if (need > lds_block)
             return fp_set_error(FP_E2BIG, "per-workgroup tables of %zu bytes exceed %zu bytes of LDS", need, lds_block);
     }
+    // LDS left over holds the hottest nodes: PACKED bin tops, or the first
+    // blocks of each BLOCKED bin (its trees' root blocks come first), counted
+    // in 16-byte pieces per bin
     size_t top_nodes = (lds_block - need) / sizeof(Node16);
-    if (t->lds_top_nodes < 0 || h.layout != FP_LAYOUT_PACKED) top_nodes = 0;  // COMPACT, BLOCKED: tops from memory
+    if (t->lds_top_nodes < 0 || h.layout == FP_LAYOUT_COMPACT) top_nodes = 0;  // COMPACT: tops from memory
     else if (t->lds_top_nodes > 0) top_nodes = std::min(top_nodes, (size_t)t->lds_top_nodes);
-    j->cap = (int32_t)std::min<size_t>(top_nodes / bpg, (size_t)h.max_top_len);
+    if (h.layout == FP_LAYOUT_BLOCKED) {
+        const size_t bw = (size_t)h.block_bytes / 16;
+        int64_t max_blocks = 0;
+        for (int32_t b = 0; b < h.n_bins; b++) max_blocks = std::max<int64_t>(max_blocks, bins_host(p)[b].deep_len);
+        j->cap = (int32_t)(std::min<size_t>(top_nodes / bpg / bw, (size_t)max_blocks) * bw);
+    } else {
+        j->cap = (int32_t)std::min<size_t>(top_nodes / bpg, (size_t)h.max_top_len);
+    }
     job_lds_layout(j);
     return FP_OK;
 }
@@ -975,8 +1006,11 @@ static int predict_impl(const fp_packed* p, const fp_tune* tune, const float* X,
 
     const int K = tune && tune->cursors > 0 ? tune->cursors : 2;
     if (K != 1 && K != 2 && K != 4 && K != 8) return fp_set_error(FP_EINVAL, "cursors must be 1, 2, 4 or 8");
-    const size_t lds_block = tune && tune->lds_top_nodes > 0 ? (dp.lds_per_block ? dp.lds_per_block : 65536)
-                                                              : fp::default_lds_block(dp);
+    const size_t lds_max = dp.lds_per_block ? dp.lds_per_block : 65536;
+    if (tune && tune->lds_bytes < 0) return fp_set_error(FP_EINVAL, "lds_bytes %d < 0", tune->lds_bytes);
+    const size_t lds_block = tune && tune->lds_bytes > 0      ? std::min((size_t)tune->lds_bytes, lds_max)
+                             : tune && tune->lds_top_nodes > 0 ? lds_max
+                                                               : fp::default_lds_block(dp);
     fp::JobDesc j;
     rc = fp::resolve_job(p, tune, X, n_rows, ld, votes, cls, lds_block, &j);
     if (rc) return rc;
