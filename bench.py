@@ -110,8 +110,9 @@ def serve_leg(fp, synth, np, torch, image_forest, seconds, warm, rate, cache, su
     for name, w, f in workloads:
         f = f if f is not None else w.forest(cache_dir=cache)
         pool, _ = w.rows(65536, w.predict_seed + 1000)
-        p = fp.fp_pack_forest(f, bin_size=f.n_trees, interleave_depth=4)
+        p = fp.fp_pack_forest(f, layout=fp.FP_LAYOUT_BLOCKED, bin_size=f.n_trees, interleave_depth=3)
         fp.fp_packed_upload(p)
+        fp.fp_packed_set_tune(p, {"rows_per_block": 32, "refill_lanes": 16})
         v, _ = fp.fp_predict(p, torch.from_numpy(pool).cuda())
         torch.cuda.synchronize()
         forests.append({"name": name, "pool": pool, "C": f.n_classes, "id": fp.fp_server_add_forest(server, p),
@@ -287,7 +288,7 @@ def main():
                         "purity on 60,000 rows, 1,000,000 rows per step",
             "n_rows": n, "n_trees": forest.n_trees, "n_features": F, "n_classes": C,
             "internal_nodes": info["n_internal"],
-            "layout": {0: "naive", 1: "packed", 2: "compact", 3: "blocked"}[info["layout"]],
+            "layout": {0: "naive", 1: "packed", 2: "compact", 3: "blocked", 4: "clustered"}[info["layout"]],
             "bin_size": info["bin_size"], "interleave_depth": info["interleave_depth"], "tune": cfg["tune"],
         },
         "naive": {"value": n / (ms_naive / 1e3), "ms_per_step": ms_naive},

@@ -127,7 +127,14 @@ enum {
      * interleave_depth, of all the bin's trees, come first, level-major.
      * Needs feature and class fields to fit 32 bits (FP_E2BIG otherwise);
      * line_align is ignored. */
-    FP_LAYOUT_BLOCKED = 3
+    FP_LAYOUT_BLOCKED = 3,
+    /* Like BLOCKED, but a 64-byte block holds the up to 7 most visited nodes
+     * reachable from its root (chosen greedily by training cardinality: the
+     * hot paths of Stat, grouped into one fetch) instead of a fixed
+     * three-level subtree, with a table that maps the 7 split outcomes to
+     * the block's exit.  Needs at most 4,096 used features and 32 classes
+     * (FP_E2BIG otherwise); line_align is ignored. */
+    FP_LAYOUT_CLUSTERED = 4
 };
 
 /*

@@ -19,7 +19,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libforestpack.so")
 
 FP_OK, FP_EINVAL, FP_ENOMEM, FP_EHIP, FP_ECORRUPT, FP_E2BIG, FP_EAGAIN, FP_ENOTREADY, FP_ENODEV = range(9)
-FP_LAYOUT_NAIVE, FP_LAYOUT_PACKED, FP_LAYOUT_COMPACT, FP_LAYOUT_BLOCKED = 0, 1, 2, 3
+FP_LAYOUT_NAIVE, FP_LAYOUT_PACKED, FP_LAYOUT_COMPACT, FP_LAYOUT_BLOCKED, FP_LAYOUT_CLUSTERED = 0, 1, 2, 3, 4
 ERROR_NAMES = {0: "FP_OK", 1: "FP_EINVAL", 2: "FP_ENOMEM", 3: "FP_EHIP", 4: "FP_ECORRUPT",
                5: "FP_E2BIG", 6: "FP_EAGAIN", 7: "FP_ENOTREADY", 8: "FP_ENODEV"}
 

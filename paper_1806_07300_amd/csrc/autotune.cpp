@@ -192,12 +192,12 @@ extern "C" int fp_autotune(const fp_forest_view* forest, const float* X, int64_t
                 }
         // pass 2: packing (layout, bin size, interleave depth)
         std::set<std::tuple<int, int, int>> tried{{FP_LAYOUT_PACKED, T, 4}};
-        for (int L : {FP_LAYOUT_PACKED, FP_LAYOUT_COMPACT, FP_LAYOUT_BLOCKED})
+        for (int L : {FP_LAYOUT_PACKED, FP_LAYOUT_COMPACT, FP_LAYOUT_BLOCKED, FP_LAYOUT_CLUSTERED})
             for (int B : {T, 64, 16}) {
                 if (B > T) continue;
                 for (int D = 0; D <= std::min(7, max_depth); D++) {
                     // BLOCKED interleaves whole blocks (three levels): only D / 3 matters
-                    if (L == FP_LAYOUT_BLOCKED && D % 3) continue;
+                    if (L >= FP_LAYOUT_BLOCKED && D % 3) continue;
                     if (!tried.insert(std::make_tuple(L, B, D)).second) continue;
                     rc = use_pack(L, B, D);
                     if (rc == FP_E2BIG) continue;  // the compact encoding does not fit this forest

@@ -94,6 +94,26 @@ static_assert(sizeof(Block48) == 48, "block is 48 bytes");
 constexpr int kBlock48WordBits = 19;
 constexpr uint32_t kBlock48MaxChildBase = (1u << 24) - 1;
 
+// CLUSTERED layout block (64 bytes): up to 7 internal nodes of one tree
+// chosen greedily by training cardinality from the block's root (the most
+// visited connected group), in slots 0..6 (slot 0 = the root), and the up to
+// 8 edges that leave them ("exits": a leaf's class or a child block).  An
+// exit is selected by the split outcomes of the slots on its path: with g =
+// the 7-bit mask of outcomes (bit s set = slot s goes right), exit e is
+// taken iff (g ^ val[e]) & care[e] == 0; the used exits partition all 128
+// masks, unused ones are all-zero.  bits[] fields (little-endian over
+// bits[0..8]): [0, 84) feature of slot s in 12 bits at 12 s; [84, 140)
+// care[e] in 7 bits at 84 + 7 e; [140, 196) val[e] at 140 + 7 e; [196, 244)
+// target[e] in 6 bits at 196 + 6 e (bit 5 set = child block child_base +
+// bits 0..2, clear = class bits 0..4); [244, 268) child_base; [268, 272)
+// number of child blocks; [272, 276) number of exits.  Absent slots are zero.
+struct BlockC64 {
+    float thr[7];
+    uint32_t bits[9];
+};
+static_assert(sizeof(BlockC64) == 64, "block is 64 bytes");
+constexpr int kClusterFeatBits = 12, kClusterMaxClasses = 32;
+
 struct BinEntry {
     int64_t node_base;   // first node of the bin in the node array
     int32_t first_tree;

@@ -36,6 +36,7 @@ using fp::Header;
 using fp::Node16;
 using fp::Node8;
 using fp::Block48;
+using fp::BlockC64;
 using fp::Block64;
 
 // ---------------------------------------------------------------------------
@@ -495,19 +496,23 @@ int pack_blocked(const fp_forest_view* v, const std::vector<TreeShape>& s, const
     const int32_t B = (o->bin_size <= 0 || o->bin_size > T) ? T : o->bin_size;
     const int32_t D = o->interleave_depth;
     const int32_t n_bins = (T + B - 1) / B;
-    fill_header_common(h, v, s, FP_LAYOUT_BLOCKED);
+    const bool clustered = o->layout == FP_LAYOUT_CLUSTERED;
+    fill_header_common(h, v, s, o->layout);
     std::vector<int32_t> remap, fmap;
     feature_map(v, s, &remap, &fmap);
     const int fb = bits_for((int64_t)fmap.size());
     const int cb = bits_for(v->n_classes);
-    if (fb + 2 * (1 + cb) > 32)
+    if (!clustered && fb + 2 * (1 + cb) > 32)
         return fp_set_error(FP_E2BIG, "blocked layout: %d feature bits and %d classes do not fit a 32-bit node word",
                             fb, v->n_classes);
+    if (clustered && (fb > kClusterFeatBits || v->n_classes > kClusterMaxClasses))
+        return fp_set_error(FP_E2BIG, "clustered layout: %zu used features (max %d) or %d classes (max %d)",
+                            fmap.size(), 1 << kClusterFeatBits, v->n_classes, kClusterMaxClasses);
     const int32_t last_interleaved_level = D / 3;
     const int P = std::max(cb, 3);
     // 48-byte blocks when a node word fits 19 bits and every bin has fewer
     // than 2^24 blocks (checked below; the packing restarts in 64-byte form)
-    bool use48 = fb + 2 * (1 + P) <= kBlock48WordBits;
+    bool use48 = !clustered && fb + 2 * (1 + P) <= kBlock48WordBits;
 
     // One tree's blocks in breadth-first order: the subtree root node of each
     // block, its level, and its slots; child blocks are found by bfs index.
@@ -522,6 +527,9 @@ int pack_blocked(const fp_forest_view* v, const std::vector<TreeShape>& s, const
         Slot slot[7];
         uint32_t first_child = 0;  // bfs index of the first child block
         uint32_t n_children = 0;
+        // CLUSTERED: exits with the outcomes that select them
+        uint32_t n_exits = 0;
+        uint32_t care[8] = {0}, val[8] = {0}, target[8] = {0};
     };
     struct TreeBlocks {
         std::vector<int32_t> root, level;
@@ -572,6 +580,105 @@ int pack_blocked(const fp_forest_view* v, const std::vector<TreeShape>& s, const
             }
             tb->body.push_back(bk);
         }
+    };
+    // CLUSTERED: greedy groups of up to 7 nodes, most samples first
+    auto build_clusters = [&](const TreeShape& t, TreeBlocks* tb) {
+        tb->root.assign(1, 0);
+        tb->level.assign(1, 0);
+        for (size_t q = 0; q < tb->root.size(); q++) {
+            // members in the order they join; parent slot and side of each
+            int32_t node[7], par[7], pside[7];
+            int m = 0;
+            struct Cand {
+                int64_t card;
+                int32_t node, par, side;
+            };
+            auto hotter = [](const Cand& a, const Cand& c) {  // max-heap by cardinality, then lower node id
+                return a.card != c.card ? a.card < c.card : a.node > c.node;
+            };
+            std::vector<Cand> front{Cand{t.card[tb->root[q]], tb->root[q], -1, 0}};
+            while (!front.empty() && m < 7) {
+                std::pop_heap(front.begin(), front.end(), hotter);
+                const Cand c = front.back();
+                front.pop_back();
+                node[m] = c.node;
+                par[m] = c.par;
+                pside[m] = c.side;
+                const int64_t g = t.base + c.node;
+                const int32_t ch[2] = {v->left[g], v->right[g]};
+                for (int side = 0; side < 2; side++)
+                    if (v->feature[t.base + ch[side]] >= 0) {
+                        front.push_back(Cand{t.card[ch[side]], ch[side], m, side});
+                        std::push_heap(front.begin(), front.end(), hotter);
+                    }
+                m++;
+            }
+            BlockIR bk;
+            auto path = [&](int slot, uint32_t* care, uint32_t* val) {  // outcomes that lead to slot
+                *care = 0;
+                *val = 0;
+                for (int x = slot; par[x] >= 0; x = par[x]) {
+                    *care |= 1u << par[x];
+                    *val |= (uint32_t)pside[x] << par[x];
+                }
+            };
+            struct Exit {
+                int e;
+                int32_t node;
+                int64_t card;
+            };
+            std::vector<Exit> ext;  // exits to child blocks
+            for (int k = 0; k < m; k++) {
+                const int64_t g = t.base + node[k];
+                Slot& sl = bk.slot[k];
+                sl.present = true;
+                sl.thr = v->threshold[g];
+                sl.feat = (uint32_t)remap[v->feature[g]];
+                const int32_t ch[2] = {v->left[g], v->right[g]};
+                for (int side = 0; side < 2; side++) {
+                    bool inside = false;
+                    for (int x = 0; x < m; x++) inside |= (par[x] == k && pside[x] == side);
+                    if (inside) continue;
+                    const int e = (int)bk.n_exits++;
+                    uint32_t care, val;
+                    path(k, &care, &val);
+                    bk.care[e] = care | (1u << k);
+                    bk.val[e] = val | ((uint32_t)side << k);
+                    const int64_t gc = t.base + ch[side];
+                    if (v->feature[gc] < 0) bk.target[e] = (uint32_t)v->leaf_class[gc];
+                    else ext.push_back(Exit{e, ch[side], t.card[ch[side]]});
+                }
+            }
+            std::stable_sort(ext.begin(), ext.end(), [](const Exit& a, const Exit& c) { return a.card > c.card; });
+            bk.first_child = (uint32_t)tb->root.size();
+            bk.n_children = (uint32_t)ext.size();
+            for (size_t r = 0; r < ext.size(); r++) {
+                bk.target[ext[r].e] = 32u | (uint32_t)r;
+                tb->root.push_back(ext[r].node);
+                tb->level.push_back(tb->level[q] + 1);
+            }
+            tb->body.push_back(bk);
+        }
+    };
+    auto encodeC = [&](const BlockIR& bk, uint32_t child_base, BlockC64* out) {
+        *out = BlockC64{};
+        auto put = [&](int pos, int width, uint32_t value) {
+            for (int i = 0; i < width; i++)
+                if (value >> i & 1u) out->bits[(pos + i) / 32] |= 1u << ((pos + i) % 32);
+        };
+        for (int k = 0; k < 7; k++) {
+            if (!bk.slot[k].present) continue;
+            out->thr[k] = bk.slot[k].thr;
+            put(kClusterFeatBits * k, kClusterFeatBits, bk.slot[k].feat);
+        }
+        for (uint32_t e = 0; e < bk.n_exits; e++) {
+            put(84 + 7 * (int)e, 7, bk.care[e]);
+            put(140 + 7 * (int)e, 7, bk.val[e]);
+            put(196 + 6 * (int)e, 6, bk.target[e]);
+        }
+        put(244, 24, bk.n_children ? child_base : 0u);
+        put(268, 4, bk.n_children);
+        put(272, 4, bk.n_exits);
     };
     // encoders: child_base is the final index of the block's first child
     auto encode64 = [&](const BlockIR& bk, uint32_t child_base, Block64* out) {
@@ -628,7 +735,9 @@ restart:
         std::vector<TreeBlocks> tb(be.n_trees);
         for (int32_t j = 0; j < be.n_trees; j++) {
             const TreeShape& t = s[be.first_tree + j];
-            if (v->feature[t.base] >= 0) build_tree(t, &tb[j]);
+            if (v->feature[t.base] < 0) continue;
+            if (clustered) build_clusters(t, &tb[j]);
+            else build_tree(t, &tb[j]);
         }
         // final position of every (tree, bfs index)
         std::vector<std::vector<int64_t>> pos(be.n_trees);
@@ -646,6 +755,8 @@ restart:
             use48 = false;
             goto restart;
         }
+        if (clustered && next > (int64_t)kBlock48MaxChildBase)
+            return fp_set_error(FP_E2BIG, "bin %d holds %lld blocks (clustered layout addresses 2^24)", b, (long long)next);
         std::vector<uint8_t>& bl = blocks[b];
         bl.assign((size_t)next * 8 * block_words, 0);
         for (int32_t j = 0; j < be.n_trees; j++) {
@@ -660,7 +771,8 @@ restart:
                 const BlockIR& bk = tb[j].body[q];
                 const uint32_t child_base = bk.n_children ? (uint32_t)pos[j][bk.first_child] : 0u;
                 uint8_t* dst = bl.data() + (size_t)pos[j][q] * 8 * block_words;
-                if (use48) encode48(bk, child_base, reinterpret_cast<Block48*>(dst));
+                if (clustered) encodeC(bk, child_base, reinterpret_cast<BlockC64*>(dst));
+                else if (use48) encode48(bk, child_base, reinterpret_cast<Block48*>(dst));
                 else encode64(bk, child_base, reinterpret_cast<Block64*>(dst));
             }
         }
@@ -722,7 +834,9 @@ int verify_buffer(const uint8_t* bytes, size_t n, std::string* why) {
         return bad("bad forest dimensions");
     if (fnv1a64(bytes + sizeof(Header), n - sizeof(Header)) != h.checksum) return bad("checksum mismatch");
     const int64_t N = h.n_nodes;
-    const int64_t unit = h.layout == FP_LAYOUT_COMPACT || h.layout == FP_LAYOUT_BLOCKED ? 8 : (int64_t)sizeof(Node16);
+    const int64_t unit = h.layout == FP_LAYOUT_COMPACT || h.layout == FP_LAYOUT_BLOCKED || h.layout == FP_LAYOUT_CLUSTERED
+                             ? 8
+                             : (int64_t)sizeof(Node16);
     if (N < 0 || h.nodes_offset < (int64_t)sizeof(Header) || h.nodes_offset % 256 ||
         h.nodes_offset + N * unit > (int64_t)n)
         return bad("node section out of bounds");
@@ -751,18 +865,23 @@ int verify_buffer(const uint8_t* bytes, size_t n, std::string* why) {
         }
         return FP_OK;
     }
-    if (h.layout != FP_LAYOUT_PACKED && h.layout != FP_LAYOUT_COMPACT && h.layout != FP_LAYOUT_BLOCKED)
+    if (h.layout != FP_LAYOUT_PACKED && h.layout != FP_LAYOUT_COMPACT && h.layout != FP_LAYOUT_BLOCKED &&
+        h.layout != FP_LAYOUT_CLUSTERED)
         return bad("unknown layout %d", h.layout);
     const bool compact = h.layout == FP_LAYOUT_COMPACT;
-    const bool blocked = h.layout == FP_LAYOUT_BLOCKED;
+    const bool clustered = h.layout == FP_LAYOUT_CLUSTERED;
+    const bool blocked = h.layout == FP_LAYOUT_BLOCKED || clustered;
     if (compact && (h.nodes_offset + 8 * N + 16 > (int64_t)n || h.compact_fbits < 1 || h.compact_fbits > 26 ||
                     h.compact_cbits < 1 || 2 * h.compact_cbits > 29 - h.compact_fbits))
         return bad("compact node section or field widths");
-    if (blocked && (h.nodes_offset + 8 * N > (int64_t)n || h.compact_fbits < 1 || h.compact_cbits < 1 ||
-                    h.compact_fbits + 2 * (1 + h.compact_cbits) > 32 || (h.block_bytes != 48 && h.block_bytes != 64) ||
-                    (h.block_bytes == 48 &&
-                     h.compact_fbits + 2 * (1 + std::max(h.compact_cbits, 3)) > fp::kBlock48WordBits)))
+    if (blocked && !clustered &&
+        (h.nodes_offset + 8 * N > (int64_t)n || h.compact_fbits < 1 || h.compact_cbits < 1 ||
+         h.compact_fbits + 2 * (1 + h.compact_cbits) > 32 || (h.block_bytes != 48 && h.block_bytes != 64) ||
+         (h.block_bytes == 48 && h.compact_fbits + 2 * (1 + std::max(h.compact_cbits, 3)) > fp::kBlock48WordBits)))
         return bad("blocked node section or field widths");
+    if (clustered && (h.nodes_offset + 8 * N > (int64_t)n || h.block_bytes != 64 || h.compact_fbits < 1 ||
+                      h.compact_fbits > fp::kClusterFeatBits || C > fp::kClusterMaxClasses))
+        return bad("clustered node section or field widths");
     const int64_t block_words = h.block_bytes == 48 ? 6 : 8;
     if (h.n_bins < 1 || h.table_offset + (int64_t)sizeof(BinEntry) * h.n_bins > h.roots_offset ||
         h.roots_offset + (int64_t)sizeof(int32_t) * h.n_trees > h.fmap_offset ||
@@ -803,6 +922,57 @@ int verify_buffer(const uint8_t* bytes, size_t n, std::string* why) {
             }
             const Node8* words = reinterpret_cast<const Node8*>(bytes + h.nodes_offset) + be.node_base;
             const int fb = h.compact_fbits, cb = h.compact_cbits;
+            if (clustered) {
+                const BlockC64* blk = reinterpret_cast<const BlockC64*>(words);
+                for (int64_t k = 0; k < be.deep_len; k++) {
+                    const BlockC64& bk = blk[k];
+                    auto get = [&](int pos, int width) -> uint32_t {
+                        uint32_t v = 0;
+                        for (int i = 0; i < width; i++) v |= ((bk.bits[(pos + i) / 32] >> ((pos + i) % 32)) & 1u) << i;
+                        return v;
+                    };
+                    const uint32_t n_child = get(268, 4), n_exit = get(272, 4);
+                    const int64_t child_base = get(244, 24);
+                    if (n_exit < 2 || n_exit > 8 || n_child > n_exit || get(276, 12) != 0 || (bk.bits[8] >> 24) != 0)
+                        return bad("bin %d block %lld: exit counts", b, (long long)k);
+                    if (n_child ? (child_base <= k || child_base + n_child > be.deep_len) : child_base != 0)
+                        return bad("bin %d block %lld: child blocks", b, (long long)k);
+                    const uint32_t n_slot = n_exit - 1;  // a binary tree of m nodes has m + 1 exits
+                    for (uint32_t sl = 0; sl < 7; sl++) {
+                        const uint32_t f = get(fp::kClusterFeatBits * (int)sl, fp::kClusterFeatBits);
+                        if (sl < n_slot ? (int64_t)f >= F : (f != 0 || bk.thr[sl] != 0.0f))
+                            return bad("bin %d block %lld slot %u", b, (long long)k, sl);
+                    }
+                    // used exits: targets in range, and their outcome patterns
+                    // partition the 2^n_slot masks (pairwise disjoint, sizes sum)
+                    uint32_t care[8], val[8], child_used = 0;
+                    int64_t covered = 0;
+                    for (uint32_t e = 0; e < 8; e++) {
+                        care[e] = get(84 + 7 * (int)e, 7);
+                        val[e] = get(140 + 7 * (int)e, 7);
+                        const uint32_t tgt = get(196 + 6 * (int)e, 6);
+                        if (e >= n_exit) {
+                            if (care[e] | val[e] | tgt) return bad("bin %d block %lld: stray exit %u", b, (long long)k, e);
+                            continue;
+                        }
+                        if ((val[e] & ~care[e]) || (care[e] >> n_slot) || care[e] == 0)
+                            return bad("bin %d block %lld exit %u pattern", b, (long long)k, e);
+                        if (tgt & 32u) {
+                            if ((tgt & 31u) >= n_child) return bad("bin %d block %lld exit %u child", b, (long long)k, e);
+                            child_used |= 1u << (tgt & 31u);
+                        } else if ((int64_t)tgt >= C) {
+                            return bad("bin %d block %lld exit %u class", b, (long long)k, e);
+                        }
+                        covered += (int64_t)1 << (n_slot - __builtin_popcount(care[e]));
+                        for (uint32_t d = 0; d < e; d++)
+                            if (((val[e] ^ val[d]) & care[e] & care[d]) == 0)
+                                return bad("bin %d block %lld exits %u and %u overlap", b, (long long)k, d, e);
+                    }
+                    if (covered != ((int64_t)1 << n_slot) || child_used != (n_child ? (1u << n_child) - 1u : 0u))
+                        return bad("bin %d block %lld: exits do not cover every outcome once", b, (long long)k);
+                }
+                continue;
+            }
             if (h.block_bytes == 48) {
                 const int P = std::max(cb, 3);
                 const Block48* blk = reinterpret_cast<const Block48*>(words);
@@ -945,7 +1115,7 @@ extern "C" int fp_pack_forest(const fp_forest_view* forest, const fp_pack_opts* 
     if (!out) return fp_set_error(FP_EINVAL, "out is NULL");
     *out = nullptr;
     if (!opts) return fp_set_error(FP_EINVAL, "opts is NULL");
-    if (opts->layout < FP_LAYOUT_NAIVE || opts->layout > FP_LAYOUT_BLOCKED)
+    if (opts->layout < FP_LAYOUT_NAIVE || opts->layout > FP_LAYOUT_CLUSTERED)
         return fp_set_error(FP_EINVAL, "unknown layout %d", opts->layout);
     if (opts->layout != FP_LAYOUT_NAIVE && (opts->interleave_depth < 0 || opts->interleave_depth > 30))
         return fp_set_error(FP_EINVAL, "interleave_depth %d outside [0, 30]", opts->interleave_depth);
@@ -955,7 +1125,7 @@ extern "C" int fp_pack_forest(const fp_forest_view* forest, const fp_pack_opts* 
         if (rc) return rc;
         std::unique_ptr<fp_packed> p(new fp_packed());
         rc = opts->layout == FP_LAYOUT_NAIVE     ? fp::pack_naive(forest, shapes, &p->bytes, &p->hdr)
-             : opts->layout == FP_LAYOUT_BLOCKED ? fp::pack_blocked(forest, shapes, opts, &p->bytes, &p->hdr)
+             : opts->layout >= FP_LAYOUT_BLOCKED ? fp::pack_blocked(forest, shapes, opts, &p->bytes, &p->hdr)
                                                  : fp::pack_packed(forest, shapes, opts, &p->bytes, &p->hdr);
         if (rc) return rc;
         *out = p.release();

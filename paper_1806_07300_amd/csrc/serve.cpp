@@ -386,7 +386,7 @@ extern "C" int fp_server_create(const fp_server_opts* opts, fp_server** out) {
 extern "C" int fp_server_add_forest(fp_server* s, const fp_packed* p, int32_t* forest_id) {
     fp_clear_error();
     if (!s || !p || !forest_id) return fp_set_error(FP_EINVAL, "NULL argument");
-    if (p->hdr.layout != FP_LAYOUT_PACKED && p->hdr.layout != FP_LAYOUT_COMPACT && p->hdr.layout != FP_LAYOUT_BLOCKED)
+    if (p->hdr.layout == FP_LAYOUT_NAIVE)
         return fp_set_error(FP_EINVAL, "forest is not in a packed layout");
     if (!p->dev) return fp_set_error(FP_ENODEV, "forest is not uploaded");
     if (p->dev_id != s->dev) return fp_set_error(FP_ENODEV, "forest on device %d, server on device %d", p->dev_id, s->dev);

@@ -256,8 +256,9 @@ __device__ int stage_group(const JobDesc& j, int group, unsigned char* smem) {
     for (int i = tid; i < (b_hi - b_lo) * j.cap; i += bd) {
         const int bl = i / j.cap, k = i - bl * j.cap;
         const BinEntry& be = j.bins[b_lo + bl];
-        const int32_t have = j.layout == FP_LAYOUT_BLOCKED ? be.deep_len * bw : be.top_len;
-        if (k < have) top[i] = j.nodes[(j.layout == FP_LAYOUT_BLOCKED ? be.node_base / 2 : be.node_base) + k];
+        const bool blk = j.layout >= FP_LAYOUT_BLOCKED;
+        const int32_t have = blk ? be.deep_len * bw : be.top_len;
+        if (k < have) top[i] = j.nodes[(blk ? be.node_base / 2 : be.node_base) + k];
     }
     for (int tl = tid; tl < nt; tl += bd) {
         const int t = t_lo + tl;
@@ -265,7 +266,7 @@ __device__ int stage_group(const JobDesc& j, int group, unsigned char* smem) {
         const BinEntry& be = j.bins[b];
         const int32_t nb = (int32_t)be.node_base;
         ttab[tl] = j.layout == FP_LAYOUT_COMPACT   ? make_int4(j.roots[t], nb, be.top_len, 0)
-                   : j.layout == FP_LAYOUT_BLOCKED ? make_int4(j.roots[t], nb, (b - b_lo) * j.cap,
+                   : j.layout >= FP_LAYOUT_BLOCKED ? make_int4(j.roots[t], nb, (b - b_lo) * j.cap,
                                                                min(be.deep_len, j.cap / max(bw, 1)))
                                                    : make_int4(j.roots[t], nb, (b - b_lo) * j.cap, min(be.top_len, j.cap));
     }
@@ -455,7 +456,7 @@ struct BlockView {
 template <bool B48>
 __device__ __forceinline__ void fetch_block(const uint2* words, const uint4* lds, int32_t bb, int32_t lb, int32_t ns,
                                             int32_t ref, uint4 (&q)[4]) {
-    constexpr int bw = B48 ? 3 : 4;
+    constexpr int bw = B48 ? 3 : 4;  // 16-byte pieces per block
     if (ref < ns) {
         const uint4* lp = lds + lb + bw * ref;
         q[0] = lp[0];
@@ -498,6 +499,43 @@ __device__ __forceinline__ BlockView view_block(const uint4 (&q)[4]) {
     return b;
 }
 
+// Field [pos, pos + width) of the 288 bits b[0..8] of a CLUSTERED block
+// (positions are compile-time constants, so this is one or two ALU ops).
+template <int pos, int width>
+__device__ __forceinline__ uint32_t cfield(const uint32_t (&b)[9]) {
+    constexpr uint32_t mask = width == 32 ? ~0u : (1u << width) - 1u;
+    if constexpr (pos % 32 + width <= 32) return (b[pos / 32] >> (pos % 32)) & mask;
+    else return __builtin_amdgcn_alignbit(b[pos / 32 + 1], b[pos / 32], pos % 32) & mask;
+}
+
+// CLUSTERED block: reads the seven split outcomes (one LDS round trip, as in
+// the BLOCKED walk) and returns the next reference: the child block or the
+// class of the one exit whose outcome pattern matches.
+template <typename Le>
+__device__ __forceinline__ int32_t cluster_step(const uint4 (&q)[4], int32_t xrow, Le&& le) {
+    const float thr[7] = {__uint_as_float(q[0].x), __uint_as_float(q[0].y), __uint_as_float(q[0].z),
+                          __uint_as_float(q[0].w), __uint_as_float(q[1].x), __uint_as_float(q[1].y),
+                          __uint_as_float(q[1].z)};
+    const uint32_t b[9] = {q[1].w, q[2].x, q[2].y, q[2].z, q[2].w, q[3].x, q[3].y, q[3].z, q[3].w};
+    const uint32_t f[7] = {cfield<0, 12>(b), cfield<12, 12>(b), cfield<24, 12>(b), cfield<36, 12>(b),
+                           cfield<48, 12>(b), cfield<60, 12>(b), cfield<72, 12>(b)};
+    uint32_t g = 0;
+#pragma unroll
+    for (int sl = 0; sl < 7; sl++) g |= (le(xrow, f[sl], thr[sl]) ? 0u : 1u) << sl;
+    uint32_t t = 0;
+#define FP_EXIT(e)                                                                                       \
+    {                                                                                                    \
+        const uint32_t care = cfield<84 + 7 * e, 7>(b), val = cfield<140 + 7 * e, 7>(b);                \
+        t |= ((g ^ val) & care) == 0 ? cfield<196 + 6 * e, 6>(b) : 0u;                                   \
+    }
+    FP_EXIT(0) FP_EXIT(1) FP_EXIT(2) FP_EXIT(3) FP_EXIT(4) FP_EXIT(5) FP_EXIT(6) FP_EXIT(7)
+#undef FP_EXIT
+    // unused exits are all-zero and add nothing; a verified block's used exits
+    // partition the outcomes, so exactly one contributes
+    const uint32_t n_child = cfield<268, 4>(b);
+    return (t & 32u) ? (int32_t)(cfield<244, 24>(b) + min(t & 7u, n_child - 1u)) : ~(int32_t)(t & 31u);
+}
+
 // BLOCKED layout walk.  Every reference is a block of the bin (or a class).
 // A block is fetched whole and walked for up to three levels from registers:
 // slot 0, then slot 1 or 2, then one of slots 3..6, ending in a class or an
@@ -505,8 +543,10 @@ __device__ __forceinline__ BlockView view_block(const uint4 (&q)[4]) {
 // features in LDS all seven split tests are read in one LDS round trip and
 // the path is resolved from a mask of sides by selects (no divergence inside
 // a block).
-template <int K, int FMODE, bool B48>
+// FMT: 0 BLOCKED 48-byte blocks, 1 BLOCKED 64-byte blocks, 2 CLUSTERED.
+template <int K, int FMODE, int FMT>
 __device__ void run_tile_blocked(const JobDesc& j, int nt, int tile, unsigned char* smem) {
+    constexpr bool B48 = FMT == 0;
     const bool feat_lds = FMODE == 2 ? (j.feat_lds != 0) : (FMODE == 1);
     const int4* ttab = reinterpret_cast<const int4*>(smem + j.off_ttab);
     const int32_t* fmap_l = reinterpret_cast<const int32_t*>(smem + j.off_fmap);
@@ -570,9 +610,10 @@ __device__ void run_tile_blocked(const JobDesc& j, int nt, int tile, unsigned ch
 #pragma unroll
         for (int k = 0; k < K; k++) {
             if (ref[k] < 0) continue;
-            const BlockView b = view_block<B48>(q[k]);
             int32_t nr;
-            if (feat_lds) {
+            if (FMT == 2) {
+                nr = cluster_step(q[k], xrow[k], le);
+            } else if (const BlockView b = view_block<B48>(q[k]); feat_lds) {
                 // all seven split tests (absent slots are zero words: feature
                 // 0, harmless) packed into a mask of sides, bit s set = slot s
                 // goes right; the path reads the mask, so the seven LDS reads
@@ -650,8 +691,9 @@ __global__ __launch_bounds__(1024, (MinWaves<K, LAYOUT>::value)) void packed_ker
     if (nt == 0) return;  // uniform per block
     for (int tile = blockIdx.x / j.G; tile < j.n_tiles; tile += blocks_per_group) {
         if (LAYOUT == FP_LAYOUT_COMPACT) run_tile_compact<K, FMODE>(j, nt, tile, smem);
-        else if (LAYOUT == FP_LAYOUT_BLOCKED && j.block_bytes == 48) run_tile_blocked<K, FMODE, true>(j, nt, tile, smem);
-        else if (LAYOUT == FP_LAYOUT_BLOCKED) run_tile_blocked<K, FMODE, false>(j, nt, tile, smem);
+        else if (LAYOUT == FP_LAYOUT_BLOCKED && j.block_bytes == 48) run_tile_blocked<K, FMODE, 0>(j, nt, tile, smem);
+        else if (LAYOUT == FP_LAYOUT_BLOCKED) run_tile_blocked<K, FMODE, 1>(j, nt, tile, smem);
+        else if (LAYOUT == FP_LAYOUT_CLUSTERED) run_tile_blocked<K, FMODE, 2>(j, nt, tile, smem);
         else run_tile<K, FMODE>(j, nt, tile, smem);
     }
 }
@@ -681,10 +723,11 @@ __global__ __launch_bounds__(1024) void batched_kernel(const JobDesc* __restrict
         if (nt == 0) continue;
         if (j.layout == FP_LAYOUT_COMPACT)
             for (int tile = w.tile_begin; tile < w.tile_end; tile++) run_tile_compact<K, 2>(j, nt, tile, smem);
-        else if (j.layout == FP_LAYOUT_BLOCKED)
+        else if (j.layout >= FP_LAYOUT_BLOCKED)
             for (int tile = w.tile_begin; tile < w.tile_end; tile++) {
-                if (j.block_bytes == 48) run_tile_blocked<1, 2, true>(j, nt, tile, smem);
-                else run_tile_blocked<1, 2, false>(j, nt, tile, smem);
+                if (j.layout == FP_LAYOUT_CLUSTERED) run_tile_blocked<1, 2, 2>(j, nt, tile, smem);
+                else if (j.block_bytes == 48) run_tile_blocked<1, 2, 0>(j, nt, tile, smem);
+                else run_tile_blocked<1, 2, 1>(j, nt, tile, smem);
             }
         else
             for (int tile = w.tile_begin; tile < w.tile_end; tile++) run_tile<K, 2>(j, nt, tile, smem);
@@ -751,6 +794,7 @@ const void* packed_fn_fm(int fmode) {
 const void* pick_packed(int K, int fmode, int layout) {
     if (K != 1 && K != 2 && K != 4 && K != 8) return nullptr;
     if (layout == FP_LAYOUT_BLOCKED) return packed_fn_fm<1, FP_LAYOUT_BLOCKED>(fmode);
+    if (layout == FP_LAYOUT_CLUSTERED) return packed_fn_fm<1, FP_LAYOUT_CLUSTERED>(fmode);
 #define FP_PICK(KK)                                                                     \
     if (K == KK)                                                                        \
         return layout == FP_LAYOUT_COMPACT ? packed_fn_fm<KK, FP_LAYOUT_COMPACT>(fmode) \
@@ -830,7 +874,8 @@ const BinEntry* bins_host(const fp_packed* p) {
 int resolve_job(const fp_packed* p, const fp_tune* t, const float* X, int64_t n_rows, int64_t ld, int32_t* votes,
                 int32_t* cls, size_t lds_block, JobDesc* j) {
     const Header& h = p->hdr;
-    if (h.layout != FP_LAYOUT_PACKED && h.layout != FP_LAYOUT_COMPACT && h.layout != FP_LAYOUT_BLOCKED)
+    if (h.layout != FP_LAYOUT_PACKED && h.layout != FP_LAYOUT_COMPACT && h.layout != FP_LAYOUT_BLOCKED &&
+        h.layout != FP_LAYOUT_CLUSTERED)
         return fp_set_error(FP_EINVAL, "forest is not in a packed layout");
     if (!p->dev) return fp_set_error(FP_ENODEV, "packed forest is not uploaded");
     if (h.n_nodes >= INT32_MAX)
@@ -889,7 +934,7 @@ int resolve_job(const fp_packed* p, const fp_tune* t, const float* X, int64_t n_
     size_t top_nodes = (lds_block - need) / sizeof(Node16);
     if (t->lds_top_nodes < 0 || h.layout == FP_LAYOUT_COMPACT) top_nodes = 0;  // COMPACT: tops from memory
     else if (t->lds_top_nodes > 0) top_nodes = std::min(top_nodes, (size_t)t->lds_top_nodes);
-    if (h.layout == FP_LAYOUT_BLOCKED) {
+    if (h.layout >= FP_LAYOUT_BLOCKED) {
         const size_t bw = (size_t)h.block_bytes / 16;
         int64_t max_blocks = 0;
         for (int32_t b = 0; b < h.n_bins; b++) max_blocks = std::max<int64_t>(max_blocks, bins_host(p)[b].deep_len);

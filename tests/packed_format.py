@@ -22,7 +22,7 @@ def decode(buf: np.ndarray) -> dict:
             "checksum", "n_used_features", "pad0", "fmap_offset", "expected_depth", "compact_fbits",
             "compact_cbits", "block_bytes", "pad1"]
     h = dict(zip(keys, f))
-    if h["layout"] in (2, 3):
+    if h["layout"] in (2, 3, 4):
         nodes = np.frombuffer(b, NODE8, count=h["n_nodes"], offset=h["nodes_offset"])
     else:
         nodes = np.frombuffer(b, NODE, count=h["n_nodes"], offset=h["nodes_offset"])
@@ -43,6 +43,8 @@ def walk(dec: dict, X: np.ndarray) -> np.ndarray:
         return walk_compact(dec, X)
     if h["layout"] == 3:
         return walk_blocked(dec, X)
+    if h["layout"] == 4:
+        return walk_clustered(dec, X)
     n, C = X.shape[0], h["n_classes"]
     votes = np.zeros((n, C), np.int32)
     nodes = dec["nodes"]
@@ -130,6 +132,7 @@ def walk_compact(dec: dict, X: np.ndarray) -> np.ndarray:
 BLOCK = np.dtype({"names": ["child_base", "ranks", "slot"],
                   "formats": ["<u4", "<u4", np.dtype((NODE8, 7))]})
 BLOCK48 = np.dtype([("words", "<u4", 5), ("thr", "<f4", 7)])
+BLOCKC = np.dtype([("thr", "<f4", 7), ("bits", "<u4", 9)])
 WORD48_BITS = 19
 
 
@@ -139,7 +142,7 @@ def blocked_bin(dec: dict, be):
     off = h["nodes_offset"] + 8 * int(be["node_base"])
     tl = int(be["top_len"])
     top = np.frombuffer(b, NODE, count=tl, offset=off)
-    dt = BLOCK48 if h["block_bytes"] == 48 else BLOCK
+    dt = BLOCKC if h["layout"] == 4 else BLOCK48 if h["block_bytes"] == 48 else BLOCK
     blocks = np.frombuffer(b, dt, count=int(be["deep_len"]), offset=off + 8 * ((2 * tl + 7) // 8 * 8))
     return top, blocks
 
@@ -227,3 +230,51 @@ def reseal(buf: np.ndarray) -> np.ndarray:
     pos = struct.calcsize("<QIi" + "i" * 8 + "q" * 7 + "ii")
     out[pos:pos + 8] = np.frombuffer(struct.pack("<Q", h), np.uint8)
     return out
+
+
+def cluster_fields(blocks):
+    """CLUSTERED blocks as plain arrays: thr [n, 7], feat [n, 7], care, val,
+    target [n, 8], child_base, n_children, n_exits [n]."""
+    n = len(blocks)
+    big = [sum(int(w) << (32 * i) for i, w in enumerate(row)) for row in blocks["bits"]]
+    get = lambda pos, width: np.array([(v >> pos) & ((1 << width) - 1) for v in big], np.int64).reshape(n)
+    return {"thr": blocks["thr"],
+            "feat": np.stack([get(12 * s, 12) for s in range(7)], 1) if n else np.zeros((0, 7), np.int64),
+            "care": np.stack([get(84 + 7 * e, 7) for e in range(8)], 1) if n else np.zeros((0, 8), np.int64),
+            "val": np.stack([get(140 + 7 * e, 7) for e in range(8)], 1) if n else np.zeros((0, 8), np.int64),
+            "target": np.stack([get(196 + 6 * e, 6) for e in range(8)], 1) if n else np.zeros((0, 8), np.int64),
+            "child_base": get(244, 24), "n_children": get(268, 4), "n_exits": get(272, 4)}
+
+
+def walk_clustered(dec: dict, X: np.ndarray) -> np.ndarray:
+    """Votes [n, C] from walking a CLUSTERED buffer (vectorised over rows):
+    all seven split outcomes of a block, then the one exit they select."""
+    h = dec["h"]
+    n, C = X.shape[0], h["n_classes"]
+    votes = np.zeros((n, C), np.int32)
+    rows = np.arange(n)
+    fmap = dec["fmap"]
+    for be in dec["bins"]:
+        _, blocks = blocked_bin(dec, be)
+        cf = cluster_fields(blocks) if len(blocks) else None
+        for j in range(int(be["n_trees"])):
+            ref = np.full(n, dec["roots"][be["root_base"] + j], np.int64)
+            while (ref >= 0).any():
+                live = ref >= 0
+                k = np.where(live, ref, 0)
+                g = np.zeros(n, np.int64)
+                for s in range(7):
+                    right = ~(X[rows, fmap[cf["feat"][k, s]]] <= cf["thr"][k, s])
+                    g |= right.astype(np.int64) << s
+                t = np.zeros(n, np.int64)
+                hits = np.zeros(n, np.int64)
+                for e in range(8):
+                    used = e < cf["n_exits"][k]
+                    m = used & (((g ^ cf["val"][k, e]) & cf["care"][k, e]) == 0)
+                    t = np.where(m, cf["target"][k, e], t)
+                    hits += m
+                assert (hits[live] == 1).all(), "exactly one exit per block"
+                nxt = np.where(t & 32, cf["child_base"][k] + (t & 7), -(t & 31) - 1)
+                ref = np.where(live, nxt, ref)
+            np.add.at(votes, (rows, -ref - 1), 1)
+    return votes

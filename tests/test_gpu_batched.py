@@ -28,6 +28,7 @@ SMALL_SPECS = [  # (trees, features, classes, rows, max_depth, bin, depth, tune)
     (30, 50, 7, 777, 12, 8, 2, {"rows_per_block": 16, "tree_groups": 2, "layout": "compact"}),
     (45, 16, 4, 2500, -1, 45, 0, {"rows_per_block": 32, "layout": "blocked"}),
     (26, 33, 9, 999, 14, 5, 3, {"rows_per_block": 8, "tree_groups": 3, "layout": "blocked"}),
+    (37, 25, 6, 1800, -1, 37, 3, {"rows_per_block": 24, "layout": "clustered"}),
 ]
 
 
@@ -37,7 +38,8 @@ def make_job(i, spec):
     f = synth.train_forest(Xt, yt, n_trees=T, n_classes=C, mtry=max(1, int(np.sqrt(F))), max_depth=depth, seed=600 + i)
     X, _ = synth.gaussian_mixture(N, F, C, seed=700 + i)
     tune = dict(tune)
-    layout = {"compact": fp.FP_LAYOUT_COMPACT, "blocked": fp.FP_LAYOUT_BLOCKED}.get(tune.pop("layout", None),
+    layout = {"compact": fp.FP_LAYOUT_COMPACT, "blocked": fp.FP_LAYOUT_BLOCKED,
+              "clustered": fp.FP_LAYOUT_CLUSTERED}.get(tune.pop("layout", None),
                                                                                 fp.FP_LAYOUT_PACKED)
     p = fp.fp_pack_forest(f, layout=layout, bin_size=B, interleave_depth=D)
     fp.fp_packed_upload(p)

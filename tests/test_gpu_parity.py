@@ -87,7 +87,8 @@ TUNES = [
 ]
 
 
-@pytest.mark.parametrize("layout", [fp.FP_LAYOUT_PACKED, fp.FP_LAYOUT_COMPACT, fp.FP_LAYOUT_BLOCKED])
+@pytest.mark.parametrize("layout", [fp.FP_LAYOUT_PACKED, fp.FP_LAYOUT_COMPACT, fp.FP_LAYOUT_BLOCKED,
+                                    fp.FP_LAYOUT_CLUSTERED])
 @pytest.mark.parametrize("tune", TUNES, ids=lambda t: "-".join(f"{k[:4]}{v}" for k, v in t.items()))
 def test_packed_launch_grid(small, tune, layout):
     f, X, want = small
@@ -95,7 +96,7 @@ def test_packed_launch_grid(small, tune, layout):
     assert_same(run(p, X, tune), want, f"layout {layout} {tune}")
 
 
-@pytest.mark.parametrize("layout", [fp.FP_LAYOUT_COMPACT, fp.FP_LAYOUT_BLOCKED])
+@pytest.mark.parametrize("layout", [fp.FP_LAYOUT_COMPACT, fp.FP_LAYOUT_BLOCKED, fp.FP_LAYOUT_CLUSTERED])
 @pytest.mark.parametrize("B", [1, 7, 32])
 @pytest.mark.parametrize("D", [0, 2, 5])
 def test_compact_layout_grid(small, B, D, layout):
@@ -140,7 +141,8 @@ def test_strided_rows_and_special_values(small):
     want = oracle.predict(f, X)
     for kw in ({"layout": fp.FP_LAYOUT_NAIVE}, {"bin_size": 4, "interleave_depth": 5},
                {"layout": fp.FP_LAYOUT_COMPACT, "bin_size": 4, "interleave_depth": 2},
-               {"layout": fp.FP_LAYOUT_BLOCKED, "bin_size": 4, "interleave_depth": 1}):
+               {"layout": fp.FP_LAYOUT_BLOCKED, "bin_size": 4, "interleave_depth": 1},
+               {"layout": fp.FP_LAYOUT_CLUSTERED, "bin_size": 4, "interleave_depth": 3}):
         p = upload(f, **kw)
         assert_same(run(p, X, ld_pad=13), want, f"padded ld {kw}")
         assert_same(run(p, X, {"feature_lds": -1, "rows_per_block": 16}), want, f"global features {kw}")
@@ -161,7 +163,8 @@ def test_degenerate_forests():
                    {"bin_size": 1, "interleave_depth": 3},
                    {"layout": fp.FP_LAYOUT_COMPACT, "bin_size": 4, "interleave_depth": 0},
                    {"layout": fp.FP_LAYOUT_BLOCKED, "bin_size": 4, "interleave_depth": 0},
-                   {"layout": fp.FP_LAYOUT_BLOCKED, "bin_size": 2, "interleave_depth": 2}):
+                   {"layout": fp.FP_LAYOUT_BLOCKED, "bin_size": 2, "interleave_depth": 2},
+                   {"layout": fp.FP_LAYOUT_CLUSTERED, "bin_size": 4, "interleave_depth": 0}):
             assert_same(run(upload(forest, **kw), X, {"rows_per_block": 8, "cursors": 4}), want,
                         f"T={forest.n_trees} {kw}")
 
@@ -179,6 +182,8 @@ def test_image_lite():
                     f"compact B={B} D={D}")
         assert_same(run(upload(f, layout=fp.FP_LAYOUT_BLOCKED, bin_size=B, interleave_depth=D), X, tune), want,
                     f"blocked B={B} D={D}")
+        assert_same(run(upload(f, layout=fp.FP_LAYOUT_CLUSTERED, bin_size=B, interleave_depth=D), X, tune), want,
+                    f"clustered B={B} D={D}")
 
 
 def test_tabular_lite():
@@ -193,6 +198,8 @@ def test_tabular_lite():
                     f"compact B={B} D={D}")
         assert_same(run(upload(f, layout=fp.FP_LAYOUT_BLOCKED, bin_size=B, interleave_depth=D), X), want,
                     f"blocked B={B} D={D}")
+        assert_same(run(upload(f, layout=fp.FP_LAYOUT_CLUSTERED, bin_size=B, interleave_depth=D), X), want,
+                    f"clustered B={B} D={D}")
 
 
 def test_image_full_size_sampled():

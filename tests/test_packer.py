@@ -450,3 +450,97 @@ def test_blocked_verifier_catches_structural_faults(small_forest):
             with pytest.raises(fp.FPError) as e:
                 fp.fp_packed_from_bytes(bad)
             assert e.value.code == fp.FP_ECORRUPT, (h["block_bytes"], i)
+
+
+@pytest.mark.parametrize("B", [1, 5, 32])
+@pytest.mark.parametrize("D", [0, 3, 6])
+def test_clustered_equals_unpacked(small_forest, small_rows, B, D):
+    p = fp.fp_pack_forest(small_forest, layout=fp.FP_LAYOUT_CLUSTERED, bin_size=B, interleave_depth=D)
+    dec = decode(fp.fp_packed_host_bytes(p))
+    assert dec["h"]["layout"] == 4
+    votes, _ = oracle.predict(small_forest, small_rows)
+    assert (walk(dec, small_rows) == votes).all()
+    q = fp.fp_packed_from_bytes(fp.fp_packed_host_bytes(p))
+    assert np.array_equal(fp.fp_packed_host_bytes(q), fp.fp_packed_host_bytes(p))
+
+
+def test_clustered_layout_invariants():
+    """A block holds a connected group of at most 7 internal nodes grown from
+    its root by always taking the frontier node with the most training samples
+    (ties: lower node id); every internal node is in exactly one block; exits
+    partition the outcomes of the block's slots; child blocks are contiguous,
+    after their parent, in descending order of cardinality."""
+    import heapq
+    from packed_format import blocked_bin, cluster_fields
+    f = synth.image(n_train=6000, n_trees=6).forest()
+    X, _ = synth.image(n_train=6000, n_trees=6).predict_rows(300)
+    c = decode(fp.fp_packed_host_bytes(fp.fp_pack_forest(f, layout=fp.FP_LAYOUT_CLUSTERED, bin_size=3,
+                                                          interleave_depth=3)))
+    assert (walk(c, X) == oracle.predict(f, X)[0]).all()
+    seen_nodes = 0
+    for bc in c["bins"]:
+        _, blocks = blocked_bin(c, bc)
+        cf = cluster_fields(blocks)
+        owner = set()
+        for j in range(int(bc["n_trees"])):
+            t = int(bc["first_tree"]) + j
+            off = f.tree_node_offset[t]
+            feat, left, right, card = (f.feature[off:], f.left[off:], f.right[off:], f.cardinality[off:])
+            root = int(c["roots"][bc["root_base"] + j])
+            stack = [(root, 0)] if root >= 0 else []
+            while stack:
+                k, orig = stack.pop()
+                assert k not in owner
+                owner.add(k)
+                # greedy reconstruction of the group from the forest
+                members, front = [], [(-card[orig], orig)]
+                while front and len(members) < 7:
+                    _, nd = heapq.heappop(front)
+                    members.append(nd)
+                    for ch in (left[nd], right[nd]):
+                        if feat[ch] >= 0:
+                            heapq.heappush(front, (-card[ch], ch))
+                m = len(members)
+                assert cf["n_exits"][k] == m + 1
+                for sl, nd in enumerate(members):
+                    assert c["fmap"][cf["feat"][k, sl]] == feat[nd] and cf["thr"][k, sl] == f.threshold[off + nd]
+                assert (cf["feat"][k, m:] == 0).all() and (cf["thr"][k, m:] == 0).all()
+                seen_nodes += m
+                # the exits partition the 2^m outcomes
+                hits = np.zeros(1 << m, np.int64)
+                g = np.arange(1 << m)
+                for e in range(m + 1):
+                    hits += ((g ^ cf["val"][k, e]) & cf["care"][k, e]) == 0
+                assert (hits == 1).all()
+                # child blocks: the internal children outside the group, in exit
+                # order (slot, then side), then hottest first (stable)
+                outside = [ch for nd in members for ch in (left[nd], right[nd]) if feat[ch] >= 0 and ch not in members]
+                assert sorted(outside) == sorted(nd for _, nd in front)
+                kids = sorted(outside, key=lambda nd: -card[nd])
+                ranks = sorted(int(tg & 7) for tg in cf["target"][k, :m + 1] if tg & 32)
+                assert ranks == list(range(len(kids))) and cf["n_children"][k] == len(kids)
+                cards = [card[nd] for nd in kids]
+                assert cards == sorted(cards, reverse=True)
+                for r, nd in enumerate(kids):
+                    child = int(cf["child_base"][k]) + r
+                    assert child > k
+                    stack.append((child, nd))
+        assert owner == set(range(int(bc["deep_len"])))
+    assert seen_nodes == int((f.feature >= 0).sum())
+
+
+def test_clustered_verifier_catches_overlapping_exits(small_forest):
+    from packed_format import BLOCKC, reseal
+    good = fp.fp_packed_host_bytes(fp.fp_pack_forest(small_forest, layout=fp.FP_LAYOUT_CLUSTERED, bin_size=4,
+                                                     interleave_depth=0))
+    dec = decode(good)
+    be = dec["bins"][0]
+    base = dec["h"]["nodes_offset"] + 8 * int(be["node_base"])
+    bad = good.copy()
+    # clear the care bits of exit 0 in block 0: it now matches every outcome
+    word = np.frombuffer(bad[base + 28 + 8:base + 28 + 12].tobytes(), "<u4")[0]  # bits[2] holds bits 64..95
+    word &= ~np.uint32(0x7F << (84 - 64))
+    bad[base + 36:base + 40] = np.frombuffer(np.array([word], "<u4").tobytes(), np.uint8)
+    with pytest.raises(fp.FPError) as e:
+        fp.fp_packed_from_bytes(reseal(bad))
+    assert e.value.code == fp.FP_ECORRUPT
