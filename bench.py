@@ -110,7 +110,10 @@ def serve_leg(fp, synth, np, torch, image_forest, seconds, warm, rate, cache, su
     for name, w, f in workloads:
         f = f if f is not None else w.forest(cache_dir=cache)
         pool, _ = w.rows(65536, w.predict_seed + 1000)
-        p = fp.fp_pack_forest(f, layout=fp.FP_LAYOUT_BLOCKED, bin_size=f.n_trees, interleave_depth=3)
+        try:  # clustered blocks where the forest's fields fit them, else plain blocks
+            p = fp.fp_pack_forest(f, layout=fp.FP_LAYOUT_CLUSTERED, bin_size=f.n_trees, interleave_depth=3)
+        except fp.FPError:
+            p = fp.fp_pack_forest(f, layout=fp.FP_LAYOUT_BLOCKED, bin_size=f.n_trees, interleave_depth=3)
         fp.fp_packed_upload(p)
         fp.fp_packed_set_tune(p, {"rows_per_block": 32, "refill_lanes": 16})
         v, _ = fp.fp_predict(p, torch.from_numpy(pool).cuda())

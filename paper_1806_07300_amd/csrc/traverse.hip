@@ -453,22 +453,31 @@ struct BlockView {
 // Fetches block `ref` of the bin starting at word bb: three (48-byte form) or
 // four (64-byte form) 16-byte loads of one line, issued back to back; the
 // bin's first `ns` blocks come from their LDS copy at piece lb instead.
+// The two sources are typed with their address spaces so that the compiler
+// keeps an LDS read and a global load rather than merging them into one flat
+// load through a selected pointer.
+typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
+typedef __attribute__((address_space(3))) const u32x4 lds_u32x4;
+typedef __attribute__((address_space(1))) const u32x4 global_u32x4;
+
+__device__ __forceinline__ uint4 as_uint4(u32x4 v) { return make_uint4(v.x, v.y, v.z, v.w); }
+
 template <bool B48>
-__device__ __forceinline__ void fetch_block(const uint2* words, const uint4* lds, int32_t bb, int32_t lb, int32_t ns,
-                                            int32_t ref, uint4 (&q)[4]) {
+__device__ __forceinline__ void fetch_block(const uint2* words, const unsigned char* smem_blocks, int32_t bb,
+                                            int32_t lb, int32_t ns, int32_t ref, uint4 (&q)[4]) {
     constexpr int bw = B48 ? 3 : 4;  // 16-byte pieces per block
     if (ref < ns) {
-        const uint4* lp = lds + lb + bw * ref;
-        q[0] = lp[0];
-        q[1] = lp[1];
-        q[2] = lp[2];
-        if (!B48) q[3] = lp[3];
+        const lds_u32x4* lp = (const lds_u32x4*)(smem_blocks) + lb + (int32_t)__umul24((uint32_t)ref, bw);
+        q[0] = as_uint4(lp[0]);
+        q[1] = as_uint4(lp[1]);
+        q[2] = as_uint4(lp[2]);
+        if (!B48) q[3] = as_uint4(lp[3]);
     } else {
-        const uint4* bp = reinterpret_cast<const uint4*>(words + bb + 2 * bw * ref);
-        q[0] = bp[0];
-        q[1] = bp[1];
-        q[2] = bp[2];
-        if (!B48) q[3] = bp[3];
+        const global_u32x4* bp = (const global_u32x4*)(words + bb) + bw * ref;
+        q[0] = as_uint4(bp[0]);
+        q[1] = as_uint4(bp[1]);
+        q[2] = as_uint4(bp[2]);
+        if (!B48) q[3] = as_uint4(bp[3]);
     }
 }
 
@@ -577,7 +586,7 @@ __device__ void run_tile_blocked(const JobDesc& j, int nt, int tile, unsigned ch
         const uint32_t rank = B48 ? (code >> 1) : ((b.ranks >> (4 * e)) & 7u);
         return (int32_t)(b.child_base + rank);
     };
-    const uint4* lds_blocks = reinterpret_cast<const uint4*>(smem + j.off_top);
+    const unsigned char* lds_blocks = smem + j.off_top;
     // per cursor: xrow, vrow = the row's first vote counter, bb = the bin's
     // first block (words), lb / ns = its LDS copy (first piece, blocks held)
     int32_t ref[K], xrow[K], vrow[K], bb[K], lb[K], ns[K];
