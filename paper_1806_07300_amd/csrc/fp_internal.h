@@ -32,7 +32,7 @@ namespace fp {
 // internal children are tree-local ids.
 // ---------------------------------------------------------------------------
 constexpr uint64_t kMagic = 0x314B4341504D5046ull;  // "FPMPACK1"
-constexpr uint32_t kFormatVersion = 3;
+constexpr uint32_t kFormatVersion = 4;
 constexpr size_t kSectionAlign = 256;
 
 struct alignas(16) Node16 {
@@ -100,16 +100,19 @@ constexpr uint32_t kBlock48MaxChildBase = (1u << 24) - 1;
 // 8 edges that leave them ("exits": a leaf's class or a child block).  An
 // exit is selected by the split outcomes of the slots on its path: with g =
 // the 7-bit mask of outcomes (bit s set = slot s goes right), exit e is
-// taken iff (g ^ val[e]) & care[e] == 0; the used exits partition all 128
-// masks, unused ones are all-zero.  bits[] fields (little-endian over
-// bits[0..8]): [0, 84) feature of slot s in 12 bits at 12 s; [84, 140)
-// care[e] in 7 bits at 84 + 7 e; [140, 196) val[e] at 140 + 7 e; [196, 244)
-// target[e] in 6 bits at 196 + 6 e (bit 5 set = child block child_base +
-// bits 0..2, clear = class bits 0..4); [244, 268) child_base; [268, 272)
-// number of child blocks; [272, 276) number of exits.  Absent slots are zero.
+// taken iff (g ^ val[e]) & care[e] == 0.  The used exits partition all 128
+// masks; an unused exit has care = val = 0x80 and never matches (g < 128).
+// care[] and val[] are bytes so that four exits are tested with one 32-bit
+// operation.  rest[] fields (little-endian over rest[0..4]): [0, 48) target
+// of exit e in 6 bits at 6 e (bit 5 set = child block child_base + bits 0..2,
+// clear = class bits 0..4); [48, 132) feature of slot s in 12 bits at
+// 48 + 12 s; [132, 156) child_base; [156, 160) number of child blocks.
+// Absent slots and unused targets are zero.
 struct BlockC64 {
     float thr[7];
-    uint32_t bits[9];
+    uint8_t care[8];
+    uint8_t val[8];
+    uint32_t rest[5];
 };
 static_assert(sizeof(BlockC64) == 64, "block is 64 bytes");
 constexpr int kClusterFeatBits = 12, kClusterMaxClasses = 32;

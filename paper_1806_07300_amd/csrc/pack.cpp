@@ -664,21 +664,25 @@ int pack_blocked(const fp_forest_view* v, const std::vector<TreeShape>& s, const
         *out = BlockC64{};
         auto put = [&](int pos, int width, uint32_t value) {
             for (int i = 0; i < width; i++)
-                if (value >> i & 1u) out->bits[(pos + i) / 32] |= 1u << ((pos + i) % 32);
+                if (value >> i & 1u) out->rest[(pos + i) / 32] |= 1u << ((pos + i) % 32);
         };
         for (int k = 0; k < 7; k++) {
             if (!bk.slot[k].present) continue;
             out->thr[k] = bk.slot[k].thr;
-            put(kClusterFeatBits * k, kClusterFeatBits, bk.slot[k].feat);
+            put(48 + kClusterFeatBits * k, kClusterFeatBits, bk.slot[k].feat);
         }
-        for (uint32_t e = 0; e < bk.n_exits; e++) {
-            put(84 + 7 * (int)e, 7, bk.care[e]);
-            put(140 + 7 * (int)e, 7, bk.val[e]);
-            put(196 + 6 * (int)e, 6, bk.target[e]);
+        for (uint32_t e = 0; e < 8; e++) {
+            if (e < bk.n_exits) {
+                out->care[e] = (uint8_t)bk.care[e];
+                out->val[e] = (uint8_t)bk.val[e];
+                put(6 * (int)e, 6, bk.target[e]);
+            } else {
+                out->care[e] = 0x80;
+                out->val[e] = 0x80;
+            }
         }
-        put(244, 24, bk.n_children ? child_base : 0u);
-        put(268, 4, bk.n_children);
-        put(272, 4, bk.n_exits);
+        put(132, 24, bk.n_children ? child_base : 0u);
+        put(156, 4, bk.n_children);
     };
     // encoders: child_base is the final index of the block's first child
     auto encode64 = [&](const BlockIR& bk, uint32_t child_base, Block64* out) {
@@ -928,34 +932,36 @@ int verify_buffer(const uint8_t* bytes, size_t n, std::string* why) {
                     const BlockC64& bk = blk[k];
                     auto get = [&](int pos, int width) -> uint32_t {
                         uint32_t v = 0;
-                        for (int i = 0; i < width; i++) v |= ((bk.bits[(pos + i) / 32] >> ((pos + i) % 32)) & 1u) << i;
+                        for (int i = 0; i < width; i++) v |= ((bk.rest[(pos + i) / 32] >> ((pos + i) % 32)) & 1u) << i;
                         return v;
                     };
-                    const uint32_t n_child = get(268, 4), n_exit = get(272, 4);
-                    const int64_t child_base = get(244, 24);
-                    if (n_exit < 2 || n_exit > 8 || n_child > n_exit || get(276, 12) != 0 || (bk.bits[8] >> 24) != 0)
+                    const uint32_t n_child = get(156, 4);
+                    const int64_t child_base = get(132, 24);
+                    uint32_t n_exit = 0;
+                    while (n_exit < 8 && bk.care[n_exit] != 0x80) n_exit++;
+                    if (n_exit < 2 || n_child > n_exit)
                         return bad("bin %d block %lld: exit counts", b, (long long)k);
                     if (n_child ? (child_base <= k || child_base + n_child > be.deep_len) : child_base != 0)
                         return bad("bin %d block %lld: child blocks", b, (long long)k);
                     const uint32_t n_slot = n_exit - 1;  // a binary tree of m nodes has m + 1 exits
                     for (uint32_t sl = 0; sl < 7; sl++) {
-                        const uint32_t f = get(fp::kClusterFeatBits * (int)sl, fp::kClusterFeatBits);
+                        const uint32_t f = get(48 + fp::kClusterFeatBits * (int)sl, fp::kClusterFeatBits);
                         if (sl < n_slot ? (int64_t)f >= F : (f != 0 || bk.thr[sl] != 0.0f))
                             return bad("bin %d block %lld slot %u", b, (long long)k, sl);
                     }
                     // used exits: targets in range, and their outcome patterns
                     // partition the 2^n_slot masks (pairwise disjoint, sizes sum)
-                    uint32_t care[8], val[8], child_used = 0;
+                    uint32_t child_used = 0;
                     int64_t covered = 0;
                     for (uint32_t e = 0; e < 8; e++) {
-                        care[e] = get(84 + 7 * (int)e, 7);
-                        val[e] = get(140 + 7 * (int)e, 7);
-                        const uint32_t tgt = get(196 + 6 * (int)e, 6);
+                        const uint32_t care = bk.care[e], val = bk.val[e];
+                        const uint32_t tgt = get(6 * (int)e, 6);
                         if (e >= n_exit) {
-                            if (care[e] | val[e] | tgt) return bad("bin %d block %lld: stray exit %u", b, (long long)k, e);
+                            if (care != 0x80 || val != 0x80 || tgt)
+                                return bad("bin %d block %lld: stray exit %u", b, (long long)k, e);
                             continue;
                         }
-                        if ((val[e] & ~care[e]) || (care[e] >> n_slot) || care[e] == 0)
+                        if ((val & ~care) || (care >> n_slot) || care == 0)
                             return bad("bin %d block %lld exit %u pattern", b, (long long)k, e);
                         if (tgt & 32u) {
                             if ((tgt & 31u) >= n_child) return bad("bin %d block %lld exit %u child", b, (long long)k, e);
@@ -963,9 +969,9 @@ int verify_buffer(const uint8_t* bytes, size_t n, std::string* why) {
                         } else if ((int64_t)tgt >= C) {
                             return bad("bin %d block %lld exit %u class", b, (long long)k, e);
                         }
-                        covered += (int64_t)1 << (n_slot - __builtin_popcount(care[e]));
+                        covered += (int64_t)1 << (n_slot - __builtin_popcount(care));
                         for (uint32_t d = 0; d < e; d++)
-                            if (((val[e] ^ val[d]) & care[e] & care[d]) == 0)
+                            if (((val ^ bk.val[d]) & care & bk.care[d]) == 0)
                                 return bad("bin %d block %lld exits %u and %u overlap", b, (long long)k, d, e);
                     }
                     if (covered != ((int64_t)1 << n_slot) || child_used != (n_child ? (1u << n_child) - 1u : 0u))

@@ -508,41 +508,45 @@ __device__ __forceinline__ BlockView view_block(const uint4 (&q)[4]) {
     return b;
 }
 
-// Field [pos, pos + width) of the 288 bits b[0..8] of a CLUSTERED block
+// Field [pos, pos + width) of the 160 bits r[0..4] of a CLUSTERED block
 // (positions are compile-time constants, so this is one or two ALU ops).
 template <int pos, int width>
-__device__ __forceinline__ uint32_t cfield(const uint32_t (&b)[9]) {
-    constexpr uint32_t mask = width == 32 ? ~0u : (1u << width) - 1u;
-    if constexpr (pos % 32 + width <= 32) return (b[pos / 32] >> (pos % 32)) & mask;
-    else return __builtin_amdgcn_alignbit(b[pos / 32 + 1], b[pos / 32], pos % 32) & mask;
+__device__ __forceinline__ uint32_t cfield(const uint32_t (&r)[5]) {
+    constexpr uint32_t mask = (1u << width) - 1u;
+    if constexpr (pos % 32 + width <= 32) return (r[pos / 32] >> (pos % 32)) & mask;
+    else return __builtin_amdgcn_alignbit(r[pos / 32 + 1], r[pos / 32], pos % 32) & mask;
+}
+
+// Bytes of x that are zero get bit 7 set, the others clear (bytes < 0x80
+// or with bit 7 set; no carry crosses a byte).
+__device__ __forceinline__ uint32_t zero_bytes(uint32_t x) {
+    return ~(((x & 0x7F7F7F7Fu) + 0x7F7F7F7Fu) | x) & 0x80808080u;
 }
 
 // CLUSTERED block: reads the seven split outcomes (one LDS round trip, as in
-// the BLOCKED walk) and returns the next reference: the child block or the
-// class of the one exit whose outcome pattern matches.
+// the BLOCKED walk), tests four exits per 32-bit operation against the
+// outcome mask replicated into every byte, and returns the next reference:
+// the child block or the class of the one exit whose pattern matches.
 template <typename Le>
 __device__ __forceinline__ int32_t cluster_step(const uint4 (&q)[4], int32_t xrow, Le&& le) {
     const float thr[7] = {__uint_as_float(q[0].x), __uint_as_float(q[0].y), __uint_as_float(q[0].z),
                           __uint_as_float(q[0].w), __uint_as_float(q[1].x), __uint_as_float(q[1].y),
                           __uint_as_float(q[1].z)};
-    const uint32_t b[9] = {q[1].w, q[2].x, q[2].y, q[2].z, q[2].w, q[3].x, q[3].y, q[3].z, q[3].w};
-    const uint32_t f[7] = {cfield<0, 12>(b), cfield<12, 12>(b), cfield<24, 12>(b), cfield<36, 12>(b),
-                           cfield<48, 12>(b), cfield<60, 12>(b), cfield<72, 12>(b)};
+    const uint32_t care_lo = q[1].w, care_hi = q[2].x, val_lo = q[2].y, val_hi = q[2].z;
+    const uint32_t r[5] = {q[2].w, q[3].x, q[3].y, q[3].z, q[3].w};
+    const uint32_t f[7] = {cfield<48, 12>(r), cfield<60, 12>(r), cfield<72, 12>(r), cfield<84, 12>(r),
+                           cfield<96, 12>(r), cfield<108, 12>(r), cfield<120, 12>(r)};
     uint32_t g = 0;
 #pragma unroll
     for (int sl = 0; sl < 7; sl++) g |= (le(xrow, f[sl], thr[sl]) ? 0u : 1u) << sl;
-    uint32_t t = 0;
-#define FP_EXIT(e)                                                                                       \
-    {                                                                                                    \
-        const uint32_t care = cfield<84 + 7 * e, 7>(b), val = cfield<140 + 7 * e, 7>(b);                \
-        t |= ((g ^ val) & care) == 0 ? cfield<196 + 6 * e, 6>(b) : 0u;                                   \
-    }
-    FP_EXIT(0) FP_EXIT(1) FP_EXIT(2) FP_EXIT(3) FP_EXIT(4) FP_EXIT(5) FP_EXIT(6) FP_EXIT(7)
-#undef FP_EXIT
-    // unused exits are all-zero and add nothing; a verified block's used exits
-    // partition the outcomes, so exactly one contributes
-    const uint32_t n_child = cfield<268, 4>(b);
-    return (t & 32u) ? (int32_t)(cfield<244, 24>(b) + min(t & 7u, n_child - 1u)) : ~(int32_t)(t & 31u);
+    const uint32_t g4 = __umul24(g, 0x010101u) | (g << 24);  // g in every byte (24-bit multiply: full rate)
+    const uint32_t z_lo = zero_bytes((g4 ^ val_lo) & care_lo), z_hi = zero_bytes((g4 ^ val_hi) & care_hi);
+    // a verified block's used exits partition the outcomes: exactly one byte is zero
+    const uint32_t e = z_lo ? (uint32_t)__builtin_ctz(z_lo) >> 3 : 4u + ((uint32_t)__builtin_ctz(z_hi | 0x80000000u) >> 3);
+    const uint64_t targets = ((uint64_t)r[1] << 32) | r[0];
+    const uint32_t t = (uint32_t)(targets >> (6 * e)) & 63u;
+    const uint32_t n_child = cfield<156, 4>(r);
+    return (t & 32u) ? (int32_t)(cfield<132, 24>(r) + min(t & 7u, n_child - 1u)) : ~(int32_t)(t & 31u);
 }
 
 // BLOCKED layout walk.  Every reference is a block of the bin (or a class).

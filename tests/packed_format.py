@@ -132,7 +132,7 @@ def walk_compact(dec: dict, X: np.ndarray) -> np.ndarray:
 BLOCK = np.dtype({"names": ["child_base", "ranks", "slot"],
                   "formats": ["<u4", "<u4", np.dtype((NODE8, 7))]})
 BLOCK48 = np.dtype([("words", "<u4", 5), ("thr", "<f4", 7)])
-BLOCKC = np.dtype([("thr", "<f4", 7), ("bits", "<u4", 9)])
+BLOCKC = np.dtype([("thr", "<f4", 7), ("care", "u1", 8), ("val", "u1", 8), ("rest", "<u4", 5)])
 WORD48_BITS = 19
 
 
@@ -234,16 +234,17 @@ def reseal(buf: np.ndarray) -> np.ndarray:
 
 def cluster_fields(blocks):
     """CLUSTERED blocks as plain arrays: thr [n, 7], feat [n, 7], care, val,
-    target [n, 8], child_base, n_children, n_exits [n]."""
+    target [n, 8], child_base, n_children, n_exits [n] (unused exits have
+    care = val = 0x80)."""
     n = len(blocks)
-    big = [sum(int(w) << (32 * i) for i, w in enumerate(row)) for row in blocks["bits"]]
+    big = [sum(int(w) << (32 * i) for i, w in enumerate(row)) for row in blocks["rest"]]
     get = lambda pos, width: np.array([(v >> pos) & ((1 << width) - 1) for v in big], np.int64).reshape(n)
+    care = blocks["care"].astype(np.int64)
     return {"thr": blocks["thr"],
-            "feat": np.stack([get(12 * s, 12) for s in range(7)], 1) if n else np.zeros((0, 7), np.int64),
-            "care": np.stack([get(84 + 7 * e, 7) for e in range(8)], 1) if n else np.zeros((0, 8), np.int64),
-            "val": np.stack([get(140 + 7 * e, 7) for e in range(8)], 1) if n else np.zeros((0, 8), np.int64),
-            "target": np.stack([get(196 + 6 * e, 6) for e in range(8)], 1) if n else np.zeros((0, 8), np.int64),
-            "child_base": get(244, 24), "n_children": get(268, 4), "n_exits": get(272, 4)}
+            "feat": np.stack([get(48 + 12 * s, 12) for s in range(7)], 1) if n else np.zeros((0, 7), np.int64),
+            "care": care, "val": blocks["val"].astype(np.int64),
+            "target": np.stack([get(6 * e, 6) for e in range(8)], 1) if n else np.zeros((0, 8), np.int64),
+            "child_base": get(132, 24), "n_children": get(156, 4), "n_exits": (care != 0x80).sum(1)}
 
 
 def walk_clustered(dec: dict, X: np.ndarray) -> np.ndarray:

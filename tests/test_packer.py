@@ -530,17 +530,20 @@ def test_clustered_layout_invariants():
 
 
 def test_clustered_verifier_catches_overlapping_exits(small_forest):
-    from packed_format import BLOCKC, reseal
+    from packed_format import reseal
     good = fp.fp_packed_host_bytes(fp.fp_pack_forest(small_forest, layout=fp.FP_LAYOUT_CLUSTERED, bin_size=4,
                                                      interleave_depth=0))
     dec = decode(good)
     be = dec["bins"][0]
     base = dec["h"]["nodes_offset"] + 8 * int(be["node_base"])
+    faults = []
     bad = good.copy()
-    # clear the care bits of exit 0 in block 0: it now matches every outcome
-    word = np.frombuffer(bad[base + 28 + 8:base + 28 + 12].tobytes(), "<u4")[0]  # bits[2] holds bits 64..95
-    word &= ~np.uint32(0x7F << (84 - 64))
-    bad[base + 36:base + 40] = np.frombuffer(np.array([word], "<u4").tobytes(), np.uint8)
-    with pytest.raises(fp.FPError) as e:
-        fp.fp_packed_from_bytes(reseal(bad))
-    assert e.value.code == fp.FP_ECORRUPT
+    bad[base + 28] = 0x01  # exit 0 tests only slot 0: it now overlaps another exit
+    faults.append(bad)
+    bad = good.copy()
+    bad[base + 28 + 7] = 0x00  # an unused exit (care 0x80) that would match everything
+    faults.append(bad)
+    for i, bad in enumerate(faults):
+        with pytest.raises(fp.FPError) as e:
+            fp.fp_packed_from_bytes(reseal(bad))
+        assert e.value.code == fp.FP_ECORRUPT, i
