@@ -191,7 +191,10 @@ struct JobDesc {
     int32_t fbits, cbits;      // COMPACT / BLOCKED field widths
     int32_t refill_min;        // idle lanes of a wavefront that trigger a refill
     int32_t block_bytes;       // BLOCKED: 48 or 64
-    int32_t pad3;
+    int32_t F;                 // feature columns of a row (the forest's n_features)
+    int32_t stage_rows;        // 1: stage tiles with whole-row 16-byte loads through imap
+    int32_t off_imap;          // LDS: column -> compacted feature (int16, -1 unused), 4 * ceil(F / 4) entries
+    int32_t pad4;
 };
 
 // One entry of the batched work list: tiles [tile_begin, tile_end) of job

@@ -167,7 +167,35 @@ __device__ __forceinline__ void refill(int32_t (&ref)[K], int32_t* pool, int U, 
 __device__ __forceinline__ void stage_tile(const JobDesc& j, float* xs, int32_t* vl, int32_t* pool, int64_t row0,
                                            int rows, bool feat_lds) {
     const int tid = threadIdx.x, bd = blockDim.x;
-    if (feat_lds) {
+    if (feat_lds && j.stage_rows) {
+        // whole rows in 16-byte loads; each used column goes to its compacted
+        // slot (imap, 4 entries per 8-byte LDS read; -1 = unused)
+        const int Q = (j.F + 3) / 4;
+        const int16_t* imap = reinterpret_cast<const int16_t*>(reinterpret_cast<const unsigned char*>(xs) - j.off_xs +
+                                                               j.off_imap);
+        const int dq = bd / Q, dc = bd - dq * Q;
+        int r = tid / Q, qd = tid - r * Q;
+        const float4* xrow = reinterpret_cast<const float4*>(j.X + (row0 + r) * j.ld);
+        const int64_t ld4 = j.ld / 4, dld4 = (int64_t)dq * ld4;
+        while (r < rows) {
+            const float4 v = xrow[qd];
+            const int2 m2 = *reinterpret_cast<const int2*>(imap + 4 * qd);
+            const int m0 = (int16_t)(m2.x & 0xFFFF), m1 = m2.x >> 16, m2v = (int16_t)(m2.y & 0xFFFF), m3 = m2.y >> 16;
+            float* dst = xs + r * j.Fcp;
+            if (m0 >= 0) dst[m0] = v.x;
+            if (m1 >= 0) dst[m1] = v.y;
+            if (m2v >= 0) dst[m2v] = v.z;
+            if (m3 >= 0) dst[m3] = v.w;
+            r += dq;
+            xrow += dld4;
+            qd += dc;
+            if (qd >= Q) {
+                qd -= Q;
+                r += 1;
+                xrow += ld4;
+            }
+        }
+    } else if (feat_lds) {
         const int Fc = j.Fc;
         const int dq = bd / Fc, dc = bd - dq * Fc;
         int r = tid / Fc, c = tid - r * Fc;
@@ -273,6 +301,14 @@ __device__ int stage_group(const JobDesc& j, int group, unsigned char* smem) {
     if (!j.feat_lds) {
         int32_t* fmap_l = reinterpret_cast<int32_t*>(smem + j.off_fmap);
         for (int c = tid; c < j.Fc; c += bd) fmap_l[c] = j.fmap[c];
+    }
+    if (j.stage_rows) {
+        int16_t* imap = reinterpret_cast<int16_t*>(smem + j.off_imap);
+        const int n_imap = (j.F + 3) / 4 * 4;
+        for (int c = tid; c < n_imap; c += bd) imap[c] = -1;
+        __syncthreads();
+        for (int i = tid; i < j.Fc; i += bd) imap[j.fmap[i]] = (int16_t)i;
+        __syncthreads();  // the first tile's staging reads imap
     }
     return nt;
 }
@@ -873,6 +909,7 @@ size_t job_lds_layout(JobDesc* j) {
     j->off_top = (int32_t)o;   o += (size_t)j->cap * j->bins_per_group * sizeof(Node16);
     j->off_ttab = (int32_t)o;  o += (size_t)j->trees_per_group * 16;
     j->off_fmap = (int32_t)o;  o += j->feat_lds ? 0 : round16((size_t)j->Fc * 4);
+    j->off_imap = (int32_t)o;  o += j->stage_rows ? round16((size_t)(j->F + 3) / 4 * 4 * 2) : 0;
     j->off_xs = (int32_t)o;    o += j->feat_lds ? round16((size_t)j->R * j->Fcp * 4) : 0;
     j->off_votes = (int32_t)o; o += round16((size_t)j->R * j->C * 4);
     j->off_pool = (int32_t)o;  o += 16;
@@ -930,6 +967,9 @@ int resolve_job(const fp_packed* p, const fp_tune* t, const float* X, int64_t n_
     j->refill_min = t->refill_lanes > 0 ? t->refill_lanes : kDefaultRefillLanes;
     // feature_lds: 1 force LDS staging, -1 read features from memory, 0 automatic
     j->feat_lds = t->feature_lds >= 0;
+    j->F = h.n_features;
+    // whole-row staging: rows start on 16 bytes and the column map fits 8 KB
+    j->stage_rows = j->feat_lds && ld % 4 == 0 && reinterpret_cast<uintptr_t>(X) % 16 == 0 && h.n_features <= 4096;
     j->cap = 0;
     size_t need = job_lds_layout(j);
     if (need > lds_block) {
@@ -937,6 +977,7 @@ int resolve_job(const fp_packed* p, const fp_tune* t, const float* X, int64_t n_
             return fp_set_error(FP_E2BIG, "observation tile of %d rows x %d columns does not fit in %zu bytes of LDS",
                                 R, j->Fc, lds_block);
         j->feat_lds = 0;
+        j->stage_rows = 0;
         need = job_lds_layout(j);
         if (need > lds_block)
             return fp_set_error(FP_E2BIG, "per-workgroup tables of %zu bytes exceed %zu bytes of LDS", need, lds_block);

@@ -223,3 +223,18 @@ def test_image_full_size_sampled():
     assert np.array_equal(v[rows], want_v) and np.array_equal(c[rows], want_c)
     assert np.array_equal(vn[rows], want_v) and np.array_equal(cn[rows], want_c)
     assert np.array_equal(v, vn) and np.array_equal(c, cn)
+
+
+@pytest.mark.parametrize("F,pad", [(30, 2), (31, 1), (29, 7), (13, 3), (30, 0)])
+def test_row_staging_ragged_columns(F, pad):
+    """Whole-row tile staging (16-byte row loads, rows 16-byte aligned) with a
+    column count that is not a multiple of 4, padded leading dimensions, and
+    the unaligned fallback (pad 0 with F % 4 != 0)."""
+    X, y = synth.gaussian_mixture(4000, F, 3, seed=900 + F)
+    f = synth.train_forest(X, y, n_trees=12, n_classes=3, mtry=max(1, F // 3), max_depth=10, seed=901 + F)
+    Xq, _ = synth.gaussian_mixture(3001, F, 3, seed=902 + F)
+    want = oracle.predict(f, Xq)
+    for layout in (fp.FP_LAYOUT_PACKED, fp.FP_LAYOUT_BLOCKED, fp.FP_LAYOUT_CLUSTERED):
+        p = upload(f, layout=layout, bin_size=12, interleave_depth=3)
+        assert_same(run(p, Xq, {"rows_per_block": 32, "cursors": 1, "block_threads": 512}, ld_pad=pad), want,
+                    f"F={F} pad={pad} layout={layout}")
