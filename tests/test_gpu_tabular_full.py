@@ -1,5 +1,5 @@
 """The full-size tabular workload (28 features, 1,024 trees grown on 1,000,000
-rows, 10,000,000 rows predicted, bins of 16 trees, PACKED and BLOCKED layouts)
+rows, 10,000,000 rows predicted, bins of 16 trees, PACKED, BLOCKED and CLUSTERED layouts)
 on the GPU, checked against the CPU checker on sampled rows and against the
 naive layout on every row.  Training the forest takes minutes of host CPU, so the test runs only
 with FP_FULL_TABULAR=1 (it prints training progress)."""
@@ -39,8 +39,8 @@ def test_tabular_full_size():
              {"rows_per_block": 32, "cursors": 4, "block_threads": 1024}),
             ("blocked", {"layout": fp.FP_LAYOUT_BLOCKED, "bin_size": 16, "interleave_depth": 3},
              {"rows_per_block": 256, "cursors": 1, "block_threads": 1024, "refill_lanes": 32}),
-            ("blocked-r64", {"layout": fp.FP_LAYOUT_BLOCKED, "bin_size": 16, "interleave_depth": 3},
-             {"rows_per_block": 64, "cursors": 1, "block_threads": 1024, "refill_lanes": 32}),
+            ("clustered", {"layout": fp.FP_LAYOUT_CLUSTERED, "bin_size": 16, "interleave_depth": 3},
+             {"rows_per_block": 256, "cursors": 1, "block_threads": 1024, "refill_lanes": 32}),
             ("naive", {"layout": fp.FP_LAYOUT_NAIVE}, {"block_threads": 256}))
     for name, kw, tune in runs:
         p = fp.fp_pack_forest(f, **kw)
@@ -61,7 +61,7 @@ def test_tabular_full_size():
         del p
     v, c = out["packed"]
     assert (v.sum(1) == f.n_trees).all()
-    for name in ("packed", "blocked", "blocked-r64"):
+    for name in ("packed", "blocked", "clustered"):
         assert np.array_equal(out[name][0], out["naive"][0]) and np.array_equal(out[name][1], out["naive"][1]), name
     rows = np.unique(np.concatenate([[0, n - 1], np.random.default_rng(11).integers(0, n, 10_000)]))
     wv, wc = oracle.predict(f, X[rows])
