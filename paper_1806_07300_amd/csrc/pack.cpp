@@ -56,7 +56,11 @@ int fp_set_error(int code, const char* fmt, ...) {
 void fp_clear_error() { g_last_error.clear(); }
 
 extern "C" const char* fp_last_error(void) { return g_last_error.c_str(); }
-extern "C" const char* fp_version(void) { return "forestpack 0.1 packed-format 1"; }
+#define FP_STR2(x) #x
+#define FP_STR(x) FP_STR2(x)
+#define FP_FORMAT_VERSION 4
+static_assert(FP_FORMAT_VERSION == fp::kFormatVersion, "version string follows the format");
+extern "C" const char* fp_version(void) { return "forestpack 0.2 packed-format " FP_STR(FP_FORMAT_VERSION); }
 
 namespace fp {
 
