@@ -128,12 +128,16 @@ enum {
      * Needs feature and class fields to fit 32 bits (FP_E2BIG otherwise);
      * line_align is ignored. */
     FP_LAYOUT_BLOCKED = 3,
-    /* Like BLOCKED, but a 64-byte block holds the up to 7 most visited nodes
+    /* Like BLOCKED, but a block holds the up to 7 most visited nodes
      * reachable from its root (chosen greedily by training cardinality: the
      * hot paths of Stat, grouped into one fetch) instead of a fixed
      * three-level subtree, with a table that maps the 7 split outcomes to
-     * the block's exit.  Needs at most 4,096 used features and 32 classes
-     * (FP_E2BIG otherwise); line_align is ignored. */
+     * the block's exit.  A block takes 48 bytes when at most 512 features
+     * are used and every threshold of the forest is exactly an fp16 value
+     * (stored as fp16, widened to the same fp32 value before the compare;
+     * e.g. pixel data with half-integer thresholds), else 64 bytes.  Needs
+     * at most 4,096 used features and 32 classes (FP_E2BIG otherwise);
+     * line_align is ignored. */
     FP_LAYOUT_CLUSTERED = 4
 };
 

@@ -32,7 +32,7 @@ namespace fp {
 // internal children are tree-local ids.
 // ---------------------------------------------------------------------------
 constexpr uint64_t kMagic = 0x314B4341504D5046ull;  // "FPMPACK1"
-constexpr uint32_t kFormatVersion = 4;
+constexpr uint32_t kFormatVersion = 5;
 constexpr size_t kSectionAlign = 256;
 
 struct alignas(16) Node16 {
@@ -116,6 +116,24 @@ struct BlockC64 {
 };
 static_assert(sizeof(BlockC64) == 64, "block is 64 bytes");
 constexpr int kClusterFeatBits = 12, kClusterMaxClasses = 32;
+
+// The 48-byte form of a CLUSTERED block, used when every threshold of the
+// forest converts to fp16 and back unchanged (integer-valued features split
+// at half-integers, for example) and at most 512 features are used: the
+// same exits, with thr16[s] the fp16 bits of slot s's threshold, and rest
+// fields (little-endian over rest[0..3], then the upper half of thr16 word 3
+// as bits [128, 144)): [0, 48) targets as in BlockC64; [48, 111) feature of
+// slot s in 9 bits at 48 + 9 s; [111, 135) child_base; [135, 139) number of
+// child blocks.
+struct BlockC48 {
+    uint16_t thr16[7];
+    uint16_t rest_hi;  // bits [128, 144) of rest
+    uint8_t care[8];
+    uint8_t val[8];
+    uint32_t rest[4];
+};
+static_assert(sizeof(BlockC48) == 48, "block is 48 bytes");
+constexpr int kCluster48FeatBits = 9;
 
 struct BinEntry {
     int64_t node_base;   // first node of the bin in the node array

@@ -24,6 +24,7 @@
 #include <algorithm>
 #include <cstdarg>
 #include <cstdio>
+#include <cmath>
 #include <cstring>
 #include <deque>
 #include <memory>
@@ -36,6 +37,7 @@ using fp::Header;
 using fp::Node16;
 using fp::Node8;
 using fp::Block48;
+using fp::BlockC48;
 using fp::BlockC64;
 using fp::Block64;
 
@@ -58,7 +60,7 @@ void fp_clear_error() { g_last_error.clear(); }
 extern "C" const char* fp_last_error(void) { return g_last_error.c_str(); }
 #define FP_STR2(x) #x
 #define FP_STR(x) FP_STR2(x)
-#define FP_FORMAT_VERSION 4
+#define FP_FORMAT_VERSION 5
 static_assert(FP_FORMAT_VERSION == fp::kFormatVersion, "version string follows the format");
 extern "C" const char* fp_version(void) { return "forestpack 0.2 packed-format " FP_STR(FP_FORMAT_VERSION); }
 
@@ -517,6 +519,14 @@ int pack_blocked(const fp_forest_view* v, const std::vector<TreeShape>& s, const
     // 48-byte blocks when a node word fits 19 bits and every bin has fewer
     // than 2^24 blocks (checked below; the packing restarts in 64-byte form)
     bool use48 = !clustered && fb + 2 * (1 + P) <= kBlock48WordBits;
+    if (clustered) {  // 48-byte clustered blocks: 9-bit features, thresholds exact in fp16
+        use48 = fb <= kCluster48FeatBits;
+        for (int64_t i = 0; use48 && i < v->tree_node_offset[T]; i++)
+            if (v->feature[i] >= 0) {
+                const float t = v->threshold[i];
+                use48 = (float)(_Float16)t == t && !std::isnan(t);
+            }
+    }
 
     // One tree's blocks in breadth-first order: the subtree root node of each
     // block, its level, and its slots; child blocks are found by bfs index.
@@ -664,6 +674,34 @@ int pack_blocked(const fp_forest_view* v, const std::vector<TreeShape>& s, const
             tb->body.push_back(bk);
         }
     };
+    auto encodeC48 = [&](const BlockIR& bk, uint32_t child_base, BlockC48* out) {
+        *out = BlockC48{};
+        uint32_t r[5] = {0, 0, 0, 0, 0};
+        auto put = [&](int pos, int width, uint32_t value) {
+            for (int i = 0; i < width; i++)
+                if (value >> i & 1u) r[(pos + i) / 32] |= 1u << ((pos + i) % 32);
+        };
+        for (int k = 0; k < 7; k++) {
+            if (!bk.slot[k].present) continue;
+            const _Float16 h16 = (_Float16)bk.slot[k].thr;
+            memcpy(&out->thr16[k], &h16, 2);
+            put(48 + kCluster48FeatBits * k, kCluster48FeatBits, bk.slot[k].feat);
+        }
+        for (uint32_t e = 0; e < 8; e++) {
+            if (e < bk.n_exits) {
+                out->care[e] = (uint8_t)bk.care[e];
+                out->val[e] = (uint8_t)bk.val[e];
+                put(6 * (int)e, 6, bk.target[e]);
+            } else {
+                out->care[e] = 0x80;
+                out->val[e] = 0x80;
+            }
+        }
+        put(111, 24, bk.n_children ? child_base : 0u);
+        put(135, 4, bk.n_children);
+        for (int i = 0; i < 4; i++) out->rest[i] = r[i];
+        out->rest_hi = (uint16_t)r[4];
+    };
     auto encodeC = [&](const BlockIR& bk, uint32_t child_base, BlockC64* out) {
         *out = BlockC64{};
         auto put = [&](int pos, int width, uint32_t value) {
@@ -779,7 +817,8 @@ restart:
                 const BlockIR& bk = tb[j].body[q];
                 const uint32_t child_base = bk.n_children ? (uint32_t)pos[j][bk.first_child] : 0u;
                 uint8_t* dst = bl.data() + (size_t)pos[j][q] * 8 * block_words;
-                if (clustered) encodeC(bk, child_base, reinterpret_cast<BlockC64*>(dst));
+                if (clustered && use48) encodeC48(bk, child_base, reinterpret_cast<BlockC48*>(dst));
+                else if (clustered) encodeC(bk, child_base, reinterpret_cast<BlockC64*>(dst));
                 else if (use48) encode48(bk, child_base, reinterpret_cast<Block48*>(dst));
                 else encode64(bk, child_base, reinterpret_cast<Block64*>(dst));
             }
@@ -887,8 +926,9 @@ int verify_buffer(const uint8_t* bytes, size_t n, std::string* why) {
          h.compact_fbits + 2 * (1 + h.compact_cbits) > 32 || (h.block_bytes != 48 && h.block_bytes != 64) ||
          (h.block_bytes == 48 && h.compact_fbits + 2 * (1 + std::max(h.compact_cbits, 3)) > fp::kBlock48WordBits)))
         return bad("blocked node section or field widths");
-    if (clustered && (h.nodes_offset + 8 * N > (int64_t)n || h.block_bytes != 64 || h.compact_fbits < 1 ||
-                      h.compact_fbits > fp::kClusterFeatBits || C > fp::kClusterMaxClasses))
+    if (clustered && (h.nodes_offset + 8 * N > (int64_t)n || (h.block_bytes != 64 && h.block_bytes != 48) ||
+                      h.compact_fbits < 1 || C > fp::kClusterMaxClasses ||
+                      h.compact_fbits > (h.block_bytes == 48 ? fp::kCluster48FeatBits : fp::kClusterFeatBits)))
         return bad("clustered node section or field widths");
     const int64_t block_words = h.block_bytes == 48 ? 6 : 8;
     if (h.n_bins < 1 || h.table_offset + (int64_t)sizeof(BinEntry) * h.n_bins > h.roots_offset ||
@@ -931,16 +971,46 @@ int verify_buffer(const uint8_t* bytes, size_t n, std::string* why) {
             const Node8* words = reinterpret_cast<const Node8*>(bytes + h.nodes_offset) + be.node_base;
             const int fb = h.compact_fbits, cb = h.compact_cbits;
             if (clustered) {
-                const BlockC64* blk = reinterpret_cast<const BlockC64*>(words);
+                const bool c48 = h.block_bytes == 48;
+                const int fw = c48 ? fp::kCluster48FeatBits : fp::kClusterFeatBits;
+                const int p_feat = 48, p_base = c48 ? 111 : 132, p_nchild = c48 ? 135 : 156, p_end = c48 ? 139 : 160;
                 for (int64_t k = 0; k < be.deep_len; k++) {
-                    const BlockC64& bk = blk[k];
+                    const uint8_t* raw = reinterpret_cast<const uint8_t*>(words) + k * h.block_bytes;
+                    uint32_t rest[5];
+                    float thr[7];
+                    const uint8_t *care_b, *val_b;
+                    if (c48) {
+                        const fp::BlockC48& b48 = *reinterpret_cast<const fp::BlockC48*>(raw);
+                        for (int i = 0; i < 4; i++) rest[i] = b48.rest[i];
+                        rest[4] = b48.rest_hi;
+                        for (int sl = 0; sl < 7; sl++) {
+                            _Float16 t16;
+                            memcpy(&t16, &b48.thr16[sl], 2);
+                            thr[sl] = (float)t16;
+                            if (std::isnan(thr[sl])) return bad("bin %d block %lld: NaN threshold", b, (long long)k);
+                        }
+                        care_b = b48.care;
+                        val_b = b48.val;
+                    } else {
+                        const BlockC64& b64 = *reinterpret_cast<const BlockC64*>(raw);
+                        for (int i = 0; i < 5; i++) rest[i] = b64.rest[i];
+                        for (int sl = 0; sl < 7; sl++) thr[sl] = b64.thr[sl];
+                        care_b = b64.care;
+                        val_b = b64.val;
+                    }
+                    struct View {
+                        const float* thr;
+                        const uint8_t *care, *val;
+                    } bk{thr, care_b, val_b};
                     auto get = [&](int pos, int width) -> uint32_t {
                         uint32_t v = 0;
-                        for (int i = 0; i < width; i++) v |= ((bk.rest[(pos + i) / 32] >> ((pos + i) % 32)) & 1u) << i;
+                        for (int i = 0; i < width; i++) v |= ((rest[(pos + i) / 32] >> ((pos + i) % 32)) & 1u) << i;
                         return v;
                     };
-                    const uint32_t n_child = get(156, 4);
-                    const int64_t child_base = get(132, 24);
+                    if (c48 ? (rest[4] >> (p_end - 128)) != 0 : false)
+                        return bad("bin %d block %lld: stray bits", b, (long long)k);
+                    const uint32_t n_child = get(p_nchild, 4);
+                    const int64_t child_base = get(p_base, 24);
                     uint32_t n_exit = 0;
                     while (n_exit < 8 && bk.care[n_exit] != 0x80) n_exit++;
                     if (n_exit < 2 || n_child > n_exit)
@@ -949,7 +1019,7 @@ int verify_buffer(const uint8_t* bytes, size_t n, std::string* why) {
                         return bad("bin %d block %lld: child blocks", b, (long long)k);
                     const uint32_t n_slot = n_exit - 1;  // a binary tree of m nodes has m + 1 exits
                     for (uint32_t sl = 0; sl < 7; sl++) {
-                        const uint32_t f = get(48 + fp::kClusterFeatBits * (int)sl, fp::kClusterFeatBits);
+                        const uint32_t f = get(p_feat + fw * (int)sl, fw);
                         if (sl < n_slot ? (int64_t)f >= F : (f != 0 || bk.thr[sl] != 0.0f))
                             return bad("bin %d block %lld slot %u", b, (long long)k, sl);
                     }

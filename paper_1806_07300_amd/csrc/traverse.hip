@@ -559,19 +559,41 @@ __device__ __forceinline__ uint32_t zero_bytes(uint32_t x) {
     return ~(((x & 0x7F7F7F7Fu) + 0x7F7F7F7Fu) | x) & 0x80808080u;
 }
 
+// Low / high fp16 half of a word widened to fp32 (exact).
+__device__ __forceinline__ float half_lo(uint32_t v) {
+    return (float)__builtin_bit_cast(_Float16, (unsigned short)(v & 0xFFFFu));
+}
+__device__ __forceinline__ float half_hi(uint32_t v) {
+    return (float)__builtin_bit_cast(_Float16, (unsigned short)(v >> 16));
+}
+
 // CLUSTERED block: reads the seven split outcomes (one LDS round trip, as in
 // the BLOCKED walk), tests four exits per 32-bit operation against the
 // outcome mask replicated into every byte, and returns the next reference:
 // the child block or the class of the one exit whose pattern matches.
-template <typename Le>
+// C48: the 48-byte form (fp16 thresholds, widened before the fp32 compare,
+// and 9-bit features); otherwise the 64-byte form.
+template <bool C48, typename Le>
 __device__ __forceinline__ int32_t cluster_step(const uint4 (&q)[4], int32_t xrow, Le&& le) {
-    const float thr[7] = {__uint_as_float(q[0].x), __uint_as_float(q[0].y), __uint_as_float(q[0].z),
-                          __uint_as_float(q[0].w), __uint_as_float(q[1].x), __uint_as_float(q[1].y),
-                          __uint_as_float(q[1].z)};
-    const uint32_t care_lo = q[1].w, care_hi = q[2].x, val_lo = q[2].y, val_hi = q[2].z;
-    const uint32_t r[5] = {q[2].w, q[3].x, q[3].y, q[3].z, q[3].w};
-    const uint32_t f[7] = {cfield<48, 12>(r), cfield<60, 12>(r), cfield<72, 12>(r), cfield<84, 12>(r),
-                           cfield<96, 12>(r), cfield<108, 12>(r), cfield<120, 12>(r)};
+    constexpr int FW = C48 ? fp::kCluster48FeatBits : fp::kClusterFeatBits;
+    constexpr int PB = C48 ? 111 : 132, PN = C48 ? 135 : 156;  // child_base, n_children
+    float thr[7];
+    uint32_t care_lo, care_hi, val_lo, val_hi, r[5];
+    if constexpr (C48) {
+        thr[0] = half_lo(q[0].x); thr[1] = half_hi(q[0].x); thr[2] = half_lo(q[0].y); thr[3] = half_hi(q[0].y);
+        thr[4] = half_lo(q[0].z); thr[5] = half_hi(q[0].z); thr[6] = half_lo(q[0].w);
+        care_lo = q[1].x; care_hi = q[1].y; val_lo = q[1].z; val_hi = q[1].w;
+        r[0] = q[2].x; r[1] = q[2].y; r[2] = q[2].z; r[3] = q[2].w; r[4] = q[0].w >> 16;
+    } else {
+        thr[0] = __uint_as_float(q[0].x); thr[1] = __uint_as_float(q[0].y); thr[2] = __uint_as_float(q[0].z);
+        thr[3] = __uint_as_float(q[0].w); thr[4] = __uint_as_float(q[1].x); thr[5] = __uint_as_float(q[1].y);
+        thr[6] = __uint_as_float(q[1].z);
+        care_lo = q[1].w; care_hi = q[2].x; val_lo = q[2].y; val_hi = q[2].z;
+        r[0] = q[2].w; r[1] = q[3].x; r[2] = q[3].y; r[3] = q[3].z; r[4] = q[3].w;
+    }
+    const uint32_t f[7] = {cfield<48, FW>(r),          cfield<48 + FW, FW>(r),     cfield<48 + 2 * FW, FW>(r),
+                           cfield<48 + 3 * FW, FW>(r), cfield<48 + 4 * FW, FW>(r), cfield<48 + 5 * FW, FW>(r),
+                           cfield<48 + 6 * FW, FW>(r)};
     uint32_t g = 0;
 #pragma unroll
     for (int sl = 0; sl < 7; sl++) g |= (le(xrow, f[sl], thr[sl]) ? 0u : 1u) << sl;
@@ -581,8 +603,8 @@ __device__ __forceinline__ int32_t cluster_step(const uint4 (&q)[4], int32_t xro
     const uint32_t e = z_lo ? (uint32_t)__builtin_ctz(z_lo) >> 3 : 4u + ((uint32_t)__builtin_ctz(z_hi | 0x80000000u) >> 3);
     const uint64_t targets = ((uint64_t)r[1] << 32) | r[0];
     const uint32_t t = (uint32_t)(targets >> (6 * e)) & 63u;
-    const uint32_t n_child = cfield<156, 4>(r);
-    return (t & 32u) ? (int32_t)(cfield<132, 24>(r) + min(t & 7u, n_child - 1u)) : ~(int32_t)(t & 31u);
+    const uint32_t n_child = cfield<PN, 4>(r);
+    return (t & 32u) ? (int32_t)(cfield<PB, 24>(r) + min(t & 7u, n_child - 1u)) : ~(int32_t)(t & 31u);
 }
 
 // BLOCKED layout walk.  Every reference is a block of the bin (or a class).
@@ -592,10 +614,11 @@ __device__ __forceinline__ int32_t cluster_step(const uint4 (&q)[4], int32_t xro
 // features in LDS all seven split tests are read in one LDS round trip and
 // the path is resolved from a mask of sides by selects (no divergence inside
 // a block).
-// FMT: 0 BLOCKED 48-byte blocks, 1 BLOCKED 64-byte blocks, 2 CLUSTERED.
+// FMT: 0 BLOCKED 48-byte blocks, 1 BLOCKED 64-byte blocks, 2 CLUSTERED
+// 64-byte blocks, 3 CLUSTERED 48-byte blocks.
 template <int K, int FMODE, int FMT>
 __device__ void run_tile_blocked(const JobDesc& j, int nt, int tile, unsigned char* smem) {
-    constexpr bool B48 = FMT == 0;
+    constexpr bool B48 = FMT == 0 || FMT == 3;
     const bool feat_lds = FMODE == 2 ? (j.feat_lds != 0) : (FMODE == 1);
     const int4* ttab = reinterpret_cast<const int4*>(smem + j.off_ttab);
     const int32_t* fmap_l = reinterpret_cast<const int32_t*>(smem + j.off_fmap);
@@ -660,8 +683,8 @@ __device__ void run_tile_blocked(const JobDesc& j, int nt, int tile, unsigned ch
         for (int k = 0; k < K; k++) {
             if (ref[k] < 0) continue;
             int32_t nr;
-            if (FMT == 2) {
-                nr = cluster_step(q[k], xrow[k], le);
+            if constexpr (FMT >= 2) {
+                nr = cluster_step<FMT == 3>(q[k], xrow[k], le);
             } else if (const BlockView b = view_block<B48>(q[k]); feat_lds) {
                 // all seven split tests (absent slots are zero words: feature
                 // 0, harmless) packed into a mask of sides, bit s set = slot s
@@ -742,6 +765,7 @@ __global__ __launch_bounds__(1024, (MinWaves<K, LAYOUT>::value)) void packed_ker
         if (LAYOUT == FP_LAYOUT_COMPACT) run_tile_compact<K, FMODE>(j, nt, tile, smem);
         else if (LAYOUT == FP_LAYOUT_BLOCKED && j.block_bytes == 48) run_tile_blocked<K, FMODE, 0>(j, nt, tile, smem);
         else if (LAYOUT == FP_LAYOUT_BLOCKED) run_tile_blocked<K, FMODE, 1>(j, nt, tile, smem);
+        else if (LAYOUT == FP_LAYOUT_CLUSTERED && j.block_bytes == 48) run_tile_blocked<K, FMODE, 3>(j, nt, tile, smem);
         else if (LAYOUT == FP_LAYOUT_CLUSTERED) run_tile_blocked<K, FMODE, 2>(j, nt, tile, smem);
         else run_tile<K, FMODE>(j, nt, tile, smem);
     }
@@ -774,7 +798,8 @@ __global__ __launch_bounds__(1024) void batched_kernel(const JobDesc* __restrict
             for (int tile = w.tile_begin; tile < w.tile_end; tile++) run_tile_compact<K, 2>(j, nt, tile, smem);
         else if (j.layout >= FP_LAYOUT_BLOCKED)
             for (int tile = w.tile_begin; tile < w.tile_end; tile++) {
-                if (j.layout == FP_LAYOUT_CLUSTERED) run_tile_blocked<1, 2, 2>(j, nt, tile, smem);
+                if (j.layout == FP_LAYOUT_CLUSTERED && j.block_bytes == 48) run_tile_blocked<1, 2, 3>(j, nt, tile, smem);
+                else if (j.layout == FP_LAYOUT_CLUSTERED) run_tile_blocked<1, 2, 2>(j, nt, tile, smem);
                 else if (j.block_bytes == 48) run_tile_blocked<1, 2, 0>(j, nt, tile, smem);
                 else run_tile_blocked<1, 2, 1>(j, nt, tile, smem);
             }

@@ -133,6 +133,8 @@ BLOCK = np.dtype({"names": ["child_base", "ranks", "slot"],
                   "formats": ["<u4", "<u4", np.dtype((NODE8, 7))]})
 BLOCK48 = np.dtype([("words", "<u4", 5), ("thr", "<f4", 7)])
 BLOCKC = np.dtype([("thr", "<f4", 7), ("care", "u1", 8), ("val", "u1", 8), ("rest", "<u4", 5)])
+BLOCKC48 = np.dtype([("thr16", "<f2", 7), ("rest_hi", "<u2"), ("care", "u1", 8), ("val", "u1", 8),
+                     ("rest", "<u4", 4)])
 WORD48_BITS = 19
 
 
@@ -142,7 +144,10 @@ def blocked_bin(dec: dict, be):
     off = h["nodes_offset"] + 8 * int(be["node_base"])
     tl = int(be["top_len"])
     top = np.frombuffer(b, NODE, count=tl, offset=off)
-    dt = BLOCKC if h["layout"] == 4 else BLOCK48 if h["block_bytes"] == 48 else BLOCK
+    if h["layout"] == 4:
+        dt = BLOCKC48 if h["block_bytes"] == 48 else BLOCKC
+    else:
+        dt = BLOCK48 if h["block_bytes"] == 48 else BLOCK
     blocks = np.frombuffer(b, dt, count=int(be["deep_len"]), offset=off + 8 * ((2 * tl + 7) // 8 * 8))
     return top, blocks
 
@@ -233,18 +238,24 @@ def reseal(buf: np.ndarray) -> np.ndarray:
 
 
 def cluster_fields(blocks):
-    """CLUSTERED blocks as plain arrays: thr [n, 7], feat [n, 7], care, val,
-    target [n, 8], child_base, n_children, n_exits [n] (unused exits have
-    care = val = 0x80)."""
+    """CLUSTERED blocks, either form, as plain arrays: thr [n, 7] (fp32),
+    feat [n, 7], care, val, target [n, 8], child_base, n_children,
+    n_exits [n] (unused exits have care = val = 0x80), and the bits above
+    the last field (must be zero)."""
     n = len(blocks)
+    c48 = blocks.dtype == BLOCKC48
+    fw, p_base, p_nchild, p_end = (9, 111, 135, 139) if c48 else (12, 132, 156, 160)
     big = [sum(int(w) << (32 * i) for i, w in enumerate(row)) for row in blocks["rest"]]
+    if c48:
+        big = [v | int(hi) << 128 for v, hi in zip(big, blocks["rest_hi"])]
     get = lambda pos, width: np.array([(v >> pos) & ((1 << width) - 1) for v in big], np.int64).reshape(n)
     care = blocks["care"].astype(np.int64)
-    return {"thr": blocks["thr"],
-            "feat": np.stack([get(48 + 12 * s, 12) for s in range(7)], 1) if n else np.zeros((0, 7), np.int64),
+    return {"thr": blocks["thr16"].astype(np.float32) if c48 else blocks["thr"],
+            "feat": np.stack([get(48 + fw * s, fw) for s in range(7)], 1) if n else np.zeros((0, 7), np.int64),
             "care": care, "val": blocks["val"].astype(np.int64),
             "target": np.stack([get(6 * e, 6) for e in range(8)], 1) if n else np.zeros((0, 8), np.int64),
-            "child_base": get(132, 24), "n_children": get(156, 4), "n_exits": (care != 0x80).sum(1)}
+            "child_base": get(p_base, 24), "n_children": get(p_nchild, 4), "n_exits": (care != 0x80).sum(1),
+            "stray": np.array([v >> p_end for v in big], object).reshape(n)}
 
 
 def walk_clustered(dec: dict, X: np.ndarray) -> np.ndarray:

@@ -14,6 +14,7 @@ import oracle
 import paper_1806_07300_amd as fp
 from paper_1806_07300_amd import presets
 import synth
+from packed_format import decode
 
 pytestmark = pytest.mark.gpu
 
@@ -146,6 +147,38 @@ def test_strided_rows_and_special_values(small):
         p = upload(f, **kw)
         assert_same(run(p, X, ld_pad=13), want, f"padded ld {kw}")
         assert_same(run(p, X, {"feature_lds": -1, "rows_per_block": 16}), want, f"global features {kw}")
+
+
+def test_fp16_threshold_blocks_special_values():
+    """CLUSTERED 48-byte blocks (fp16 thresholds widened in the kernel): a
+    forest whose thresholds are fp16 subnormals and an image forest, with rows
+    on the thresholds, one fp32 ulp either side, and non-finite values."""
+    rng = np.random.default_rng(5)
+    Xi = rng.integers(0, 120, size=(4000, 6))
+    y = ((Xi[:, 0] + Xi[:, 1] * 2 + rng.integers(0, 40, 4000)) // 70).astype(np.int32)
+    tiny = synth.train_forest((Xi * 2.0 ** -23).astype(np.float32), y, n_trees=8, n_classes=int(y.max()) + 1,
+                              mtry=3, max_depth=12, seed=3)
+    w = synth.image(n_train=6000, n_trees=8)
+    for f, X in ((tiny, (rng.integers(0, 120, size=(5000, 6)) * 2.0 ** -23).astype(np.float32)),
+                 (w.forest(), w.predict_rows(5000)[0])):
+        X = X.copy()
+        thr = f.threshold[f.feature >= 0]
+        m = rng.random(X.shape)
+        sel = m < 0.3
+        pick = rng.choice(thr, size=sel.sum())
+        bump = rng.integers(-1, 2, size=sel.sum())
+        X[sel] = np.where(bump > 0, np.nextafter(pick, np.float32(np.inf)),
+                          np.where(bump < 0, np.nextafter(pick, np.float32(-np.inf)), pick))
+        X[(m >= 0.3) & (m < 0.33)] = np.nan
+        X[(m >= 0.33) & (m < 0.35)] = -np.inf
+        X[(m >= 0.35) & (m < 0.37)] = np.float32(1e-44)
+        X[(m >= 0.37) & (m < 0.39)] = -0.0
+        want = oracle.predict(f, X)
+        p = upload(f, layout=fp.FP_LAYOUT_CLUSTERED, bin_size=4, interleave_depth=3)
+        assert decode(fp.fp_packed_host_bytes(p))["h"]["block_bytes"] == 48
+        assert_same(run(p, X), want, f"F={X.shape[1]} staged rows")
+        assert_same(run(p, X, ld_pad=3), want, f"F={X.shape[1]} padded ld")
+        assert_same(run(p, X, {"feature_lds": -1, "rows_per_block": 16}), want, f"F={X.shape[1]} global features")
 
 
 def test_degenerate_forests():

@@ -476,11 +476,13 @@ def test_clustered_layout_invariants():
     X, _ = synth.image(n_train=6000, n_trees=6).predict_rows(300)
     c = decode(fp.fp_packed_host_bytes(fp.fp_pack_forest(f, layout=fp.FP_LAYOUT_CLUSTERED, bin_size=3,
                                                           interleave_depth=3)))
+    assert c["h"]["block_bytes"] == 48  # 353 used pixel columns, half-integer thresholds
     assert (walk(c, X) == oracle.predict(f, X)[0]).all()
     seen_nodes = 0
     for bc in c["bins"]:
         _, blocks = blocked_bin(c, bc)
         cf = cluster_fields(blocks)
+        assert all(v == 0 for v in cf["stray"])
         owner = set()
         for j in range(int(bc["n_trees"])):
             t = int(bc["first_tree"]) + j
@@ -529,20 +531,75 @@ def test_clustered_layout_invariants():
     assert seen_nodes == int((f.feature >= 0).sum())
 
 
-def test_clustered_verifier_catches_overlapping_exits(small_forest):
+@pytest.fixture(scope="module")
+def image_forest():
+    return synth.image(n_train=6000, n_trees=6).forest(), synth.image(n_train=6000, n_trees=6).predict_rows(500)[0]
+
+
+def test_clustered_block_form_choice(small_forest, image_forest):
+    """The 48-byte form (fp16 thresholds, 9-bit features) is taken only when
+    every threshold converts to fp16 exactly and the used features fit 9 bits,
+    so both forms compare the same fp32 values."""
+    f, X = image_forest
+    pack = lambda f: decode(fp.fp_packed_host_bytes(fp.fp_pack_forest(f, layout=fp.FP_LAYOUT_CLUSTERED, bin_size=2,
+                                                                      interleave_depth=3)))
+    assert pack(small_forest)["h"]["block_bytes"] == 64  # thresholds are not fp16 values
+    c48 = pack(f)
+    assert c48["h"]["block_bytes"] == 48 and c48["h"]["compact_fbits"] <= 9
+    votes = oracle.predict(f, X)[0]
+    assert (walk(c48, X) == votes).all()
+    # one threshold with fp32-only precision sends the whole forest to 64 bytes
+    g = f.subset(range(f.n_trees))  # copies every array
+    i = int(np.nonzero(g.feature >= 0)[0][3])
+    g.threshold[i] = np.float32(g.threshold[i] + np.float32(1e-3))
+    c64 = pack(g)
+    assert c64["h"]["block_bytes"] == 64
+    assert (walk(c64, X) == oracle.predict(g, X)[0]).all()
+
+
+def test_clustered_fp16_denormal_thresholds():
+    """Thresholds that are fp16 subnormals (multiples of 2^-24 below 2^-14)
+    still take the 48-byte form and widen back to the same fp32 values."""
+    rng = np.random.default_rng(5)
+    Xi = rng.integers(0, 120, size=(4000, 6))
+    y = ((Xi[:, 0] + Xi[:, 1] * 2 + rng.integers(0, 40, 4000)) // 70).astype(np.int32)
+    X = (Xi * 2.0 ** -23).astype(np.float32)
+    f = synth.train_forest(X, y, n_trees=8, n_classes=int(y.max()) + 1, mtry=3, max_depth=12, seed=3)
+    th = f.threshold[f.feature >= 0]
+    assert ((np.abs(th) < 2.0 ** -14) & (th != 0)).all()
+    c = decode(fp.fp_packed_host_bytes(fp.fp_pack_forest(f, layout=fp.FP_LAYOUT_CLUSTERED, bin_size=4,
+                                                          interleave_depth=3)))
+    assert c["h"]["block_bytes"] == 48
+    Xq = (rng.integers(0, 120, size=(3000, 6)) * 2.0 ** -23).astype(np.float32)
+    Xq[::7] = np.nextafter(Xq[::7], np.float32(1))  # one fp32 ulp above grid points
+    assert (walk(c, Xq) == oracle.predict(f, Xq)[0]).all()
+
+
+@pytest.mark.parametrize("form", [64, 48])
+def test_clustered_verifier_catches_overlapping_exits(small_forest, image_forest, form):
     from packed_format import reseal
-    good = fp.fp_packed_host_bytes(fp.fp_pack_forest(small_forest, layout=fp.FP_LAYOUT_CLUSTERED, bin_size=4,
+    f = small_forest if form == 64 else image_forest[0]
+    good = fp.fp_packed_host_bytes(fp.fp_pack_forest(f, layout=fp.FP_LAYOUT_CLUSTERED, bin_size=4,
                                                      interleave_depth=0))
     dec = decode(good)
+    assert dec["h"]["block_bytes"] == form
     be = dec["bins"][0]
     base = dec["h"]["nodes_offset"] + 8 * int(be["node_base"])
+    care = 28 if form == 64 else 16  # byte offset of the care bytes in a block
     faults = []
     bad = good.copy()
-    bad[base + 28] = 0x01  # exit 0 tests only slot 0: it now overlaps another exit
+    bad[base + care] = 0x01  # exit 0 tests only slot 0: it now overlaps another exit
     faults.append(bad)
     bad = good.copy()
-    bad[base + 28 + 7] = 0x00  # an unused exit (care 0x80) that would match everything
+    bad[base + care + 7] = 0x00  # an unused exit (care 0x80) that would match everything
     faults.append(bad)
+    if form == 48:
+        bad = good.copy()
+        bad[base + 14:base + 16] = [0, 0xFF]  # bits above the last field (rest_hi)
+        faults.append(bad)
+        bad = good.copy()
+        bad[base:base + 2] = [0x00, 0x7E]  # a NaN threshold
+        faults.append(bad)
     for i, bad in enumerate(faults):
         with pytest.raises(fp.FPError) as e:
             fp.fp_packed_from_bytes(reseal(bad))
