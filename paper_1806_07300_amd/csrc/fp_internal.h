@@ -32,7 +32,7 @@ namespace fp {
 // internal children are tree-local ids.
 // ---------------------------------------------------------------------------
 constexpr uint64_t kMagic = 0x314B4341504D5046ull;  // "FPMPACK1"
-constexpr uint32_t kFormatVersion = 5;
+constexpr uint32_t kFormatVersion = 6;
 constexpr size_t kSectionAlign = 256;
 
 struct alignas(16) Node16 {
@@ -121,10 +121,11 @@ constexpr int kClusterFeatBits = 12, kClusterMaxClasses = 32;
 // forest converts to fp16 and back unchanged (integer-valued features split
 // at half-integers, for example) and at most 512 features are used: the
 // same exits, with thr16[s] the fp16 bits of slot s's threshold, and rest
-// fields (little-endian over rest[0..3], then the upper half of thr16 word 3
-// as bits [128, 144)): [0, 48) targets as in BlockC64; [48, 111) feature of
-// slot s in 9 bits at 48 + 9 s; [111, 135) child_base; [135, 139) number of
-// child blocks.
+// fields (little-endian over rest[0..3], then rest_hi as bits [128, 144)):
+// [0, 48) targets as in BlockC64; the 9-bit feature of slot s at
+// kC48FeatPos[s], placed so that none crosses a 32-bit word; [57, 61) the
+// number of child blocks; [123, 144) child_base (21 bits).  Bits [61, 64)
+// and [91, 96) are zero.
 struct BlockC48 {
     uint16_t thr16[7];
     uint16_t rest_hi;  // bits [128, 144) of rest
@@ -134,6 +135,9 @@ struct BlockC48 {
 };
 static_assert(sizeof(BlockC48) == 48, "block is 48 bytes");
 constexpr int kCluster48FeatBits = 9;
+constexpr int kC48FeatPos[7] = {48, 64, 73, 82, 96, 105, 114};
+constexpr int kC48NChildPos = 57, kC48BasePos = 123, kC48BaseBits = 21;
+constexpr uint32_t kC48MaxChildBase = (1u << kC48BaseBits) - 1u;
 
 struct BinEntry {
     int64_t node_base;   // first node of the bin in the node array

@@ -60,7 +60,7 @@ void fp_clear_error() { g_last_error.clear(); }
 extern "C" const char* fp_last_error(void) { return g_last_error.c_str(); }
 #define FP_STR2(x) #x
 #define FP_STR(x) FP_STR2(x)
-#define FP_FORMAT_VERSION 5
+#define FP_FORMAT_VERSION 6
 static_assert(FP_FORMAT_VERSION == fp::kFormatVersion, "version string follows the format");
 extern "C" const char* fp_version(void) { return "forestpack 0.2 packed-format " FP_STR(FP_FORMAT_VERSION); }
 
@@ -685,7 +685,7 @@ int pack_blocked(const fp_forest_view* v, const std::vector<TreeShape>& s, const
             if (!bk.slot[k].present) continue;
             const _Float16 h16 = (_Float16)bk.slot[k].thr;
             memcpy(&out->thr16[k], &h16, 2);
-            put(48 + kCluster48FeatBits * k, kCluster48FeatBits, bk.slot[k].feat);
+            put(fp::kC48FeatPos[k], kCluster48FeatBits, bk.slot[k].feat);
         }
         for (uint32_t e = 0; e < 8; e++) {
             if (e < bk.n_exits) {
@@ -697,8 +697,8 @@ int pack_blocked(const fp_forest_view* v, const std::vector<TreeShape>& s, const
                 out->val[e] = 0x80;
             }
         }
-        put(111, 24, bk.n_children ? child_base : 0u);
-        put(135, 4, bk.n_children);
+        put(fp::kC48BasePos, fp::kC48BaseBits, bk.n_children ? child_base : 0u);
+        put(fp::kC48NChildPos, 4, bk.n_children);
         for (int i = 0; i < 4; i++) out->rest[i] = r[i];
         out->rest_hi = (uint16_t)r[4];
     };
@@ -797,7 +797,7 @@ restart:
             for (size_t q = 0; q < tb[j].root.size(); q++)
                 if (pos[j][q] < 0) pos[j][q] = next++;
         if (next > INT32_MAX) return fp_set_error(FP_E2BIG, "bin %d holds too many blocks", b);
-        if (use48 && next > (int64_t)kBlock48MaxChildBase) {
+        if (use48 && next > (int64_t)(clustered ? fp::kC48MaxChildBase : kBlock48MaxChildBase)) {
             use48 = false;
             goto restart;
         }
@@ -973,7 +973,8 @@ int verify_buffer(const uint8_t* bytes, size_t n, std::string* why) {
             if (clustered) {
                 const bool c48 = h.block_bytes == 48;
                 const int fw = c48 ? fp::kCluster48FeatBits : fp::kClusterFeatBits;
-                const int p_feat = 48, p_base = c48 ? 111 : 132, p_nchild = c48 ? 135 : 156, p_end = c48 ? 139 : 160;
+                const int p_base = c48 ? fp::kC48BasePos : 132, w_base = c48 ? fp::kC48BaseBits : 24;
+                const int p_nchild = c48 ? fp::kC48NChildPos : 156;
                 for (int64_t k = 0; k < be.deep_len; k++) {
                     const uint8_t* raw = reinterpret_cast<const uint8_t*>(words) + k * h.block_bytes;
                     uint32_t rest[5];
@@ -1007,10 +1008,10 @@ int verify_buffer(const uint8_t* bytes, size_t n, std::string* why) {
                         for (int i = 0; i < width; i++) v |= ((rest[(pos + i) / 32] >> ((pos + i) % 32)) & 1u) << i;
                         return v;
                     };
-                    if (c48 ? (rest[4] >> (p_end - 128)) != 0 : false)
+                    if (c48 ? (get(61, 3) | get(91, 5) | (rest[4] >> 16)) != 0 : false)
                         return bad("bin %d block %lld: stray bits", b, (long long)k);
                     const uint32_t n_child = get(p_nchild, 4);
-                    const int64_t child_base = get(p_base, 24);
+                    const int64_t child_base = get(p_base, w_base);
                     uint32_t n_exit = 0;
                     while (n_exit < 8 && bk.care[n_exit] != 0x80) n_exit++;
                     if (n_exit < 2 || n_child > n_exit)
@@ -1019,7 +1020,7 @@ int verify_buffer(const uint8_t* bytes, size_t n, std::string* why) {
                         return bad("bin %d block %lld: child blocks", b, (long long)k);
                     const uint32_t n_slot = n_exit - 1;  // a binary tree of m nodes has m + 1 exits
                     for (uint32_t sl = 0; sl < 7; sl++) {
-                        const uint32_t f = get(p_feat + fw * (int)sl, fw);
+                        const uint32_t f = get(c48 ? fp::kC48FeatPos[sl] : 48 + fw * (int)sl, fw);
                         if (sl < n_slot ? (int64_t)f >= F : (f != 0 || bk.thr[sl] != 0.0f))
                             return bad("bin %d block %lld slot %u", b, (long long)k, sl);
                     }

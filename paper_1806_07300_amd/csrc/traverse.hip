@@ -498,22 +498,33 @@ typedef __attribute__((address_space(1))) const u32x4 global_u32x4;
 
 __device__ __forceinline__ uint4 as_uint4(u32x4 v) { return make_uint4(v.x, v.y, v.z, v.w); }
 
+// LDS byte address of a pointer into the workgroup's shared memory, and back.
+__device__ __forceinline__ uint32_t lds_addr(const void* p) {
+    return (uint32_t)(size_t)(__attribute__((address_space(3))) const void*)p;
+}
+template <typename T>
+__device__ __forceinline__ __attribute__((address_space(3))) const T* lds_ptr(uint32_t a) {
+    return (__attribute__((address_space(3))) const T*)(size_t)a;
+}
+
+// bp = the bin's first block in memory, la = LDS byte address of its copy
+// (blocks below ns).
 template <bool B48>
-__device__ __forceinline__ void fetch_block(const uint2* words, const unsigned char* smem_blocks, int32_t bb,
-                                            int32_t lb, int32_t ns, int32_t ref, uint4 (&q)[4]) {
+__device__ __forceinline__ void fetch_block(const global_u32x4* bp, uint32_t la, int32_t ns, int32_t ref,
+                                            uint4 (&q)[4]) {
     constexpr int bw = B48 ? 3 : 4;  // 16-byte pieces per block
     if (ref < ns) {
-        const lds_u32x4* lp = (const lds_u32x4*)(smem_blocks) + lb + (int32_t)__umul24((uint32_t)ref, bw);
+        const lds_u32x4* lp = lds_ptr<u32x4>(la + (B48 ? __umul24((uint32_t)ref, 48u) : (uint32_t)ref << 6));
         q[0] = as_uint4(lp[0]);
         q[1] = as_uint4(lp[1]);
         q[2] = as_uint4(lp[2]);
         if (!B48) q[3] = as_uint4(lp[3]);
     } else {
-        const global_u32x4* bp = (const global_u32x4*)(words + bb) + bw * ref;
-        q[0] = as_uint4(bp[0]);
-        q[1] = as_uint4(bp[1]);
-        q[2] = as_uint4(bp[2]);
-        if (!B48) q[3] = as_uint4(bp[3]);
+        const global_u32x4* gp = bp + bw * ref;
+        q[0] = as_uint4(gp[0]);
+        q[1] = as_uint4(gp[1]);
+        q[2] = as_uint4(gp[2]);
+        if (!B48) q[3] = as_uint4(gp[3]);
     }
 }
 
@@ -559,6 +570,15 @@ __device__ __forceinline__ uint32_t zero_bytes(uint32_t x) {
     return ~(((x & 0x7F7F7F7Fu) + 0x7F7F7F7Fu) | x) & 0x80808080u;
 }
 
+// Bits [OFF, OFF + W) of x as one v_bfe_u32 the compiler cannot fold into the
+// address arithmetic that follows (which would cost a shift and a mask).
+template <int OFF, int W>
+__device__ __forceinline__ uint32_t bfe_u32(uint32_t x) {
+    uint32_t r;
+    asm("v_bfe_u32 %0, %1, %2, %3" : "=v"(r) : "v"(x), "i"(OFF), "i"(W));
+    return r;
+}
+
 // Low / high fp16 half of a word widened to fp32 (exact).
 __device__ __forceinline__ float half_lo(uint32_t v) {
     return (float)__builtin_bit_cast(_Float16, (unsigned short)(v & 0xFFFFu));
@@ -575,36 +595,51 @@ __device__ __forceinline__ float half_hi(uint32_t v) {
 // and 9-bit features); otherwise the 64-byte form.
 template <bool C48, typename Le>
 __device__ __forceinline__ int32_t cluster_step(const uint4 (&q)[4], int32_t xrow, Le&& le) {
-    constexpr int FW = C48 ? fp::kCluster48FeatBits : fp::kClusterFeatBits;
-    constexpr int PB = C48 ? 111 : 132, PN = C48 ? 135 : 156;  // child_base, n_children
     float thr[7];
-    uint32_t care_lo, care_hi, val_lo, val_hi, r[5];
+    uint32_t care_lo, care_hi, val_lo, val_hi, r[5], f[7], child_base, n_child;
     if constexpr (C48) {
         thr[0] = half_lo(q[0].x); thr[1] = half_hi(q[0].x); thr[2] = half_lo(q[0].y); thr[3] = half_hi(q[0].y);
         thr[4] = half_lo(q[0].z); thr[5] = half_hi(q[0].z); thr[6] = half_lo(q[0].w);
         care_lo = q[1].x; care_hi = q[1].y; val_lo = q[1].z; val_hi = q[1].w;
-        r[0] = q[2].x; r[1] = q[2].y; r[2] = q[2].z; r[3] = q[2].w; r[4] = q[0].w >> 16;
+        r[0] = q[2].x; r[1] = q[2].y; r[2] = q[2].z; r[3] = q[2].w;
+        static_assert(fp::kC48FeatPos[0] == 48 && fp::kC48FeatPos[1] == 64 && fp::kC48FeatPos[2] == 73 &&
+                          fp::kC48FeatPos[3] == 82 && fp::kC48FeatPos[4] == 96 && fp::kC48FeatPos[5] == 105 &&
+                          fp::kC48FeatPos[6] == 114 && fp::kC48NChildPos == 57 && fp::kC48BasePos == 123,
+                      "field positions below follow the 48-byte block");
+        f[0] = bfe_u32<16, 9>(r[1]);
+        f[1] = bfe_u32<0, 9>(r[2]); f[2] = bfe_u32<9, 9>(r[2]); f[3] = bfe_u32<18, 9>(r[2]);
+        f[4] = bfe_u32<0, 9>(r[3]); f[5] = bfe_u32<9, 9>(r[3]); f[6] = bfe_u32<18, 9>(r[3]);
+        n_child = (r[1] >> 25) & 15u;
+        child_base = __builtin_amdgcn_alignbit(q[0].w >> 16, r[3], 27);  // rest bits [123, 144)
     } else {
         thr[0] = __uint_as_float(q[0].x); thr[1] = __uint_as_float(q[0].y); thr[2] = __uint_as_float(q[0].z);
         thr[3] = __uint_as_float(q[0].w); thr[4] = __uint_as_float(q[1].x); thr[5] = __uint_as_float(q[1].y);
         thr[6] = __uint_as_float(q[1].z);
         care_lo = q[1].w; care_hi = q[2].x; val_lo = q[2].y; val_hi = q[2].z;
         r[0] = q[2].w; r[1] = q[3].x; r[2] = q[3].y; r[3] = q[3].z; r[4] = q[3].w;
+        constexpr int FW = fp::kClusterFeatBits;
+        f[0] = cfield<48, FW>(r); f[1] = cfield<48 + FW, FW>(r); f[2] = cfield<48 + 2 * FW, FW>(r);
+        f[3] = cfield<48 + 3 * FW, FW>(r); f[4] = cfield<48 + 4 * FW, FW>(r); f[5] = cfield<48 + 5 * FW, FW>(r);
+        f[6] = cfield<48 + 6 * FW, FW>(r);
+        n_child = cfield<156, 4>(r);
+        child_base = cfield<132, 24>(r);
     }
-    const uint32_t f[7] = {cfield<48, FW>(r),          cfield<48 + FW, FW>(r),     cfield<48 + 2 * FW, FW>(r),
-                           cfield<48 + 3 * FW, FW>(r), cfield<48 + 4 * FW, FW>(r), cfield<48 + 5 * FW, FW>(r),
-                           cfield<48 + 6 * FW, FW>(r)};
     uint32_t g = 0;
 #pragma unroll
     for (int sl = 0; sl < 7; sl++) g |= (le(xrow, f[sl], thr[sl]) ? 0u : 1u) << sl;
-    const uint32_t g4 = __umul24(g, 0x010101u) | (g << 24);  // g in every byte (24-bit multiply: full rate)
+    const uint32_t g4 = __builtin_amdgcn_perm(g, g, 0u);  // byte 0 of g copied into every byte
     const uint32_t z_lo = zero_bytes((g4 ^ val_lo) & care_lo), z_hi = zero_bytes((g4 ^ val_hi) & care_hi);
-    // a verified block's used exits partition the outcomes: exactly one byte is zero
-    const uint32_t e = z_lo ? (uint32_t)__builtin_ctz(z_lo) >> 3 : 4u + ((uint32_t)__builtin_ctz(z_hi | 0x80000000u) >> 3);
+    // a verified block's used exits partition the outcomes: exactly one byte
+    // is zero (the top bit keeps e <= 7 for any bytes); both outcomes of the
+    // exit are formed and selected, without a branch
+    const uint64_t z = ((uint64_t)(z_hi | 0x80000000u) << 32) | z_lo;
+    const uint32_t e = (uint32_t)__builtin_ctzll(z) >> 3;
     const uint64_t targets = ((uint64_t)r[1] << 32) | r[0];
-    const uint32_t t = (uint32_t)(targets >> (6 * e)) & 63u;
-    const uint32_t n_child = cfield<PN, 4>(r);
-    return (t & 32u) ? (int32_t)(cfield<PB, 24>(r) + min(t & 7u, n_child - 1u)) : ~(int32_t)(t & 31u);
+    const uint32_t t = (uint32_t)(targets >> __umul24(e, 6u)) & 63u;
+    const int32_t child = (int32_t)(child_base + min(t & 7u, n_child - 1u));
+    const int32_t leaf = ~(int32_t)(t & 31u);
+    const int32_t m = -(int32_t)(t >> 5);  // all ones when the exit leads to a child block
+    return (child & m) | (leaf & ~m);
 }
 
 // BLOCKED layout walk.  Every reference is a block of the bin (or a class).
@@ -638,27 +673,34 @@ __device__ void run_tile_blocked(const JobDesc& j, int nt, int tile, unsigned ch
 
     const int U = rows_here * nt;
     const uint32_t rmagic = 0xFFFFFFFFu / (uint32_t)rows_here;
-    // x <= thr for compacted feature f; xrow = the row's first feature in the
-    // LDS tile (or its row in the tile when features stay in memory)
+    // x <= thr for compacted feature f; xrow = LDS byte address of the row's
+    // first feature in the tile (or its row in the tile when features stay
+    // in memory)
     auto le = [&](int32_t xrow, uint32_t f, float thr) {
-        const float x = feat_lds ? xs[xrow + (int32_t)f] : j.X[(row0 + xrow) * j.ld + fmap_l[f]];
+        const float x = feat_lds ? lds_ptr<float>((uint32_t)xrow)[f] : j.X[(row0 + xrow) * j.ld + fmap_l[f]];
         return x <= thr;
     };
+    const uint32_t xs_addr = lds_addr(xs), blocks_addr = lds_addr(smem + j.off_top);
     // the block an exit leaves to: rank from the code (48-byte form) or the table
     auto exit_to = [&](const BlockView& b, uint32_t e, uint32_t code) -> int32_t {
         const uint32_t rank = B48 ? (code >> 1) : ((b.ranks >> (4 * e)) & 7u);
         return (int32_t)(b.child_base + rank);
     };
-    const unsigned char* lds_blocks = smem + j.off_top;
-    // per cursor: xrow, vrow = the row's first vote counter, bb = the bin's
-    // first block (words), lb / ns = its LDS copy (first piece, blocks held)
-    int32_t ref[K], xrow[K], vrow[K], bb[K], lb[K], ns[K];
+    // per cursor: xrow, vrow = the row's first vote counter, bp = the bin's
+    // first block, la / ns = its LDS copy (byte address, blocks held)
+    int32_t ref[K], xrow[K], vrow[K], ns[K];
+    uint32_t la[K];
+    const global_u32x4* bp[K];
 #pragma unroll
-    for (int k = 0; k < K; k++) { ref[k] = kDone; xrow[k] = 0; vrow[k] = 0; bb[k] = 0; lb[k] = 0; ns[k] = 0; }
+    for (int k = 0; k < K; k++) {
+        ref[k] = kDone; xrow[k] = 0; vrow[k] = 0; ns[k] = 0; la[k] = 0; bp[k] = nullptr;
+    }
     auto take = [&](int k, int r, int4 e) -> int32_t {
-        xrow[k] = feat_lds ? (int32_t)__umul24((uint32_t)r, (uint32_t)j.Fcp) : r;
+        xrow[k] = feat_lds ? (int32_t)(xs_addr + 4u * __umul24((uint32_t)r, (uint32_t)j.Fcp)) : r;
         vrow[k] = (int32_t)__umul24((uint32_t)r, (uint32_t)j.C);
-        bb[k] = e.y; lb[k] = e.z; ns[k] = e.w;
+        bp[k] = (const global_u32x4*)(words + e.y);
+        la[k] = blocks_addr + 16u * (uint32_t)e.z;
+        ns[k] = e.w;
         if (e.x < 0) {  // the root is a leaf
             atomicAdd(&vl[vrow[k] - e.x - 1], 1);
             return kDone;
@@ -678,7 +720,7 @@ __device__ void run_tile_blocked(const JobDesc& j, int nt, int tile, unsigned ch
         uint4 q[K][4];
 #pragma unroll
         for (int k = 0; k < K; k++)
-            if (ref[k] >= 0) fetch_block<B48>(words, lds_blocks, bb[k], lb[k], ns[k], ref[k], q[k]);
+            if (ref[k] >= 0) fetch_block<B48>(bp[k], la[k], ns[k], ref[k], q[k]);
 #pragma unroll
         for (int k = 0; k < K; k++) {
             if (ref[k] < 0) continue;
@@ -693,7 +735,7 @@ __device__ void run_tile_blocked(const JobDesc& j, int nt, int tile, unsigned ch
                 uint32_t gm = 0;
 #pragma unroll
                 for (int sl = 0; sl < 7; sl++)
-                    gm |= (xs[xrow[k] + (int32_t)(b.w[sl] & fmask)] <= __uint_as_float(b.t[sl]) ? 0u : 1u) << sl;
+                    gm |= (lds_ptr<float>((uint32_t)xrow[k])[b.w[sl] & fmask] <= __uint_as_float(b.t[sl]) ? 0u : 1u) << sl;
                 const uint32_t side0 = gm & 1u;
                 const uint32_t c0 = (b.w[0] >> (side0 ? sh_r : sh_l)) & code_mask;
                 const uint32_t side1 = (gm >> (1 + side0)) & 1u;

@@ -136,6 +136,7 @@ BLOCKC = np.dtype([("thr", "<f4", 7), ("care", "u1", 8), ("val", "u1", 8), ("res
 BLOCKC48 = np.dtype([("thr16", "<f2", 7), ("rest_hi", "<u2"), ("care", "u1", 8), ("val", "u1", 8),
                      ("rest", "<u4", 4)])
 WORD48_BITS = 19
+C48_FEAT_POS = [48, 64, 73, 82, 96, 105, 114]  # 9-bit feature fields of a 48-byte CLUSTERED block
 
 
 def blocked_bin(dec: dict, be):
@@ -244,18 +245,26 @@ def cluster_fields(blocks):
     the last field (must be zero)."""
     n = len(blocks)
     c48 = blocks.dtype == BLOCKC48
-    fw, p_base, p_nchild, p_end = (9, 111, 135, 139) if c48 else (12, 132, 156, 160)
+    if c48:  # features placed so that none crosses a 32-bit word
+        fw, fpos, (p_base, w_base), p_nchild = 9, C48_FEAT_POS, (123, 21), 57
+        spare = [(61, 3), (91, 5)]
+    else:
+        fw, fpos, (p_base, w_base), p_nchild = 12, [48 + 12 * s for s in range(7)], (132, 24), 156
+        spare = []
     big = [sum(int(w) << (32 * i) for i, w in enumerate(row)) for row in blocks["rest"]]
     if c48:
         big = [v | int(hi) << 128 for v, hi in zip(big, blocks["rest_hi"])]
     get = lambda pos, width: np.array([(v >> pos) & ((1 << width) - 1) for v in big], np.int64).reshape(n)
     care = blocks["care"].astype(np.int64)
+    stray = np.zeros(n, np.int64)
+    for pos, width in spare:
+        stray |= get(pos, width)
     return {"thr": blocks["thr16"].astype(np.float32) if c48 else blocks["thr"],
-            "feat": np.stack([get(48 + fw * s, fw) for s in range(7)], 1) if n else np.zeros((0, 7), np.int64),
+            "feat": np.stack([get(p, fw) for p in fpos], 1) if n else np.zeros((0, 7), np.int64),
             "care": care, "val": blocks["val"].astype(np.int64),
             "target": np.stack([get(6 * e, 6) for e in range(8)], 1) if n else np.zeros((0, 8), np.int64),
-            "child_base": get(p_base, 24), "n_children": get(p_nchild, 4), "n_exits": (care != 0x80).sum(1),
-            "stray": np.array([v >> p_end for v in big], object).reshape(n)}
+            "child_base": get(p_base, w_base), "n_children": get(p_nchild, 4), "n_exits": (care != 0x80).sum(1),
+            "stray": stray}
 
 
 def walk_clustered(dec: dict, X: np.ndarray) -> np.ndarray:

@@ -595,7 +595,10 @@ def test_clustered_verifier_catches_overlapping_exits(small_forest, image_forest
     faults.append(bad)
     if form == 48:
         bad = good.copy()
-        bad[base + 14:base + 16] = [0, 0xFF]  # bits above the last field (rest_hi)
+        bad[base + 32 + 7] |= 0x40  # bit 62: a spare bit between the fields
+        faults.append(bad)
+        bad = good.copy()
+        bad[base + 32 + 11] |= 0x10  # bit 92: another spare bit
         faults.append(bad)
         bad = good.copy()
         bad[base:base + 2] = [0x00, 0x7E]  # a NaN threshold
