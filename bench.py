@@ -9,8 +9,13 @@ rows).  Inputs are resident in HBM before timing starts.  Prints one JSON line.
 
   python bench.py [--gpus 1] [--steps K] [--warmup W]
 
-Extra modes used for profiling (rocprofv3 runs):
+Extra modes:
   --only packed|naive|copy   run only that kernel, --steps times, no JSON
+                             (profiling runs under rocprofv3)
+  --ladder image|tabular     the layout ablation of Sec. III-A (Fig. 4): BF,
+                             DF, DF-, Stat, Bin, Bin+, then the block layouts,
+                             same rows and forest, every rung checked bit for
+                             bit against BF; prints one JSON line
 """
 from __future__ import annotations
 
@@ -167,6 +172,73 @@ def serve_leg(fp, synth, np, torch, image_forest, seconds, warm, rate, cache, su
     return out
 
 
+# The paper's layout ablation (Sec. III-A, Fig. 4) mapped to this GPU path:
+# BF and DF run the naive kernel (a lane per row, trees in turn, leaves
+# stored, features from memory); DF-, Stat and Bin run the packed kernel
+# with one walk per lane (no round-robin), Bin+ with four walks per lane
+# interleaved; the block layouts follow with their own launches.
+def ladder_rungs(workload: str, fp, presets):
+    wide = dict(rows_per_block=48, block_threads=1024) if workload == "image" else \
+        dict(rows_per_block=256, block_threads=1024)
+    one = dict(wide, cursors=1)
+    rr = dict(wide, cursors=4)
+    blk = dict(wide, cursors=1, refill_lanes=32 if workload == "image" else 16)
+    B = 16
+    clustered = presets.IMAGE["pack"] if workload == "image" else \
+        {"layout": fp.FP_LAYOUT_CLUSTERED, "bin_size": 16, "interleave_depth": 3}
+    return [
+        ("BF", {"layout": fp.FP_LAYOUT_NAIVE}, {"block_threads": 256}),
+        ("DF", {"layout": fp.FP_LAYOUT_NAIVE, "node_order": fp.FP_ORDER_DF}, {"block_threads": 256}),
+        ("DF-", {"layout": fp.FP_LAYOUT_PACKED, "bin_size": 1, "interleave_depth": 0,
+                 "node_order": fp.FP_ORDER_DF}, one),
+        ("Stat", {"layout": fp.FP_LAYOUT_PACKED, "bin_size": 1, "interleave_depth": 0}, one),
+        ("Bin", {"layout": fp.FP_LAYOUT_PACKED, "bin_size": B, "interleave_depth": 3}, one),
+        ("Bin+", {"layout": fp.FP_LAYOUT_PACKED, "bin_size": B, "interleave_depth": 3}, rr),
+        ("COMPACT", {"layout": fp.FP_LAYOUT_COMPACT, "bin_size": B, "interleave_depth": 3}, rr),
+        ("BLOCKED", {"layout": fp.FP_LAYOUT_BLOCKED, "bin_size": B, "interleave_depth": 3}, blk),
+        ("CLUSTERED", clustered, presets.IMAGE["tune"] if workload == "image" else blk),
+    ]
+
+
+def ladder(args, fp, synth, torch):
+    from paper_1806_07300_amd import presets
+    t0 = time.perf_counter()
+    w = synth.image(n_predict=args.rows) if args.ladder == "image" else synth.tabular(n_predict=args.rows)
+    forest = w.forest(cache_dir=args.cache, progress=lambda done, total: log(f"trained {done}/{total} trees"))
+    X, _ = w.predict_rows()
+    n, C = X.shape[0], forest.n_classes
+    log(f"ladder {args.ladder}: {forest.n_trees} trees, {n} rows ({time.perf_counter() - t0:.1f} s)")
+    Xd = torch.from_numpy(X).cuda()
+    votes = torch.empty((n, C), dtype=torch.int32, device="cuda")
+    cls = torch.empty((n,), dtype=torch.int32, device="cuda")
+    ref = None
+    rungs = []
+    for name, pack, tune in ladder_rungs(args.ladder, fp, presets):
+        p = fp.fp_pack_forest(forest, **pack)
+        fp.fp_packed_upload(p)
+        run = lambda: fp.fp_predict_tuned(p, tune, Xd, votes, cls)
+        votes.fill_(-1)
+        run()
+        torch.cuda.synchronize()
+        if ref is None:
+            ref = votes.clone()
+        exact = bool(torch.equal(votes, ref))
+        ms, _ = time_steps(run, args.steps, args.warmup, torch)
+        info = fp.fp_packed_info_get(p)
+        rungs.append({"name": name, "pack": pack, "tune": tune, "ms": ms, "obs_per_s": n / (ms / 1e3),
+                      "bytes": info["bytes"], "bit_exact_vs_BF": exact})
+        log(f"{name:9s} {ms:9.3f} ms  {n / ms / 1e3:8.2f} M obs/s  {info['bytes'] / 2**20:8.1f} MiB  exact={exact}")
+        del p
+        if not exact:
+            print(f"{name}: votes differ from BF", file=sys.stderr)
+            sys.exit(3)
+    bf = rungs[0]["ms"]
+    for r in rungs:
+        r["speedup_vs_BF"] = bf / r["ms"]
+    print(json.dumps({"ladder": args.ladder, "n_rows": n, "n_trees": forest.n_trees, "steps": args.steps,
+                      "rungs": rungs}), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -179,6 +251,7 @@ def main():
     ap.add_argument("--no-serve", action="store_true")
     ap.add_argument("--serve-seconds", type=float, default=10.0)
     ap.add_argument("--serve-rate", type=float, default=20000.0)
+    ap.add_argument("--ladder", choices=["image", "tabular"], default=None)
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print(f"bench.py measures one GPU only (asked for {args.gpus}); the multi-GPU design is "
@@ -204,6 +277,10 @@ def main():
             b.copy_(a)
         torch.cuda.synchronize()
         print("copy done: bytes read per launch", a.numel() * 4, "written", b.numel() * 4, flush=True)
+        return
+
+    if args.ladder:
+        ladder(args, fp, synth, torch)
         return
 
     t0 = time.perf_counter()

@@ -141,6 +141,17 @@ enum {
     FP_LAYOUT_CLUSTERED = 4
 };
 
+/* Node order inside a tree, for the layout ablation of Sec. III-A (Fig. 4). */
+enum {
+    /* the layout's own order: breadth-first (NAIVE), Stat (PACKED, COMPACT),
+     * blocks (BLOCKED, CLUSTERED) */
+    FP_ORDER_DEFAULT = 0,
+    /* depth-first pre-order, left child first: with NAIVE the DF layout (leaves
+     * stored), with PACKED the DF- layout (class references, no Stat); other
+     * layouts reject it (FP_EINVAL) */
+    FP_ORDER_DF = 1
+};
+
 /*
  * Packing parameters (Sec. III-A, "two parameters used when interleaving"):
  *   bin_size          trees per bin (stripe width); <= 0 or > T: one bin of all
@@ -151,12 +162,14 @@ enum {
  *   line_align        1: start each deep subtree on a 128-byte line when it
  *                     fits in the remaining part of the current line otherwise;
  *                     0: dense.  (Ignored by the naive layout.)
+ *   node_order        FP_ORDER_DEFAULT or FP_ORDER_DF (see above).
  */
 typedef struct fp_pack_opts {
     int32_t layout;
     int32_t bin_size;
     int32_t interleave_depth;
     int32_t line_align;
+    int32_t node_order;
 } fp_pack_opts;
 
 typedef struct fp_packed fp_packed;

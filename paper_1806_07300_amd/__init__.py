@@ -20,6 +20,7 @@ LIB_PATH = os.path.join(HERE, "libforestpack.so")
 
 FP_OK, FP_EINVAL, FP_ENOMEM, FP_EHIP, FP_ECORRUPT, FP_E2BIG, FP_EAGAIN, FP_ENOTREADY, FP_ENODEV = range(9)
 FP_LAYOUT_NAIVE, FP_LAYOUT_PACKED, FP_LAYOUT_COMPACT, FP_LAYOUT_BLOCKED, FP_LAYOUT_CLUSTERED = 0, 1, 2, 3, 4
+FP_ORDER_DEFAULT, FP_ORDER_DF = 0, 1
 ERROR_NAMES = {0: "FP_OK", 1: "FP_EINVAL", 2: "FP_ENOMEM", 3: "FP_EHIP", 4: "FP_ECORRUPT",
                5: "FP_E2BIG", 6: "FP_EAGAIN", 7: "FP_ENOTREADY", 8: "FP_ENODEV"}
 
@@ -44,7 +45,8 @@ class fp_forest_view(ctypes.Structure):
 
 
 class fp_pack_opts(ctypes.Structure):
-    _fields_ = [("layout", _i32), ("bin_size", _i32), ("interleave_depth", _i32), ("line_align", _i32)]
+    _fields_ = [("layout", _i32), ("bin_size", _i32), ("interleave_depth", _i32), ("line_align", _i32),
+                ("node_order", _i32)]
 
 
 class fp_packed_info(ctypes.Structure):
@@ -200,7 +202,8 @@ def _view_from(forest):
 
 
 def fp_pack_forest(forest, layout: int = FP_LAYOUT_PACKED, bin_size: int = 16,
-                   interleave_depth: int = 3, line_align: int = 0, use_cardinality: bool = True) -> Packed:
+                   interleave_depth: int = 3, line_align: int = 0, use_cardinality: bool = True,
+                   node_order: int = FP_ORDER_DEFAULT) -> Packed:
     """Pack a trained forest (any object with the fp_forest_view arrays as attributes)."""
     if not use_cardinality:
         class _NoCard:
@@ -212,7 +215,7 @@ def fp_pack_forest(forest, layout: int = FP_LAYOUT_PACKED, bin_size: int = 16,
         f2.cardinality = None
         forest = f2
     view, keep = _view_from(forest)
-    opts = fp_pack_opts(layout, bin_size, interleave_depth, line_align)
+    opts = fp_pack_opts(layout, bin_size, interleave_depth, line_align, node_order)
     out = _vp()
     _check(lib().fp_pack_forest(ctypes.byref(view), ctypes.byref(opts), ctypes.byref(out)), "fp_pack_forest")
     del keep

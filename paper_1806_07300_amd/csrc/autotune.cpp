@@ -124,7 +124,7 @@ extern "C" int fp_autotune(const fp_forest_view* forest, const float* X, int64_t
             auto k = std::make_tuple(layout, B, D);
             if (!packs.count(k)) {
                 std::unique_ptr<PackedPtr> pp(new PackedPtr());
-                fp_pack_opts po{layout, B, D, 0};
+                fp_pack_opts po{layout, B, D, 0, FP_ORDER_DEFAULT};
                 int r = fp_pack_forest(forest, &po, &pp->p);
                 if (r) return r;
                 packs[k] = std::move(pp);
@@ -234,7 +234,7 @@ extern "C" int fp_autotune(const fp_forest_view* forest, const float* X, int64_t
             rc = try_tune(t);
             if (rc) return rc;
         }
-        out->pack = fp_pack_opts{best_L, best_B, best_D, 0};
+        out->pack = fp_pack_opts{best_L, best_B, best_D, 0, FP_ORDER_DEFAULT};
         out->tune = best_t;
         out->best_ms = best;
         if (hipStreamSynchronize(stream) != hipSuccess) return fp_set_error(FP_EHIP, "hipStreamSynchronize failed");

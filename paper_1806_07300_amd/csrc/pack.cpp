@@ -219,9 +219,25 @@ void finish(std::vector<uint8_t>* bytes, Header* h) {
     memcpy(bytes->data(), h, sizeof *h);
 }
 
-int pack_naive(const fp_forest_view* v, const std::vector<TreeShape>& s, std::vector<uint8_t>* out,
-               Header* h) {
+// Depth-first pre-order of a tree's nodes, left child first (the DF layout).
+void depth_first(const fp_forest_view* v, const TreeShape& t, std::vector<int32_t>* order) {
+    order->clear();
+    std::vector<int32_t> stack{0};
+    while (!stack.empty()) {
+        const int32_t n = stack.back();
+        stack.pop_back();
+        order->push_back(n);
+        const int64_t g = t.base + n;
+        if (v->feature[g] < 0) continue;
+        stack.push_back(v->right[g]);
+        stack.push_back(v->left[g]);
+    }
+}
+
+int pack_naive(const fp_forest_view* v, const std::vector<TreeShape>& s, const fp_pack_opts* opts,
+               std::vector<uint8_t>* out, Header* h) {
     fill_header_common(h, v, s, FP_LAYOUT_NAIVE);
+    const bool df = opts->node_order == FP_ORDER_DF;
     int64_t n_nodes = 0;
     for (const auto& t : s) n_nodes += (int64_t)t.bfs.size();
     const size_t table_off = sizeof(Header);
@@ -231,14 +247,16 @@ int pack_naive(const fp_forest_view* v, const std::vector<TreeShape>& s, std::ve
     int64_t* offs = reinterpret_cast<int64_t*>(out->data() + table_off);
     Node16* nodes = reinterpret_cast<Node16*>(out->data() + nodes_off);
     int64_t o = 0;
-    std::vector<int32_t> pos;
+    std::vector<int32_t> pos, dfo;
     for (int32_t ti = 0; ti < v->n_trees; ti++) {
         const TreeShape& t = s[ti];
         offs[ti] = o;
+        if (df) depth_first(v, t, &dfo);
+        const std::vector<int32_t>& order = df ? dfo : t.bfs;  // both hold every reachable node once
         pos.assign(t.size, -1);
-        for (size_t k = 0; k < t.bfs.size(); k++) pos[t.bfs[k]] = (int32_t)k;
-        for (size_t k = 0; k < t.bfs.size(); k++) {
-            const int64_t g = t.base + t.bfs[k];
+        for (size_t k = 0; k < order.size(); k++) pos[order[k]] = (int32_t)k;
+        for (size_t k = 0; k < order.size(); k++) {
+            const int64_t g = t.base + order[k];
             Node16& nd = nodes[o + (int64_t)k];
             if (v->feature[g] >= 0) {
                 nd.thr = v->threshold[g];
@@ -297,6 +315,7 @@ int pack_packed(const fp_forest_view* v, const std::vector<TreeShape>& s, const 
     const int32_t D = o->interleave_depth;
     const bool compact = o->layout == FP_LAYOUT_COMPACT;
     const bool align_lines = o->line_align != 0 && !compact;
+    const bool stat = o->node_order != FP_ORDER_DF;  // DF-: plain depth-first, left child first
     const int32_t n_bins = (T + B - 1) / B;
     fill_header_common(h, v, s, compact ? FP_LAYOUT_COMPACT : FP_LAYOUT_PACKED);
 
@@ -344,8 +363,9 @@ int pack_packed(const fp_forest_view* v, const std::vector<TreeShape>& s, const 
                     const int32_t l = v->left[g], r = v->right[g];
                     const bool li = is_internal(v, t, l), ri = is_internal(v, t, r);
                     if (li && ri) {
-                        // hot child (more training samples; ties -> left) goes right after n
-                        const bool left_hot = t.card[l] >= t.card[r];
+                        // hot child (more training samples; ties -> left) goes right after
+                        // n; without Stat the left child does
+                        const bool left_hot = !stat || t.card[l] >= t.card[r];
                         stack.push_back(left_hot ? r : l);
                         stack.push_back(left_hot ? l : r);
                     } else if (li) {
@@ -1200,12 +1220,16 @@ extern "C" int fp_pack_forest(const fp_forest_view* forest, const fp_pack_opts* 
         return fp_set_error(FP_EINVAL, "unknown layout %d", opts->layout);
     if (opts->layout != FP_LAYOUT_NAIVE && (opts->interleave_depth < 0 || opts->interleave_depth > 30))
         return fp_set_error(FP_EINVAL, "interleave_depth %d outside [0, 30]", opts->interleave_depth);
+    if (opts->node_order != FP_ORDER_DEFAULT && opts->node_order != FP_ORDER_DF)
+        return fp_set_error(FP_EINVAL, "unknown node_order %d", opts->node_order);
+    if (opts->node_order == FP_ORDER_DF && opts->layout != FP_LAYOUT_NAIVE && opts->layout != FP_LAYOUT_PACKED)
+        return fp_set_error(FP_EINVAL, "node_order DF needs the NAIVE or PACKED layout");
     try {
         std::vector<fp::TreeShape> shapes;
         int rc = fp::validate_view(forest, &shapes);
         if (rc) return rc;
         std::unique_ptr<fp_packed> p(new fp_packed());
-        rc = opts->layout == FP_LAYOUT_NAIVE     ? fp::pack_naive(forest, shapes, &p->bytes, &p->hdr)
+        rc = opts->layout == FP_LAYOUT_NAIVE     ? fp::pack_naive(forest, shapes, opts, &p->bytes, &p->hdr)
              : opts->layout >= FP_LAYOUT_BLOCKED ? fp::pack_blocked(forest, shapes, opts, &p->bytes, &p->hdr)
                                                  : fp::pack_packed(forest, shapes, opts, &p->bytes, &p->hdr);
         if (rc) return rc;

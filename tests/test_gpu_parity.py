@@ -108,6 +108,20 @@ def test_compact_layout_grid(small, B, D, layout):
                     f"layout={layout} B={B} D={D} K={K}")
 
 
+def test_ablation_orders(small):
+    """The DF layout (NAIVE, depth-first, leaves stored) on the naive kernel and
+    DF- (PACKED without Stat) on the packed kernel, one and four walks per
+    lane, against the checker."""
+    f, X, want = small
+    p = upload(f, layout=fp.FP_LAYOUT_NAIVE, node_order=fp.FP_ORDER_DF)
+    assert_same(run(p, X, {"block_threads": 256}), want, "DF")
+    for B, D in ((1, 0), (16, 3)):
+        p = upload(f, bin_size=B, interleave_depth=D, node_order=fp.FP_ORDER_DF)
+        for K in (1, 4):
+            assert_same(run(p, X, {"cursors": K, "rows_per_block": 32, "block_threads": 1024}), want,
+                        f"DF- B={B} D={D} K={K}")
+
+
 @pytest.mark.parametrize("n", [0, 1, 15, 17, 257, 4099])
 def test_ragged_and_empty(small, n):
     f, X, _ = small

@@ -133,6 +133,76 @@ def test_layout_invariants(small_forest, B, D, align):
     assert np.array_equal(dec["fmap"], used) and info["n_used_features"] == len(used)
 
 
+def test_naive_depth_first_order(small_forest, small_rows):
+    """NAIVE with node_order DF (the DF layout of Sec. III-A): every tree's
+    nodes, leaves included, in depth-first pre-order, left child first; the
+    walk still gives the checker's votes."""
+    f = small_forest
+    dec = decode(fp.fp_packed_host_bytes(fp.fp_pack_forest(f, layout=fp.FP_LAYOUT_NAIVE,
+                                                           node_order=fp.FP_ORDER_DF)))
+    off = dec["tree_off"]
+    for t in range(f.n_trees):
+        tn = dec["nodes"][off[t]:off[t + 1]]
+        o = f.tree_node_offset[t]
+        assert len(tn) == f.tree_node_offset[t + 1] - o
+        # packed index i must be the i-th node of a pre-order walk of the original tree
+        order, stack = [], [0]
+        while stack:
+            n = stack.pop()
+            order.append(n)
+            if f.feature[o + n] >= 0:
+                stack += [f.right[o + n], f.left[o + n]]
+        pos = {n: i for i, n in enumerate(order)}
+        for i, n in enumerate(order):
+            nd = tn[i]
+            if f.feature[o + n] >= 0:
+                assert (nd["feat"], nd["thr"]) == (f.feature[o + n], f.threshold[o + n])
+                assert (nd["left"], nd["right"]) == (pos[f.left[o + n]], pos[f.right[o + n]])
+                assert nd["left"] == i + 1  # the left child always follows its parent
+            else:
+                assert nd["feat"] < 0 and nd["left"] == f.leaf_class[o + n]
+    assert (walk(dec, small_rows) == oracle.predict(f, small_rows)[0]).all()
+
+
+@pytest.mark.parametrize("B,D", [(1, 0), (16, 3), (5, 1)])
+def test_packed_without_stat(small_forest, small_rows, B, D):
+    """PACKED with node_order DF (DF-: class references, no Stat): below the
+    interleaved levels the left internal child follows its parent whatever
+    the cardinalities; predictions unchanged."""
+    f = small_forest
+    dec = decode(fp.fp_packed_host_bytes(fp.fp_pack_forest(f, bin_size=B, interleave_depth=D,
+                                                           node_order=fp.FP_ORDER_DF)))
+    assert (walk(dec, small_rows) == oracle.predict(f, small_rows)[0]).all()
+    n_right_hot = 0
+    for be in dec["bins"]:
+        seen = {}
+        for j in range(be["n_trees"]):
+            for ref, (orig, d) in node_map(f, dec, be, j).items():
+                seen[ref] = (orig, d, j)
+        for i, (orig, d, j) in seen.items():
+            if i < be["top_len"]:
+                continue
+            off = f.tree_node_offset[be["first_tree"] + j]
+            l, r = f.left[off + orig], f.right[off + orig]
+            li, ri = f.feature[off + l] >= 0, f.feature[off + r] >= 0
+            if not (li or ri):
+                continue
+            nxt = seen.get(i + 1)
+            assert nxt is not None and nxt[0] == (l if li else r) and nxt[2] == j
+            n_right_hot += li and ri and f.cardinality[off + r] > f.cardinality[off + l]
+    assert n_right_hot > 0  # Stat would have placed these right children first
+
+
+def test_node_order_rejected_where_undefined(small_forest):
+    for layout in (fp.FP_LAYOUT_COMPACT, fp.FP_LAYOUT_BLOCKED, fp.FP_LAYOUT_CLUSTERED):
+        with pytest.raises(fp.FPError) as e:
+            fp.fp_pack_forest(small_forest, layout=layout, node_order=fp.FP_ORDER_DF)
+        assert e.value.code == fp.FP_EINVAL
+    with pytest.raises(fp.FPError) as e:
+        fp.fp_pack_forest(small_forest, node_order=2)
+    assert e.value.code == fp.FP_EINVAL
+
+
 def test_deterministic_bytes_and_roundtrip(small_forest, tmp_path):
     a = fp.fp_packed_host_bytes(fp.fp_pack_forest(small_forest, bin_size=8, interleave_depth=2))
     b = fp.fp_packed_host_bytes(fp.fp_pack_forest(small_forest, bin_size=8, interleave_depth=2))
