@@ -200,6 +200,30 @@ def ladder_rungs(workload: str, fp, presets):
     ]
 
 
+def eu_stat(bias: float) -> float:
+    """Expected uses of a fetched cache line (Sec. III-A): one node for sure,
+    then each further node of the line (two per line, plus the adjacent line
+    the prefetcher brings) with probability `bias` per level."""
+    return 1.0 + bias * (1.0 + bias * (1.0 + bias))
+
+
+def eu_model(name: str, info: dict, D: int) -> tuple:
+    """(fetches, well-used nodes, EU) of a ladder rung for the run-time
+    estimate of Eqs. 1-2: time = (BF time / BF fetches) * (fetches - WuN) / EU.
+    DF has no access statistics, so its bias is 1/2; the interleaved levels of
+    a bin are its well-used nodes; a block is one fetch whatever it holds."""
+    f, d, b = info["expected_fetches"], info["expected_depth"], info["mean_bias"]
+    if name == "BF":
+        return f, 0.0, 1.0
+    if name in ("DF", "DF-"):
+        return f, 0.0, eu_stat(0.5)
+    if name == "Stat":
+        return f, 0.0, eu_stat(b)
+    if name in ("Bin", "Bin+", "COMPACT"):
+        return f, min(D + 1.0, d), eu_stat(b)
+    return f, 0.0, 1.0
+
+
 def ladder(args, fp, synth, torch):
     from paper_1806_07300_amd import presets
     t0 = time.perf_counter()
@@ -225,16 +249,23 @@ def ladder(args, fp, synth, torch):
         exact = bool(torch.equal(votes, ref))
         ms, _ = time_steps(run, args.steps, args.warmup, torch)
         info = fp.fp_packed_info_get(p)
+        fetches, wun, eu = eu_model(name, info, pack.get("interleave_depth", 0))
         rungs.append({"name": name, "pack": pack, "tune": tune, "ms": ms, "obs_per_s": n / (ms / 1e3),
-                      "bytes": info["bytes"], "bit_exact_vs_BF": exact})
-        log(f"{name:9s} {ms:9.3f} ms  {n / ms / 1e3:8.2f} M obs/s  {info['bytes'] / 2**20:8.1f} MiB  exact={exact}")
+                      "bytes": info["bytes"], "bit_exact_vs_BF": exact, "expected_depth": info["expected_depth"],
+                      "mean_bias": info["mean_bias"], "expected_fetches": fetches, "well_used_nodes": wun,
+                      "eu": eu})
+        log(f"{name:9s} {ms:9.3f} ms  {n / ms / 1e3:8.2f} M obs/s  {info['bytes'] / 2**20:8.1f} MiB  "
+            f"fetches/walk {fetches:6.2f}  EU {eu:5.3f}  exact={exact}")
         del p
         if not exact:
             print(f"{name}: votes differ from BF", file=sys.stderr)
             sys.exit(3)
     bf = rungs[0]["ms"]
+    miss = bf / rungs[0]["expected_fetches"]  # Eq. 1: BF time per fetched node
     for r in rungs:
         r["speedup_vs_BF"] = bf / r["ms"]
+        r["eu_model_ms"] = miss * (r["expected_fetches"] - r["well_used_nodes"]) / r["eu"]  # Eq. 2
+        log(f"{r['name']:9s} measured {r['ms']:9.3f} ms, Eq. 2 estimate {r['eu_model_ms']:9.3f} ms")
     print(json.dumps({"ladder": args.ladder, "n_rows": n, "n_trees": forest.n_trees, "steps": args.steps,
                       "rungs": rungs}), flush=True)
 

@@ -189,6 +189,12 @@ typedef struct fp_packed_info {
     double expected_depth;   /* internal nodes a training-distributed observation
                                 visits per tree (leaf depths weighted by
                                 cardinality): the average depth of Eq. 1 */
+    double mean_bias;        /* mean over internal nodes of max(LC, RC) / PN,
+                                the bias of the EU estimate (Sec. III-A) */
+    double expected_fetches; /* fetch units such an observation loads per tree:
+                                nodes (NAIVE: expected_depth + 1 for the stored
+                                leaf; PACKED, COMPACT: expected_depth) or blocks
+                                (BLOCKED, CLUSTERED) */
 } fp_packed_info;
 
 /*

@@ -54,7 +54,8 @@ class fp_packed_info(ctypes.Structure):
                 ("bin_size", _i32), ("interleave_depth", _i32), ("n_bins", _i32), ("max_top_nodes", _i32),
                 ("n_nodes", _i64), ("n_internal", _i64), ("n_leaves", _i64), ("bytes", _i64),
                 ("uploaded", _i32), ("max_depth", _i32), ("n_used_features", _i32), ("reserved", _i32),
-                ("expected_depth", ctypes.c_double)]
+                ("expected_depth", ctypes.c_double), ("mean_bias", ctypes.c_double),
+                ("expected_fetches", ctypes.c_double)]
 
 
 class fp_tune(ctypes.Structure):

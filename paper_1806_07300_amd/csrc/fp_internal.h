@@ -32,7 +32,7 @@ namespace fp {
 // internal children are tree-local ids.
 // ---------------------------------------------------------------------------
 constexpr uint64_t kMagic = 0x314B4341504D5046ull;  // "FPMPACK1"
-constexpr uint32_t kFormatVersion = 6;
+constexpr uint32_t kFormatVersion = 7;
 constexpr size_t kSectionAlign = 256;
 
 struct alignas(16) Node16 {
@@ -171,7 +171,9 @@ struct Header {
     int32_t compact_cbits;  // COMPACT, BLOCKED: class bits cb
     int32_t block_bytes;    // BLOCKED: 48 or 64
     int32_t pad1;
-    uint8_t pad[256 - 160];
+    double mean_bias;        // mean over internal nodes of max(LC, RC) / PN (cardinalities)
+    double expected_fetches; // mean over trees of the cardinality-weighted fetch units per walk
+    uint8_t pad[256 - 176];
 };
 static_assert(sizeof(Header) == 256, "header is 256 bytes");
 

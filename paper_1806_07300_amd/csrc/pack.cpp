@@ -60,7 +60,7 @@ void fp_clear_error() { g_last_error.clear(); }
 extern "C" const char* fp_last_error(void) { return g_last_error.c_str(); }
 #define FP_STR2(x) #x
 #define FP_STR(x) FP_STR2(x)
-#define FP_FORMAT_VERSION 6
+#define FP_FORMAT_VERSION 7
 static_assert(FP_FORMAT_VERSION == fp::kFormatVersion, "version string follows the format");
 extern "C" const char* fp_version(void) { return "forestpack 0.2 packed-format " FP_STR(FP_FORMAT_VERSION); }
 
@@ -195,7 +195,8 @@ void fill_header_common(Header* h, const fp_forest_view* v, const std::vector<Tr
     h->n_trees = v->n_trees;
     h->n_features = v->n_features;
     h->n_classes = v->n_classes;
-    double depth_sum = 0.0;
+    double depth_sum = 0.0, bias_sum = 0.0;
+    int64_t bias_n = 0;
     for (const auto& t : s) {
         h->n_internal += t.n_internal;
         h->n_leaves += t.n_leaves;
@@ -203,14 +204,24 @@ void fill_header_common(Header* h, const fp_forest_view* v, const std::vector<Tr
         // expected internal nodes visited by a training-distributed observation
         // (the average depth of Eq. 1): leaf depths weighted by leaf cardinality
         double num = 0.0, den = 0.0;
-        for (int32_t n : t.bfs)
-            if (v->feature[t.base + n] < 0) {
+        for (int32_t n : t.bfs) {
+            const int64_t g = t.base + n;
+            if (v->feature[g] < 0) {
                 num += (double)t.card[n] * t.depth[n];
                 den += (double)t.card[n];
+            } else if (t.card[n] > 0) {
+                // the bias of a split (Sec. III-A): max(LC, RC) / PN
+                bias_sum += (double)std::max(t.card[v->left[g]], t.card[v->right[g]]) / (double)t.card[n];
+                bias_n++;
             }
+        }
         depth_sum += den > 0 ? num / den : 0.0;
     }
     h->expected_depth = depth_sum / (double)s.size();
+    h->mean_bias = bias_n ? bias_sum / (double)bias_n : 0.0;
+    // node layouts fetch one node per internal node visited; the naive layout
+    // also fetches the leaf; block layouts overwrite this with blocks per walk
+    h->expected_fetches = h->expected_depth + (layout == FP_LAYOUT_NAIVE ? 1.0 : 0.0);
 }
 
 void finish(std::vector<uint8_t>* bytes, Header* h) {
@@ -789,9 +800,11 @@ int pack_blocked(const fp_forest_view* v, const std::vector<TreeShape>& s, const
     std::vector<std::vector<uint8_t>> blocks(n_bins);
     std::vector<int32_t> roots(T, 0);
     int64_t word_cursor = 0;
+    double fetch_sum = 0.0;  // per tree: blocks a training-distributed walk fetches
 restart:
     const int64_t block_words = use48 ? 6 : 8;  // 8-byte words per block
     word_cursor = 0;
+    fetch_sum = 0.0;
     for (int32_t b = 0; b < n_bins; b++) {
         BinEntry& be = bins[b];
         be.first_tree = b * B;
@@ -804,6 +817,9 @@ restart:
             if (v->feature[t.base] < 0) continue;
             if (clustered) build_clusters(t, &tb[j]);
             else build_tree(t, &tb[j]);
+            // a walk fetches block q iff it reaches q's root node
+            if (t.card[0] > 0)
+                for (int32_t r : tb[j].root) fetch_sum += (double)t.card[r] / (double)t.card[0];
         }
         // final position of every (tree, bfs index)
         std::vector<std::vector<int64_t>> pos(be.n_trees);
@@ -875,6 +891,7 @@ restart:
     h->compact_fbits = fb;
     h->compact_cbits = cb;
     h->block_bytes = use48 ? 48 : 64;
+    h->expected_fetches = fetch_sum / (double)T;
     h->table_offset = (int64_t)table_off;
     h->roots_offset = (int64_t)roots_off;
     h->nodes_offset = (int64_t)nodes_off;
@@ -1261,6 +1278,8 @@ extern "C" int fp_packed_info_get(const fp_packed* p, fp_packed_info* out) {
     out->max_depth = h.max_depth;
     out->n_used_features = h.n_used_features;
     out->expected_depth = h.expected_depth;
+    out->mean_bias = h.mean_bias;
+    out->expected_fetches = h.expected_fetches;
     return FP_OK;
 }
 

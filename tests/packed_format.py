@@ -6,7 +6,7 @@ import struct
 
 import numpy as np
 
-HEADER = struct.Struct("<QIi" + "i" * 8 + "q" * 7 + "ii" + "Q" + "ii" + "q" + "d" + "ii" + "ii")
+HEADER = struct.Struct("<QIi" + "i" * 8 + "q" * 7 + "ii" + "Q" + "ii" + "q" + "d" + "ii" + "ii" + "dd")
 NODE8 = np.dtype([("thr", "<f4"), ("w", "<u4")])
 NODE = np.dtype([("thr", "<f4"), ("feat", "<i4"), ("left", "<i4"), ("right", "<i4")])
 BIN = np.dtype([("node_base", "<i8"), ("first_tree", "<i4"), ("n_trees", "<i4"), ("top_len", "<i4"),
@@ -20,7 +20,7 @@ def decode(buf: np.ndarray) -> dict:
             "interleave_depth", "n_bins", "max_top_len", "max_bin_trees", "total_bytes", "table_offset",
             "roots_offset", "nodes_offset", "n_nodes", "n_internal", "n_leaves", "max_depth", "line_align",
             "checksum", "n_used_features", "pad0", "fmap_offset", "expected_depth", "compact_fbits",
-            "compact_cbits", "block_bytes", "pad1"]
+            "compact_cbits", "block_bytes", "pad1", "mean_bias", "expected_fetches"]
     h = dict(zip(keys, f))
     if h["layout"] in (2, 3, 4):
         nodes = np.frombuffer(b, NODE8, count=h["n_nodes"], offset=h["nodes_offset"])
@@ -193,8 +193,9 @@ def block_fields(h, blocks):
     return {"child_base": child_base, "thr": thr, "word": word, "feat": feat, "kind": kind, "pay": pay}
 
 
-def walk_blocked(dec: dict, X: np.ndarray) -> np.ndarray:
-    """Votes [n, C] from walking a BLOCKED buffer (vectorised over rows)."""
+def walk_blocked(dec: dict, X: np.ndarray, stats: dict | None = None) -> np.ndarray:
+    """Votes [n, C] from walking a BLOCKED buffer (vectorised over rows);
+    stats["fetches"] counts the blocks the walks load."""
     h = dec["h"]
     n, C = X.shape[0], h["n_classes"]
     votes = np.zeros((n, C), np.int32)
@@ -208,6 +209,8 @@ def walk_blocked(dec: dict, X: np.ndarray) -> np.ndarray:
             k = np.where(ref >= 0, ref, 0)
             slot = np.zeros(n, np.int64)
             live = ref >= 0
+            if stats is not None:
+                stats["fetches"] = stats.get("fetches", 0) + int(live.sum())
             while live.any():
                 f = bf["feat"][k, slot]
                 side = np.where(X[rows, fmap[f]] <= bf["thr"][k, slot], 0, 1)
@@ -220,6 +223,8 @@ def walk_blocked(dec: dict, X: np.ndarray) -> np.ndarray:
                 k = np.where(ex, bf["child_base"][k] + pay, k)
                 slot = np.where(inner, 2 * slot + 1 + side, np.where(ex, 0, slot))
                 live = live & ~leaf
+                if stats is not None:
+                    stats["fetches"] += int(ex.sum())
             np.add.at(votes, (rows, -ref - 1), 1)
     return votes
 
@@ -267,9 +272,10 @@ def cluster_fields(blocks):
             "stray": stray}
 
 
-def walk_clustered(dec: dict, X: np.ndarray) -> np.ndarray:
+def walk_clustered(dec: dict, X: np.ndarray, stats: dict | None = None) -> np.ndarray:
     """Votes [n, C] from walking a CLUSTERED buffer (vectorised over rows):
-    all seven split outcomes of a block, then the one exit they select."""
+    all seven split outcomes of a block, then the one exit they select;
+    stats["fetches"] counts the blocks the walks load."""
     h = dec["h"]
     n, C = X.shape[0], h["n_classes"]
     votes = np.zeros((n, C), np.int32)
@@ -282,6 +288,8 @@ def walk_clustered(dec: dict, X: np.ndarray) -> np.ndarray:
             ref = np.full(n, dec["roots"][be["root_base"] + j], np.int64)
             while (ref >= 0).any():
                 live = ref >= 0
+                if stats is not None:
+                    stats["fetches"] = stats.get("fetches", 0) + int(live.sum())
                 k = np.where(live, ref, 0)
                 g = np.zeros(n, np.int64)
                 for s in range(7):

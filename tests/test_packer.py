@@ -203,6 +203,49 @@ def test_node_order_rejected_where_undefined(small_forest):
     assert e.value.code == fp.FP_EINVAL
 
 
+def test_cost_model_statistics():
+    """expected_depth, expected_fetches and mean_bias mean what they claim.
+    Trees grown without bootstrap give every node the number of training rows
+    that reach it as its cardinality, so walking the training rows themselves
+    must visit expected_depth internal nodes and load expected_fetches fetch
+    units per tree on average, exactly; mean_bias is max(LC, RC) / PN averaged
+    over internal nodes, recounted here from the trees."""
+    from packed_format import walk_blocked, walk_clustered
+    X, y = synth.gaussian_mixture(3000, 12, 3, seed=31)
+    f = synth.train_forest(X, y, n_trees=5, n_classes=3, mtry=4, max_depth=10, bootstrap=False, seed=32)
+    n_walks = len(X) * f.n_trees
+    _, _, visits = oracle.predict(f, X, return_visits=True)
+    depth = visits / n_walks
+    ratios = []
+    for t in range(f.n_trees):
+        o = f.tree_node_offset[t]
+        for n in range(f.tree_node_offset[t + 1] - o):
+            if f.feature[o + n] >= 0:
+                lc, rc = f.cardinality[o + f.left[o + n]], f.cardinality[o + f.right[o + n]]
+                assert lc + rc == f.cardinality[o + n]
+                ratios.append(max(lc, rc) / (lc + rc))
+    bias = float(np.mean(ratios))
+    assert 0.5 < bias < 1.0
+    for layout in (fp.FP_LAYOUT_NAIVE, fp.FP_LAYOUT_PACKED, fp.FP_LAYOUT_COMPACT, fp.FP_LAYOUT_BLOCKED,
+                   fp.FP_LAYOUT_CLUSTERED):
+        p = fp.fp_pack_forest(f, layout=layout, bin_size=2, interleave_depth=3)
+        info = fp.fp_packed_info_get(p)
+        assert info["expected_depth"] == pytest.approx(depth, rel=1e-12), layout
+        assert info["mean_bias"] == pytest.approx(bias, rel=1e-12), layout
+        if layout == fp.FP_LAYOUT_NAIVE:
+            want = depth + 1  # the stored leaf is fetched too
+        elif layout in (fp.FP_LAYOUT_PACKED, fp.FP_LAYOUT_COMPACT):
+            want = depth
+        else:
+            stats = {}
+            dec = decode(fp.fp_packed_host_bytes(p))
+            walk_fn = walk_blocked if layout == fp.FP_LAYOUT_BLOCKED else walk_clustered
+            assert (walk_fn(dec, X, stats) == oracle.predict(f, X)[0]).all()
+            want = stats["fetches"] / n_walks
+            assert want < depth / 2  # a block serves more than two visits here
+        assert info["expected_fetches"] == pytest.approx(want, rel=1e-12), layout
+
+
 def test_deterministic_bytes_and_roundtrip(small_forest, tmp_path):
     a = fp.fp_packed_host_bytes(fp.fp_pack_forest(small_forest, bin_size=8, interleave_depth=2))
     b = fp.fp_packed_host_bytes(fp.fp_pack_forest(small_forest, bin_size=8, interleave_depth=2))
