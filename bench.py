@@ -12,10 +12,14 @@ rows).  Inputs are resident in HBM before timing starts.  Prints one JSON line.
 Extra modes:
   --only packed|naive|copy   run only that kernel, --steps times, no JSON
                              (profiling runs under rocprofv3)
-  --ladder image|tabular     the layout ablation of Sec. III-A (Fig. 4): BF,
-                             DF, DF-, Stat, Bin, Bin+, then the block layouts,
-                             same rows and forest, every rung checked bit for
-                             bit against BF; prints one JSON line
+  --ladder image|tabular|tabular_imb
+                             the layout ablation of Sec. III-A (Fig. 4): BF,
+                             DF, DF-, Stat (training statistics), Stat-obs
+                             (statistics inferred from 100,000 of the rows),
+                             Bin, Bin+, then the block layouts, same rows and
+                             forest, every rung checked bit for bit against
+                             BF; tabular_imb is the 10%-positive variant
+                             (128 trees); prints one JSON line
 """
 from __future__ import annotations
 
@@ -192,6 +196,7 @@ def ladder_rungs(workload: str, fp, presets):
         ("DF-", {"layout": fp.FP_LAYOUT_PACKED, "bin_size": 1, "interleave_depth": 0,
                  "node_order": fp.FP_ORDER_DF}, one),
         ("Stat", {"layout": fp.FP_LAYOUT_PACKED, "bin_size": 1, "interleave_depth": 0}, one),
+        ("Stat-obs", {"layout": fp.FP_LAYOUT_PACKED, "bin_size": 1, "interleave_depth": 0}, one),
         ("Bin", {"layout": fp.FP_LAYOUT_PACKED, "bin_size": B, "interleave_depth": 3}, one),
         ("Bin+", {"layout": fp.FP_LAYOUT_PACKED, "bin_size": B, "interleave_depth": 3}, rr),
         ("COMPACT", {"layout": fp.FP_LAYOUT_COMPACT, "bin_size": B, "interleave_depth": 3}, rr),
@@ -217,7 +222,7 @@ def eu_model(name: str, info: dict, D: int) -> tuple:
         return f, 0.0, 1.0
     if name in ("DF", "DF-"):
         return f, 0.0, eu_stat(0.5)
-    if name == "Stat":
+    if name in ("Stat", "Stat-obs"):
         return f, 0.0, eu_stat(b)
     if name in ("Bin", "Bin+", "COMPACT"):
         return f, min(D + 1.0, d), eu_stat(b)
@@ -225,20 +230,30 @@ def eu_model(name: str, info: dict, D: int) -> tuple:
 
 
 def ladder(args, fp, synth, torch):
+    import numpy as np
     from paper_1806_07300_amd import presets
     t0 = time.perf_counter()
-    w = synth.image(n_predict=args.rows) if args.ladder == "image" else synth.tabular(n_predict=args.rows)
+    if args.ladder == "image":
+        w = synth.image(n_predict=args.rows)
+    elif args.ladder == "tabular":
+        w = synth.tabular(n_predict=args.rows)
+    else:
+        w = synth.tabular(n_train=200_000, n_trees=128, n_predict=args.rows, imbalanced=True)
     forest = w.forest(cache_dir=args.cache, progress=lambda done, total: log(f"trained {done}/{total} trees"))
-    X, _ = w.predict_rows()
+    X, y = w.predict_rows()
     n, C = X.shape[0], forest.n_classes
-    log(f"ladder {args.ladder}: {forest.n_trees} trees, {n} rows ({time.perf_counter() - t0:.1f} s)")
+    log(f"ladder {args.ladder}: {forest.n_trees} trees, {n} rows, class shares "
+        f"{[round(float(v), 3) for v in np.bincount(y, minlength=C) / max(n, 1)]} ({time.perf_counter() - t0:.1f} s)")
     Xd = torch.from_numpy(X).cuda()
+    # Stat-obs: the same packing with node statistics inferred from observations
+    observed = forest.subset(range(forest.n_trees))
+    observed.cardinality = fp.fp_infer_cardinality(forest, Xd[:min(n, 100_000)])
     votes = torch.empty((n, C), dtype=torch.int32, device="cuda")
     cls = torch.empty((n,), dtype=torch.int32, device="cuda")
     ref = None
     rungs = []
     for name, pack, tune in ladder_rungs(args.ladder, fp, presets):
-        p = fp.fp_pack_forest(forest, **pack)
+        p = fp.fp_pack_forest(observed if name == "Stat-obs" else forest, **pack)
         fp.fp_packed_upload(p)
         run = lambda: fp.fp_predict_tuned(p, tune, Xd, votes, cls)
         votes.fill_(-1)
@@ -282,7 +297,7 @@ def main():
     ap.add_argument("--no-serve", action="store_true")
     ap.add_argument("--serve-seconds", type=float, default=10.0)
     ap.add_argument("--serve-rate", type=float, default=20000.0)
-    ap.add_argument("--ladder", choices=["image", "tabular"], default=None)
+    ap.add_argument("--ladder", choices=["image", "tabular", "tabular_imb"], default=None)
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print(f"bench.py measures one GPU only (asked for {args.gpus}); the multi-GPU design is "

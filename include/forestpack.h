@@ -229,6 +229,24 @@ int fp_packed_upload(fp_packed *p, void *dev, size_t cap, void *stream);
 
 void fp_packed_free(fp_packed *p);
 
+/*
+ * Node cardinalities inferred from observations (Sec. III-A: the statistics
+ * Stat orders by may be collected during training or inferred afterwards from
+ * a suitably large set of observations).  Every row of X_dev (device fp32
+ * [n_rows][ld], row-major, ld >= n_features) is walked through every tree on
+ * the GPU (`stream`, synchronised before returning); card_out (host int64,
+ * one entry per node of the view: tree_node_offset[T] entries, owned by the
+ * caller) receives for each node the number of rows that reach it (a leaf:
+ * rows ending there; an internal node: the sum of its children; unreachable
+ * nodes 0).  Pass it as the view's `cardinality` to fp_pack_forest.  The
+ * library allocates and frees temporary device memory (the forest in the
+ * NAIVE layout and one int32 counter per node).  Errors: FP_EINVAL (NULL,
+ * ld < n_features, n_rows outside [0, 2^31-1]), FP_ECORRUPT (malformed forest),
+ * FP_ENOMEM, FP_EHIP.
+ */
+int fp_infer_cardinality(const fp_forest_view *forest, const float *X_dev, int64_t n_rows, int64_t ld,
+                         int64_t *card_out, void *stream);
+
 /* ------------------------------------------------------------------------ */
 /* Single-forest prediction                                                   */
 /* ------------------------------------------------------------------------ */

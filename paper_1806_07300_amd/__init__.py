@@ -123,6 +123,7 @@ def lib():
             "fp_packed_save": ([_vp, ctypes.c_char_p], ctypes.c_int),
             "fp_packed_load": ([ctypes.c_char_p, ctypes.POINTER(_vp)], ctypes.c_int),
             "fp_packed_upload": ([_vp, _vp, ctypes.c_size_t, _vp], ctypes.c_int),
+            "fp_infer_cardinality": ([ctypes.POINTER(fp_forest_view), _vp, _i64, _i64, _vp, _vp], ctypes.c_int),
             "fp_packed_free": ([_vp], None),
             "fp_packed_set_tune": ([_vp, ctypes.POINTER(fp_tune)], ctypes.c_int),
             "fp_packed_get_tune": ([_vp, ctypes.POINTER(fp_tune)], ctypes.c_int),
@@ -348,6 +349,19 @@ def fp_predict_tuned(p: Packed, tune, X, votes=None, cls=None, stream=None, want
                                   _vp(votes.data_ptr()), _vp(cls.data_ptr()) if cls is not None else None,
                                   _stream_ptr(stream)), "fp_predict_tuned")
     return votes, cls
+
+
+def fp_infer_cardinality(forest, X, stream=None):
+    """Per-node counts of the rows of X (CUDA fp32 [n, >= F]) that reach each
+    node, int64 [tree_node_offset[T]]: a forest's access statistics inferred
+    from observations, for fp_pack_forest's Stat order."""
+    view, keep = _view_from(forest)
+    n, ld = _check_rows(X, int(forest.n_features))
+    card = np.zeros(int(np.asarray(forest.tree_node_offset)[-1]), np.int64)
+    _check(lib().fp_infer_cardinality(ctypes.byref(view), _vp(X.data_ptr()), n, ld, _vp(card.ctypes.data),
+                                      _stream_ptr(stream)), "fp_infer_cardinality")
+    del keep
+    return card
 
 
 # ---------------------------------------------------------------------------

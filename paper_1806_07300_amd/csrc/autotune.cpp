@@ -26,6 +26,8 @@
 
 namespace {
 
+using fp::DevBuf;
+
 std::mutex g_cache_mu;
 std::map<uint64_t, fp_autotune_result> g_cache;
 
@@ -49,24 +51,6 @@ uint64_t fingerprint(const fp_forest_view* v, int64_t sample, int threads, int K
     int64_t cfg[4] = {sample, threads, K, reps};
     return mix(h, cfg, sizeof cfg);
 }
-
-struct DevBuf {
-    void* p = nullptr;
-    size_t cap = 0;
-    ~DevBuf() {
-        if (p) (void)hipFree(p);
-    }
-    int ensure(size_t n) {
-        if (n <= cap) return FP_OK;
-        if (p) (void)hipFree(p);
-        p = nullptr;
-        cap = 0;
-        hipError_t e = hipMalloc(&p, n);
-        if (e != hipSuccess) return fp_set_error(FP_ENOMEM, "hipMalloc(%zu): %s", n, hipGetErrorString(e));
-        cap = n;
-        return FP_OK;
-    }
-};
 
 struct PackedPtr {
     fp_packed* p = nullptr;

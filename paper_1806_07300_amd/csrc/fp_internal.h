@@ -251,6 +251,9 @@ int packed_occupancy(int K, int fmode, int layout, int threads, size_t lds, int*
 int batched_occupancy(int K, int threads, size_t lds, int* blocks_per_cu);
 
 int launch_fill(int32_t* p, int64_t n, int32_t v, hipStream_t s);
+// counts[i] += observations whose walk ends at node i of a NAIVE layout
+int launch_leaf_counts(const Node16* nodes, const int64_t* tree_off, int32_t n_trees, const float* X, int64_t n_rows,
+                       int64_t ld, int32_t* counts, hipStream_t s);
 int launch_argmax(const int32_t* votes, int32_t* cls, int64_t n, int32_t C, hipStream_t s);
 int launch_packed(const JobDesc& j, int K, int threads, int blocks, hipStream_t s);
 int launch_batched(const JobDesc* jobs, const WorkItem* items, int32_t n_items, int32_t* counter, int K,
@@ -283,3 +286,29 @@ struct fp_packed {
 // Error helpers (thread-local last error).
 int fp_set_error(int code, const char* fmt, ...);
 void fp_clear_error();
+
+namespace fp {
+
+// A device allocation owned by host code, released with the object.
+struct DevBuf {
+    void* p = nullptr;
+    size_t cap = 0;
+    DevBuf() = default;
+    DevBuf(const DevBuf&) = delete;
+    DevBuf& operator=(const DevBuf&) = delete;
+    ~DevBuf() {
+        if (p) (void)hipFree(p);
+    }
+    int ensure(size_t n) {
+        if (n <= cap) return FP_OK;
+        if (p) (void)hipFree(p);
+        p = nullptr;
+        cap = 0;
+        hipError_t e = hipMalloc(&p, n);
+        if (e != hipSuccess) return fp_set_error(FP_ENOMEM, "hipMalloc(%zu): %s", n, hipGetErrorString(e));
+        cap = n;
+        return FP_OK;
+    }
+};
+
+}  // namespace fp

@@ -1362,6 +1362,59 @@ extern "C" int fp_packed_upload(fp_packed* p, void* dev, size_t cap, void* strea
     return FP_OK;
 }
 
+extern "C" int fp_infer_cardinality(const fp_forest_view* forest, const float* X_dev, int64_t n_rows, int64_t ld,
+                                    int64_t* card_out, void* stream_v) {
+    fp_clear_error();
+    if (!forest || !card_out) return fp_set_error(FP_EINVAL, "NULL argument");
+    if (n_rows < 0 || n_rows > INT32_MAX) return fp_set_error(FP_EINVAL, "n_rows %lld outside [0, 2^31-1]", (long long)n_rows);
+    if (n_rows > 0 && !X_dev) return fp_set_error(FP_EINVAL, "X is NULL");
+    if (ld < forest->n_features) return fp_set_error(FP_EINVAL, "ld %lld < n_features %d", (long long)ld, forest->n_features);
+    hipStream_t stream = static_cast<hipStream_t>(stream_v);
+    try {
+        std::vector<fp::TreeShape> shapes;
+        int rc = fp::validate_view(forest, &shapes);
+        if (rc) return rc;
+        // the forest in the breadth-first NAIVE layout (leaves stored), walked on the GPU
+        std::vector<uint8_t> bytes;
+        fp::Header h;
+        const fp_pack_opts opts{FP_LAYOUT_NAIVE, 0, 0, 0, FP_ORDER_DEFAULT};
+        rc = fp::pack_naive(forest, shapes, &opts, &bytes, &h);
+        if (rc) return rc;
+        std::vector<int32_t> counts((size_t)h.n_nodes, 0);
+        if (n_rows > 0) {
+            fp::DevBuf buf, cnt;
+            if ((rc = buf.ensure(bytes.size())) || (rc = cnt.ensure(sizeof(int32_t) * counts.size()))) return rc;
+            hipError_t e = hipMemcpyAsync(buf.p, bytes.data(), bytes.size(), hipMemcpyHostToDevice, stream);
+            if (e == hipSuccess) e = hipMemsetAsync(cnt.p, 0, sizeof(int32_t) * counts.size(), stream);
+            if (e != hipSuccess) return fp_set_error(FP_EHIP, "upload: %s", hipGetErrorString(e));
+            const uint8_t* base = static_cast<const uint8_t*>(buf.p);
+            rc = fp::launch_leaf_counts(reinterpret_cast<const fp::Node16*>(base + h.nodes_offset),
+                                        reinterpret_cast<const int64_t*>(base + h.table_offset), forest->n_trees,
+                                        X_dev, n_rows, ld, static_cast<int32_t*>(cnt.p), stream);
+            if (rc) return rc;
+            e = hipMemcpyAsync(counts.data(), cnt.p, sizeof(int32_t) * counts.size(), hipMemcpyDeviceToHost, stream);
+            if (e == hipSuccess) e = hipStreamSynchronize(stream);
+            if (e != hipSuccess) return fp_set_error(FP_EHIP, "counts: %s", hipGetErrorString(e));
+        }
+        // leaf counts back to the caller's node ids, summed up to the roots
+        const int64_t* offs = reinterpret_cast<const int64_t*>(bytes.data() + h.table_offset);
+        for (int32_t ti = 0; ti < forest->n_trees; ti++) {
+            const fp::TreeShape& t = shapes[ti];
+            std::vector<int64_t> card((size_t)t.size, 0);
+            for (size_t k = t.bfs.size(); k-- > 0;) {  // children before parents
+                const int32_t n = t.bfs[k];
+                const int64_t g = t.base + n;
+                card[n] = forest->feature[g] < 0 ? counts[(size_t)(offs[ti] + (int64_t)k)]
+                                                 : card[forest->left[g]] + card[forest->right[g]];
+            }
+            memcpy(card_out + t.base, card.data(), sizeof(int64_t) * card.size());
+        }
+        return FP_OK;
+    } catch (const std::bad_alloc&) {
+        return fp_set_error(FP_ENOMEM, "out of host memory");
+    }
+}
+
 extern "C" void fp_packed_free(fp_packed* p) { delete p; }
 
 extern "C" int fp_packed_set_tune(fp_packed* p, const fp_tune* tune) {

@@ -61,6 +61,31 @@ struct NaiveArgs {
     int32_t n_trees, C;
 };
 
+// Leaf statistics from observations (Sec. III-A: the access statistics Stat
+// orders by may be inferred after training from a set of observations): one
+// lane per observation walks every tree of a NAIVE-layout forest and adds one
+// to the counter of the leaf it reaches (position in the layout).  Grid-stride
+// over rows; integer atomics, so the counts are exact and order-independent.
+__global__ __launch_bounds__(256) void leaf_count_kernel(const Node16* __restrict__ nodes,
+                                                         const int64_t* __restrict__ tree_off, int32_t n_trees,
+                                                         const float* __restrict__ X, int64_t n_rows, int64_t ld,
+                                                         int32_t* __restrict__ counts) {
+    for (int64_t row = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; row < n_rows;
+         row += (int64_t)gridDim.x * blockDim.x) {
+        const float* x = X + row * ld;
+        for (int32_t t = 0; t < n_trees; t++) {
+            const Node16* tn = nodes + tree_off[t];
+            int32_t n = 0;
+            while (true) {  // a verified buffer's children come after their parent: the walk ends
+                const Node16 nd = tn[n];
+                if (nd.feat < 0) break;
+                n = x[nd.feat] <= nd.thr ? nd.left : nd.right;
+            }
+            atomicAdd(&counts[tree_off[t] + n], 1);
+        }
+    }
+}
+
 template <bool LDS_VOTES>
 __global__ __launch_bounds__(1024) void naive_kernel(NaiveArgs a) {
     extern __shared__ int32_t vl[];  // [C][blockDim] when LDS_VOTES
@@ -1083,6 +1108,15 @@ int batched_occupancy(int K, int threads, size_t lds, int* blocks_per_cu) {
     hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, fn, threads, lds);
     *blocks_per_cu = (e == hipSuccess && occ > 0) ? occ : 1;
     return FP_OK;
+}
+
+int launch_leaf_counts(const Node16* nodes, const int64_t* tree_off, int32_t n_trees, const float* X, int64_t n_rows,
+                       int64_t ld, int32_t* counts, hipStream_t s) {
+    if (n_rows <= 0 || n_trees <= 0) return FP_OK;
+    const int64_t blocks = std::min<int64_t>((n_rows + 255) / 256, 65536);
+    hipLaunchKernelGGL(leaf_count_kernel, dim3((unsigned)blocks), dim3(256), 0, s, nodes, tree_off, n_trees, X, n_rows,
+                       ld, counts);
+    return check_launch("leaf_count_kernel");
 }
 
 int launch_fill(int32_t* p, int64_t n, int32_t v, hipStream_t s) {

@@ -300,10 +300,11 @@ def tabular_model(model_seed: int = 200) -> TabularModel:
     return TabularModel(pairs, A, w)
 
 
-def tabular_data(n: int, seed: int, start: int = 0, model: TabularModel | None = None):
+def tabular_data(n: int, seed: int, start: int = 0, model: TabularModel | None = None, shift: float = 0.0):
     """Higgs-shaped rows: 21 standard normals plus 7 pairwise products (28 fp32
-    features); label ~ Bernoulli(sigmoid(2 q)) for the standardised quadratic
-    form q = z'Az + w'z (mean tr A, sd sqrt(2 tr A^2 + |w|^2))."""
+    features); label ~ Bernoulli(sigmoid(2 q - shift)) for the standardised
+    quadratic form q = z'Az + w'z (mean tr A, sd sqrt(2 tr A^2 + |w|^2)).
+    shift 0 gives about half positives; shift 3.35 about 10% (class imbalance)."""
     mdl = model or tabular_model()
     mean_q = float(np.trace(mdl.A))
     sd_q = math.sqrt(2.0 * float(np.trace(mdl.A @ mdl.A)) + float(mdl.w @ mdl.w))
@@ -313,7 +314,7 @@ def tabular_data(n: int, seed: int, start: int = 0, model: TabularModel | None =
         prods = z[:, mdl.pairs[:, 0]] * z[:, mdl.pairs[:, 1]]
         q = np.einsum("ij,jk,ik->i", z, mdl.A, z) + z @ mdl.w
         qt = (q - mean_q) / sd_q
-        p1 = 1.0 / (1.0 + np.exp(-2.0 * qt))
+        p1 = 1.0 / (1.0 + np.exp(-(2.0 * qt - shift)))
         y = (rng.random(m) < p1).astype(np.int32)
         X = np.concatenate([z, prods], axis=1).astype(np.float32)
         return X, y
@@ -337,12 +338,13 @@ class Workload:
     predict_seed: int
     forest_seed: int
     kind: str  # "mixture" | "image" | "tabular"
+    shift: float = 0.0  # tabular: label logit offset (class imbalance)
 
     def rows(self, n: int, seed: int, start: int = 0):
         if self.kind == "image":
             return image_data(n, seed, start)
         if self.kind == "tabular":
-            return tabular_data(n, seed, start)
+            return tabular_data(n, seed, start, shift=self.shift)
         return gaussian_mixture(n, self.n_features, self.n_classes, seed, start)
 
     def train_rows(self):
@@ -378,10 +380,16 @@ def image(n_train: int = 60_000, n_trees: int = 128, n_predict: int = 1_000_000)
     return Workload(name, IMAGE_F, IMAGE_C, n_trees, 28, -1, n_train, n_predict, 101, 102, 103, "image")
 
 
-def tabular(n_train: int = 1_000_000, n_trees: int = 1024, n_predict: int = 10_000_000) -> Workload:
-    """28-feature binary tabular rows; 1024 trees, mtry 5, min leaf 1; 1M train, 10M predict."""
+def tabular(n_train: int = 1_000_000, n_trees: int = 1024, n_predict: int = 10_000_000,
+            imbalanced: bool = False) -> Workload:
+    """28-feature binary tabular rows; 1024 trees, mtry 5, min leaf 1; 1M train, 10M predict.
+    imbalanced: about 10% positives (label logit shifted by 3.35), where the
+    splits are more lopsided and Stat has more to gain (Sec. IV-A)."""
     name = "tabular" if (n_train, n_trees) == (1_000_000, 1024) else f"tabular_{n_train}_{n_trees}"
-    return Workload(name, TAB_Z + TAB_P, 2, n_trees, 5, -1, n_train, n_predict, 201, 202, 203, "tabular")
+    if imbalanced:
+        name += "_imb"
+    return Workload(name, TAB_Z + TAB_P, 2, n_trees, 5, -1, n_train, n_predict, 201, 202, 203, "tabular",
+                    shift=3.35 if imbalanced else 0.0)
 
 
 @dataclass

@@ -122,6 +122,46 @@ def test_ablation_orders(small):
                         f"DF- B={B} D={D} K={K}")
 
 
+def test_infer_cardinality_matches_training_counts():
+    """Trees grown without bootstrap: walking the training rows on the GPU
+    gives back exactly the training cardinality of every node, and packing
+    with the inferred statistics gives the same bytes."""
+    X, y = synth.gaussian_mixture(6000, 10, 3, seed=41)
+    f = synth.train_forest(X, y, n_trees=7, n_classes=3, mtry=3, max_depth=14, bootstrap=False, seed=42)
+    card = fp.fp_infer_cardinality(f, torch.from_numpy(X).cuda())
+    for t in range(f.n_trees):
+        assert card[f.tree_node_offset[t]] == len(X)
+    assert np.array_equal(card, f.cardinality)
+    g = f.subset(range(f.n_trees))
+    g.cardinality = card
+    for kw in ({"bin_size": 3, "interleave_depth": 2}, {"layout": fp.FP_LAYOUT_CLUSTERED, "bin_size": 3}):
+        assert np.array_equal(fp.fp_packed_host_bytes(fp.fp_pack_forest(f, **kw)),
+                              fp.fp_packed_host_bytes(fp.fp_pack_forest(g, **kw)))
+
+
+def test_infer_cardinality_invariants(small):
+    """Bootstrap forest, unseen rows (padded leading dimension): each tree's
+    root count is the row count, internal counts are sums of their children,
+    internal counts add up to the checker's node visits, and the leaf counts
+    per class add up to the checker's votes."""
+    f, X, want = small
+    n = 5000
+    Xp = np.full((n, X.shape[1] + 3), np.nan, np.float32)
+    Xp[:, :X.shape[1]] = X[:n]
+    card = fp.fp_infer_cardinality(f, torch.from_numpy(Xp).cuda())
+    votes, _, visits = oracle.predict(f, X[:n], return_visits=True)
+    internal = f.feature >= 0
+    assert card[internal].sum() == visits
+    per_class = np.bincount(f.leaf_class[~internal], weights=card[~internal], minlength=f.n_classes)
+    assert np.array_equal(per_class.astype(np.int64), votes.sum(0))
+    for t in range(f.n_trees):
+        o, e = f.tree_node_offset[t], f.tree_node_offset[t + 1]
+        assert card[o] == n
+        for i in np.nonzero(f.feature[o:e] >= 0)[0]:
+            assert card[o + i] == card[o + f.left[o + i]] + card[o + f.right[o + i]]
+    assert not fp.fp_infer_cardinality(f, torch.empty((0, X.shape[1]), dtype=torch.float32, device="cuda")).any()
+
+
 @pytest.mark.parametrize("n", [0, 1, 15, 17, 257, 4099])
 def test_ragged_and_empty(small, n):
     f, X, _ = small
