@@ -842,8 +842,9 @@ __global__ __launch_bounds__(1024, (MinWaves<K, LAYOUT>::value)) void packed_ker
 // (items are ordered largest first) and restage LDS when the (job, group)
 // changes.  Every workgroup exits once the counter passes n_items.
 template <int K>
-__global__ __launch_bounds__(1024) void batched_kernel(const JobDesc* __restrict__ jobs, const WorkItem* __restrict__ items,
-                                                       int32_t n_items, int32_t* counter) {
+__global__ __launch_bounds__(1024, (K <= 2 ? 8 : 4)) void batched_kernel(const JobDesc* __restrict__ jobs,
+                                                                         const WorkItem* __restrict__ items,
+                                                                         int32_t n_items, int32_t* counter) {
     extern __shared__ __align__(16) unsigned char smem[];
     __shared__ int32_t s_item;
     int staged_job = -1, staged_group = -1, nt = 0;

@@ -114,7 +114,7 @@ def test_batched_workload_64_forests():
     1-200,000 rows each), every forest autotuned, one persistent graph launch.
     Every row's votes sum to its forest's tree count; sampled rows match the
     checker; every forest matches its single-forest prediction exactly."""
-    threads, cursors = 512, 4
+    threads, cursors = 1024, 2
     jobs = []
     for i in range(64):
         w = synth.batched_workload(i)
