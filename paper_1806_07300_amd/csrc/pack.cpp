@@ -1384,6 +1384,12 @@ extern "C" int fp_infer_cardinality(const fp_forest_view* forest, const float* X
         if (n_rows > 0) {
             fp::DevBuf buf, cnt;
             if ((rc = buf.ensure(bytes.size())) || (rc = cnt.ensure(sizeof(int32_t) * counts.size()))) return rc;
+            // once work is queued, every exit waits for the stream before the
+            // buffers above (and the host vectors the copies use) go away
+            struct Drain {
+                hipStream_t s;
+                ~Drain() { (void)hipStreamSynchronize(s); }
+            } drain{stream};
             hipError_t e = hipMemcpyAsync(buf.p, bytes.data(), bytes.size(), hipMemcpyHostToDevice, stream);
             if (e == hipSuccess) e = hipMemsetAsync(cnt.p, 0, sizeof(int32_t) * counts.size(), stream);
             if (e != hipSuccess) return fp_set_error(FP_EHIP, "upload: %s", hipGetErrorString(e));
