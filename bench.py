@@ -20,6 +20,11 @@ Extra modes:
                              forest, every rung checked bit for bit against
                              BF; tabular_imb is the 10%-positive variant
                              (128 trees); prints one JSON line
+  --probes                   the ceilings: HBM stream rate, dependent random
+                             gathers (16/48-byte fetches, 1-4 chains per lane)
+                             against working-set size, host-to-device copy
+                             rate, and the naive kernel's workgroup-size sweep
+                             on the image workload; prints one JSON line
 """
 from __future__ import annotations
 
@@ -285,6 +290,65 @@ def ladder(args, fp, synth, torch):
                       "rungs": rungs}), flush=True)
 
 
+def gather_ceiling(fp, torch, working_set: int, fetch_bytes: int, chains=(1, 2, 4)) -> dict:
+    """Best dependent-gather rate over chains per lane through a buffer of
+    about `working_set` bytes (the probe rounds the element count down to a
+    power of two)."""
+    buf = torch.empty(max(working_set, 1024 * fetch_bytes) // 4 + 16, dtype=torch.int32, device="cuda")
+    n = 1
+    while n * 2 * fetch_bytes <= buf.numel() * 4:
+        n *= 2
+    best = max((fp.fp_probe_gather(buf, fetch_bytes, c, steps=max(64, 1024 // c)), c) for c in chains)
+    del buf
+    return {"working_set_bytes": n * fetch_bytes, "fetch_bytes": fetch_bytes, "fetches_per_s": best[0],
+            "gbps": best[0] * fetch_bytes / 1e9, "chains_per_lane": best[1]}
+
+
+def probes(args, fp, synth, torch):
+    out = {"probes": True}
+    a = torch.ones(1 << 29, dtype=torch.int32, device="cuda")  # 2 GiB
+    b = torch.empty_like(a)
+    out["stream_gbps"] = max(fp.fp_probe_stream(a, b) for _ in range(3))
+    log(f"stream copy: {out['stream_gbps']:.0f} GB/s (read + write)")
+    del a, b
+    curve = []
+    for ws in (1 << 20, 4 << 20, 16 << 20, 64 << 20, 256 << 20, 1 << 30, 4 << 30, 8 << 30):
+        for fb in (16, 48):
+            g = gather_ceiling(fp, torch, ws, fb)
+            curve.append(g)
+            log(f"gather {g['working_set_bytes'] / 2**20:8.1f} MiB x {fb:2d} B: {g['fetches_per_s'] / 1e9:7.1f} G fetches/s "
+                f"= {g['gbps']:7.0f} GB/s ({g['chains_per_lane']} chains per lane)")
+    out["gather"] = curve
+    # host-to-device rate of the image batch from pinned memory
+    w = synth.image(n_predict=args.rows)
+    forest = w.forest(cache_dir=args.cache)
+    X, _ = w.predict_rows()
+    Xh = torch.from_numpy(X).pin_memory()
+    Xd = torch.empty_like(Xh, device="cuda")
+    Xd.copy_(Xh, non_blocking=True)
+    torch.cuda.synchronize()
+    t0, t1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    t0.record()
+    Xd.copy_(Xh, non_blocking=True)
+    t1.record()
+    torch.cuda.synchronize()
+    h2d_ms = t0.elapsed_time(t1)
+    out["h2d"] = {"bytes": X.nbytes, "ms": h2d_ms, "gbps": X.nbytes / (h2d_ms * 1e-3) / 1e9}
+    log(f"host to device (pinned): {X.nbytes / 2**30:.2f} GiB in {h2d_ms:.1f} ms = {out['h2d']['gbps']:.1f} GB/s")
+    # the naive kernel's own workgroup-size sweep (same layout, flags and resident rows)
+    naive = fp.fp_pack_forest(forest, layout=fp.FP_LAYOUT_NAIVE)
+    fp.fp_packed_upload(naive)
+    votes = torch.empty((X.shape[0], forest.n_classes), dtype=torch.int32, device="cuda")
+    cls = torch.empty((X.shape[0],), dtype=torch.int32, device="cuda")
+    sweep = {}
+    for th in (64, 128, 256, 512, 1024):
+        ms, _ = time_steps(lambda: fp.fp_predict_tuned(naive, {"block_threads": th}, Xd, votes, cls), 5, 1, torch)
+        sweep[th] = ms
+        log(f"naive, {th:4d}-thread workgroups: {ms:.2f} ms")
+    out["naive_sweep_ms"] = sweep
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -298,6 +362,7 @@ def main():
     ap.add_argument("--serve-seconds", type=float, default=10.0)
     ap.add_argument("--serve-rate", type=float, default=20000.0)
     ap.add_argument("--ladder", choices=["image", "tabular", "tabular_imb"], default=None)
+    ap.add_argument("--probes", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print(f"bench.py measures one GPU only (asked for {args.gpus}); the multi-GPU design is "
@@ -327,6 +392,9 @@ def main():
 
     if args.ladder:
         ladder(args, fp, synth, torch)
+        return
+    if args.probes:
+        probes(args, fp, synth, torch)
         return
 
     t0 = time.perf_counter()
@@ -396,6 +464,13 @@ def main():
     algo_bytes = n * (F * 4 + C * 4 + 4) + info["bytes"]
     achieved = algo_bytes / (ms_packed / 1e3) / 1e9
     traffic = read_traffic()
+    # the dependent-gather ceiling at the packed forest's size, against the
+    # kernel's expected fetch rate (training-distributed fetch units per walk)
+    g = gather_ceiling(fp, torch, 2 * info["bytes"], 48)  # the 48-byte clustered block
+    kernel_fetches = info["expected_fetches"] * forest.n_trees * n / (ms_packed / 1e3)
+    gather = dict(g, kernel_fetches_per_s=kernel_fetches, frac=kernel_fetches / g["fetches_per_s"])
+    log(f"gather ceiling at {g['working_set_bytes'] / 2**20:.1f} MiB: {g['fetches_per_s'] / 1e9:.1f} G fetches/s; "
+        f"kernel {kernel_fetches / 1e9:.1f} G blocks/s")
     out = {
         "metric": METRIC,
         "value": value,
@@ -427,6 +502,7 @@ def main():
             "frac": achieved / HBM_PEAK_GBS,
             "traffic": traffic,
         },
+        "gather": gather,
         "wall_s_timed": wall_packed,
         "pack_s": pack_s,
     }

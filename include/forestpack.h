@@ -498,6 +498,34 @@ typedef struct fp_replay_request {
 int fp_serve_replay(fp_server *s, const fp_replay_request *reqs, int64_t n, int32_t submit_threads,
                     double *latency_ms, double *lag_ms);
 
+/* ------------------------------------------------------------------------ */
+/* Measurement probes (the ceilings the walk is measured against; not part of */
+/* classification)                                                          */
+/* ------------------------------------------------------------------------ */
+/*
+ * HBM stream rate: copies `bytes` (a multiple of 16) from src_dev to dst_dev
+ * (device buffers, 16-byte aligned, caller-owned) with 16-byte coalesced
+ * loads and stores, once to warm up and once timed with HIP events on
+ * `stream`; *gbps = bytes read + written per second / 1e9.
+ * Errors: FP_EINVAL, FP_EHIP.
+ */
+int fp_probe_stream(const void *src_dev, void *dst_dev, uint64_t bytes, double *gbps, void *stream);
+
+/*
+ * Dependent random-gather rate, the ceiling of a walk whose every fetch
+ * needs the previous one (Sec. III: a cache miss per node; on the GPU a
+ * dependent load per node or block).  buf_dev (caller-owned, 16-byte
+ * aligned, `bytes` long, overwritten) is laid out as one pseudo-random cycle
+ * over n elements of fetch_bytes (16, 48 or 64) bytes, n the largest power of
+ * two that fits (at least 1024, at most 2^31); every lane of a full GPU
+ * (2 x CUs workgroups of 1024) follows `chains` (1, 2, 4, 8) independent
+ * chains for `steps` steps, loading each element whole.  *fetches_per_s =
+ * element fetches per second (timed launch after a warm-up).
+ * Errors: FP_EINVAL, FP_EHIP.
+ */
+int fp_probe_gather(void *buf_dev, uint64_t bytes, int32_t fetch_bytes, int32_t chains, int32_t steps,
+                    double *fetches_per_s, void *stream);
+
 #ifdef __cplusplus
 }
 #endif

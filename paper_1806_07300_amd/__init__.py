@@ -124,6 +124,9 @@ def lib():
             "fp_packed_load": ([ctypes.c_char_p, ctypes.POINTER(_vp)], ctypes.c_int),
             "fp_packed_upload": ([_vp, _vp, ctypes.c_size_t, _vp], ctypes.c_int),
             "fp_infer_cardinality": ([ctypes.POINTER(fp_forest_view), _vp, _i64, _i64, _vp, _vp], ctypes.c_int),
+            "fp_probe_stream": ([_vp, _vp, ctypes.c_uint64, ctypes.POINTER(ctypes.c_double), _vp], ctypes.c_int),
+            "fp_probe_gather": ([_vp, ctypes.c_uint64, _i32, _i32, _i32, ctypes.POINTER(ctypes.c_double), _vp],
+                                ctypes.c_int),
             "fp_packed_free": ([_vp], None),
             "fp_packed_set_tune": ([_vp, ctypes.POINTER(fp_tune)], ctypes.c_int),
             "fp_packed_get_tune": ([_vp, ctypes.POINTER(fp_tune)], ctypes.c_int),
@@ -362,6 +365,23 @@ def fp_infer_cardinality(forest, X, stream=None):
                                       _stream_ptr(stream)), "fp_infer_cardinality")
     del keep
     return card
+
+
+def fp_probe_stream(src, dst, stream=None) -> float:
+    """HBM stream rate in GB/s (read + write) of copying CUDA tensor src into dst."""
+    nbytes = min(src.numel() * src.element_size(), dst.numel() * dst.element_size()) // 16 * 16
+    out = ctypes.c_double(0.0)
+    _check(lib().fp_probe_stream(_vp(src.data_ptr()), _vp(dst.data_ptr()), nbytes, ctypes.byref(out),
+                                 _stream_ptr(stream)), "fp_probe_stream")
+    return out.value
+
+
+def fp_probe_gather(buf, fetch_bytes: int = 16, chains: int = 1, steps: int = 256, stream=None) -> float:
+    """Dependent random fetches per second through CUDA tensor buf (overwritten)."""
+    out = ctypes.c_double(0.0)
+    _check(lib().fp_probe_gather(_vp(buf.data_ptr()), buf.numel() * buf.element_size(), fetch_bytes, chains, steps,
+                                 ctypes.byref(out), _stream_ptr(stream)), "fp_probe_gather")
+    return out.value
 
 
 # ---------------------------------------------------------------------------
