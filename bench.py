@@ -468,7 +468,9 @@ def main():
     # kernel's expected fetch rate (training-distributed fetch units per walk)
     g = gather_ceiling(fp, torch, 2 * info["bytes"], 48)  # the 48-byte clustered block
     kernel_fetches = info["expected_fetches"] * forest.n_trees * n / (ms_packed / 1e3)
-    gather = dict(g, kernel_fetches_per_s=kernel_fetches, frac=kernel_fetches / g["fetches_per_s"])
+    gather = {"working_set_bytes": g["working_set_bytes"], "fetch_bytes": g["fetch_bytes"],
+              "probe_fetches_per_s": g["fetches_per_s"], "probe_chains_per_lane": g["chains_per_lane"],
+              "kernel_block_fetches_per_s": kernel_fetches, "kernel_over_probe": kernel_fetches / g["fetches_per_s"]}
     log(f"gather ceiling at {g['working_set_bytes'] / 2**20:.1f} MiB: {g['fetches_per_s'] / 1e9:.1f} G fetches/s; "
         f"kernel {kernel_fetches / 1e9:.1f} G blocks/s")
     out = {
@@ -502,7 +504,7 @@ def main():
             "frac": achieved / HBM_PEAK_GBS,
             "traffic": traffic,
         },
-        "gather": gather,
+        "gather_probe": gather,
         "wall_s_timed": wall_packed,
         "pack_s": pack_s,
     }
