@@ -253,7 +253,9 @@ int fp_infer_cardinality(const fp_forest_view *forest, const float *X_dev, int64
 /*
  * Launch parameters of the traversal kernels (the GPU form of assigning bins
  * to workers, Sec. III, and of Bin+ round-robin evaluation, Sec. III-B).
- *   rows_per_block  observations per workgroup (packed layouts; 1..4096)
+ *   rows_per_block  observations per workgroup (packed layouts; 1..4096;
+ *                   0: 16, halved until the workgroup's LDS tables fit, e.g.
+ *                   for thousands of classes)
  *   cursors         trees a lane walks concurrently, round-robin (1, 2, 4, 8);
  *                   BLOCKED walks one block per lane and ignores it
  *   tree_groups     bins are split into this many groups, each group handled

@@ -1023,7 +1023,9 @@ int resolve_job(const fp_packed* p, const fp_tune* t, const float* X, int64_t n_
     if (!p->dev) return fp_set_error(FP_ENODEV, "packed forest is not uploaded");
     if (h.n_nodes >= INT32_MAX)
         return fp_set_error(FP_E2BIG, "packed forest has %lld nodes (limit 2^31-1)", (long long)h.n_nodes);
-    const int R = t->rows_per_block > 0 ? t->rows_per_block : 16;
+    // rows_per_block 0: start at 16 and halve until the workgroup's tables fit
+    const bool auto_R = t->rows_per_block <= 0;
+    int R = auto_R ? 16 : t->rows_per_block;
     if (R > 4096) return fp_set_error(FP_EINVAL, "rows_per_block %d exceeds 4096", R);
     int G = t->tree_groups > 0 ? t->tree_groups : 1;
     if (G > h.n_bins) G = h.n_bins;
@@ -1059,19 +1061,33 @@ int resolve_job(const fp_packed* p, const fp_tune* t, const float* X, int64_t n_
     if (t->refill_lanes < 0 || t->refill_lanes > 64) return fp_set_error(FP_EINVAL, "refill_lanes %d outside [0, 64]", t->refill_lanes);
     j->refill_min = t->refill_lanes > 0 ? t->refill_lanes : kDefaultRefillLanes;
     // feature_lds: 1 force LDS staging, -1 read features from memory, 0 automatic
-    j->feat_lds = t->feature_lds >= 0;
     j->F = h.n_features;
-    // whole-row staging: rows start on 16 bytes and the column map fits 8 KB
-    j->stage_rows = j->feat_lds && ld % 4 == 0 && reinterpret_cast<uintptr_t>(X) % 16 == 0 && h.n_features <= 4096;
     j->cap = 0;
-    size_t need = job_lds_layout(j);
+    // LDS need of a tile of r rows, with or without the row tile in LDS
+    auto size_for = [&](int r, bool feat) {
+        j->R = r;
+        j->n_tiles = (int32_t)((n_rows + r - 1) / r);
+        j->feat_lds = feat;
+        // whole-row staging: rows start on 16 bytes and the column map fits 8 KB
+        j->stage_rows = feat && ld % 4 == 0 && reinterpret_cast<uintptr_t>(X) % 16 == 0 && h.n_features <= 4096;
+        return job_lds_layout(j);
+    };
+    // fit by shrinking an automatic tile first (features in LDS matter most),
+    // then by reading features from memory
+    auto fit = [&](bool feat) {
+        size_t need = size_for(R, feat);
+        for (int r = R; need > lds_block && auto_R && r > 1;) {
+            r = std::max(1, r / 2);
+            need = size_for(r, feat);
+        }
+        return need;
+    };
+    size_t need = fit(t->feature_lds >= 0);
     if (need > lds_block) {
         if (t->feature_lds == 1)
             return fp_set_error(FP_E2BIG, "observation tile of %d rows x %d columns does not fit in %zu bytes of LDS",
                                 R, j->Fc, lds_block);
-        j->feat_lds = 0;
-        j->stage_rows = 0;
-        need = job_lds_layout(j);
+        need = fit(false);
         if (need > lds_block)
             return fp_set_error(FP_E2BIG, "per-workgroup tables of %zu bytes exceed %zu bytes of LDS", need, lds_block);
     }

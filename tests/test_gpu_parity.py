@@ -325,3 +325,30 @@ def test_row_staging_ragged_columns(F, pad):
         p = upload(f, layout=layout, bin_size=12, interleave_depth=3)
         assert_same(run(p, Xq, {"rows_per_block": 32, "cursors": 1, "block_threads": 512}, ld_pad=pad), want,
                     f"F={F} pad={pad} layout={layout}")
+
+
+def test_many_classes_and_features():
+    """Wide forests at the layouts' field limits through the kernels: 4,096
+    classes (the packed kernel's vote-counter limit) in the node layouts, 32
+    classes over 4,096 used features in the clustered 64-byte form, and 512
+    features with fp16 thresholds in the clustered 48-byte form."""
+    from handmade import depth3_forest
+    rng = np.random.default_rng(12)
+    feats = lambda n_used, T: [[(7 * t + k) % n_used for k in range(7)] for t in range(T)]
+    cases = [(depth3_forest(600, feats(700, 600), 4096), [{"layout": fp.FP_LAYOUT_NAIVE},
+                                                          {"bin_size": 16, "interleave_depth": 2},
+                                                          {"layout": fp.FP_LAYOUT_COMPACT, "bin_size": 16}]),
+             (depth3_forest(586, feats(4096, 586), 32), [{"layout": fp.FP_LAYOUT_CLUSTERED, "bin_size": 64}]),
+             (depth3_forest(74, feats(512, 74), 32), [{"layout": fp.FP_LAYOUT_CLUSTERED, "bin_size": 74}])]
+    for f, layouts in cases:
+        X = rng.random((3000, f.n_features), dtype=np.float32)
+        want = oracle.predict(f, X)
+        for kw in layouts:
+            try:
+                p = upload(f, **kw)
+            except fp.FPError as e:  # a layout whose fields cannot hold this forest says so
+                assert e.code == fp.FP_E2BIG, kw
+                continue
+            r = 2 if f.n_classes > 1000 else 8  # explicit tiles must fit 4,096 vote counters per row
+            for tune in (None, {"rows_per_block": r, "cursors": 1, "block_threads": 256}):
+                assert_same(run(p, X, tune), want, f"C={f.n_classes} F={f.n_features} {kw} {tune}")

@@ -720,3 +720,27 @@ def test_clustered_verifier_catches_overlapping_exits(small_forest, image_forest
         with pytest.raises(fp.FPError) as e:
             fp.fp_packed_from_bytes(reseal(bad))
         assert e.value.code == fp.FP_ECORRUPT, i
+
+
+def test_clustered_limits():
+    from handmade import depth3_forest
+    """CLUSTERED holds at most 32 classes and 4,096 used features (12-bit
+    fields), and takes the 48-byte form up to 512 used features when every
+    threshold is an fp16 value; past each limit it reports FP_E2BIG or falls
+    back to the 64-byte form, and packs at the limit walk like the checker."""
+    rng = np.random.default_rng(8)
+    def check(f, want_bytes):
+        dec = decode(fp.fp_packed_host_bytes(fp.fp_pack_forest(f, layout=fp.FP_LAYOUT_CLUSTERED, bin_size=64,
+                                                               interleave_depth=3)))
+        assert dec["h"]["block_bytes"] == want_bytes
+        X = rng.random((200, f.n_features), dtype=np.float32)
+        assert (walk(dec, X) == oracle.predict(f, X)[0]).all()
+    feats = lambda n_used, T: [[(7 * t + k) % n_used for k in range(7)] for t in range(T)]
+    check(depth3_forest(74, feats(512, 74), 32), 48)           # 518 splits over exactly 512 features
+    check(depth3_forest(74, feats(513, 74), 32), 64)           # 513 features: 9 bits no longer suffice
+    check(depth3_forest(74, feats(512, 74), 32, thr=0.1), 64)  # 0.1 is not an fp16 value
+    check(depth3_forest(586, feats(4096, 586), 32), 64)        # 4,102 splits over exactly 4,096 features
+    for f in (depth3_forest(586, feats(4097, 586), 32), depth3_forest(8, feats(56, 8), 33)):
+        with pytest.raises(fp.FPError) as e:
+            fp.fp_pack_forest(f, layout=fp.FP_LAYOUT_CLUSTERED)
+        assert e.value.code == fp.FP_E2BIG
