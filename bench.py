@@ -365,8 +365,8 @@ def main():
     ap.add_argument("--probes", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
-        print(f"bench.py measures one GPU only (asked for {args.gpus}); the multi-GPU design is "
-              "described in DESIGN.md and not run here.", file=sys.stderr)
+        print(f"bench.py measures one GPU only (asked for {args.gpus}); rows shard across GPUs with the "
+              "forest replicated and no exchange, which is not run here.", file=sys.stderr)
         sys.exit(2)
 
     import numpy as np
