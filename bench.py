@@ -447,17 +447,19 @@ def main():
     ms_naive, _ = time_steps(run_naive, max(3, args.steps // 2), 1, torch)
     log(f"naive : {ms_naive:.3f} ms/step")
 
-    cpu = None
-    visits_per_row = None
-    if not args.no_cpu_baseline:
-        cpu, visits_per_row = cpu_baseline(forest, X)
-        log(f"cpu baseline: {cpu['value']:.0f} obs/s ({cpu['sample']})")
-
+    # serving first: the checker's OpenMP threads may keep spinning after their
+    # run and would delay the replay driver's submissions
     serve = None
     if not args.no_serve:
         serve = serve_leg(fp, synth, np, torch, forest, args.serve_seconds, 1.0, args.serve_rate, args.cache)
         log(f"serve: p50 {serve['p50_ms']:.2f} ms, p99 {serve['p99_ms']:.2f} ms, "
             f"{serve['served_rows_per_s'] / 1e6:.2f} M rows/s, saturated={serve['saturated']}")
+
+    cpu = None
+    visits_per_row = None
+    if not args.no_cpu_baseline:
+        cpu, visits_per_row = cpu_baseline(forest, X)
+        log(f"cpu baseline: {cpu['value']:.0f} obs/s ({cpu['sample']})")
 
     value = n / (ms_packed / 1e3)
     # compulsory HBM bytes per launch: observations in, votes and classes out, the packed forest once
