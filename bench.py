@@ -107,7 +107,7 @@ def cpu_baseline(forest, X, target_s=10.0):
             "sample": f"first {n} rows of the batch, all {n_threads} host threads, {dt:.1f} s"}, visits / n
 
 
-def serve_leg(fp, synth, np, torch, image_forest, seconds, warm, rate, cache, submit_threads=2):
+def serve_leg(fp, synth, np, torch, image_forest, seconds, warm, rate, cache, submit_threads=2, launch=None):
     """Open-loop serving measurement: 8 resident forests (the image forest, a
     tabular forest, six of the 64 batched-workload forests chosen by seed 4),
     Poisson arrivals at `rate` requests/s, rows per request log-uniform in
@@ -119,7 +119,8 @@ def serve_leg(fp, synth, np, torch, image_forest, seconds, warm, rate, cache, su
     workloads = [("image", synth.image(), image_forest),
                  ("tabular", synth.tabular(n_train=200_000, n_trees=128), None)]
     workloads += [(f"batched_{i}", synth.batched_workload(i), None) for i in picks]
-    server = fp.fp_server_create(hbm_budget_bytes=4 << 30, max_inflight=4, max_rows_per_launch=262144)
+    server = fp.fp_server_create(hbm_budget_bytes=4 << 30, max_inflight=4, max_rows_per_launch=262144,
+                                 **(launch or {}))
     forests = []
     for name, w, f in workloads:
         f = f if f is not None else w.forest(cache_dir=cache)

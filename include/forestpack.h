@@ -436,8 +436,8 @@ typedef struct fp_server_opts {
     int64_t max_rows_per_launch; /* coalescing cap per launch (0: 262144) */
     int32_t max_inflight;        /* launches in flight (0: 4) */
     int32_t max_queue;           /* pending requests before FP_EAGAIN (0: 1 << 20) */
-    int32_t block_threads;       /* workgroup size of the launches (0: 512) */
-    int32_t cursors;             /* cursors per lane (0: 4) */
+    int32_t block_threads;       /* workgroup size of the launches (0: 1024) */
+    int32_t cursors;             /* cursors per lane (0: 2) */
 } fp_server_opts;
 
 typedef struct fp_serve_stats {
