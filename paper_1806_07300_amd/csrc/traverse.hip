@@ -46,6 +46,7 @@ namespace {
 
 constexpr int32_t kDone = INT32_MIN;
 constexpr int kDefaultRefillLanes = 16;
+constexpr int kStageBatch = 4;  // row loads a thread issues before scattering them (tile staging)
 
 // ---------------------------------------------------------------------------
 // naive kernel
@@ -202,22 +203,36 @@ __device__ __forceinline__ void stage_tile(const JobDesc& j, float* xs, int32_t*
         int r = tid / Q, qd = tid - r * Q;
         const float4* xrow = reinterpret_cast<const float4*>(j.X + (row0 + r) * j.ld);
         const int64_t ld4 = j.ld / 4, dld4 = (int64_t)dq * ld4;
+        // kStageBatch independent 16-byte loads in flight per thread, then
+        // their scatter into the compacted columns
         while (r < rows) {
-            const float4 v = xrow[qd];
-            const int2 m2 = *reinterpret_cast<const int2*>(imap + 4 * qd);
-            const int m0 = (int16_t)(m2.x & 0xFFFF), m1 = m2.x >> 16, m2v = (int16_t)(m2.y & 0xFFFF), m3 = m2.y >> 16;
-            float* dst = xs + r * j.Fcp;
-            if (m0 >= 0) dst[m0] = v.x;
-            if (m1 >= 0) dst[m1] = v.y;
-            if (m2v >= 0) dst[m2v] = v.z;
-            if (m3 >= 0) dst[m3] = v.w;
-            r += dq;
-            xrow += dld4;
-            qd += dc;
-            if (qd >= Q) {
-                qd -= Q;
-                r += 1;
-                xrow += ld4;
+            float4 v[kStageBatch];
+            int rr[kStageBatch], qq[kStageBatch];
+#pragma unroll
+            for (int u = 0; u < kStageBatch; u++) {
+                rr[u] = r;
+                qq[u] = qd;
+                if (r < rows) v[u] = xrow[qd];
+                r += dq;
+                xrow += dld4;
+                qd += dc;
+                if (qd >= Q) {
+                    qd -= Q;
+                    r += 1;
+                    xrow += ld4;
+                }
+            }
+#pragma unroll
+            for (int u = 0; u < kStageBatch; u++) {
+                if (rr[u] >= rows) break;
+                const int2 m2 = *reinterpret_cast<const int2*>(imap + 4 * qq[u]);
+                const int m0 = (int16_t)(m2.x & 0xFFFF), m1 = m2.x >> 16, m2v = (int16_t)(m2.y & 0xFFFF),
+                          m3 = m2.y >> 16;
+                float* dst = xs + rr[u] * j.Fcp;
+                if (m0 >= 0) dst[m0] = v[u].x;
+                if (m1 >= 0) dst[m1] = v[u].y;
+                if (m2v >= 0) dst[m2v] = v[u].z;
+                if (m3 >= 0) dst[m3] = v[u].w;
             }
         }
     } else if (feat_lds) {
