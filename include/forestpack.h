@@ -265,7 +265,14 @@ int fp_infer_cardinality(const fp_forest_view *forest, const float *X_dev, int64
  *   lds_top_nodes   bin-top nodes staged in LDS (0: the whole top region as far
  *                   as LDS allows; -1: none)
  *   feature_lds     1: stage the observation tile in LDS (FP_E2BIG if it cannot
- *                   fit); -1: read features from memory; 0: LDS when it fits
+ *                   fit); -1: read features from memory; 0: LDS when it fits;
+ *                   2: as 1, always in fp32.  Otherwise the LDS tile of a
+ *                   CLUSTERED forest in its 48-byte form (every threshold
+ *                   exact in fp16) holds fp16 values rounded toward
+ *                   +infinity, half the bytes per row: for a threshold t
+ *                   exact in fp16, x <= t holds exactly when the rounded
+ *                   x <= t, so votes do not change (NaN stays NaN and goes
+ *                   right); twice the rows fit a given LDS budget
  *   refill_lanes    a wavefront hands its idle cursors new walks once this many
  *                   of its lanes (1..64) are idle in a cursor slot, or when none
  *                   is walking; larger values spend fewer instructions on

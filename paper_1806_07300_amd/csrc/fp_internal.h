@@ -202,7 +202,7 @@ struct JobDesc {
     int64_t n_rows;
     int32_t* votes;
     int32_t* cls;
-    int32_t Fc, Fcp, C;        // used feature columns, LDS row stride (floats), classes
+    int32_t Fc, Fcp, C;        // used feature columns, LDS row stride (elements), classes
     int32_t n_bins, bin_size;
     int32_t R;                 // observations per tile
     int32_t G, bins_per_group, trees_per_group;
@@ -218,7 +218,7 @@ struct JobDesc {
     int32_t F;                 // feature columns of a row (the forest's n_features)
     int32_t stage_rows;        // 1: stage tiles with whole-row 16-byte loads through imap
     int32_t off_imap;          // LDS: column -> compacted feature (int16, -1 unused), 4 * ceil(F / 4) entries
-    int32_t pad4;
+    int32_t x16;               // 1: the LDS tile holds fp16 features rounded toward +inf (CLUSTERED 48-byte form)
 };
 
 // One entry of the batched work list: tiles [tile_begin, tile_end) of job

@@ -34,6 +34,7 @@
 #include <cstdio>
 #include <cstring>
 #include <mutex>
+#include <type_traits>
 
 #include "fp_internal.h"
 
@@ -186,10 +187,30 @@ __device__ __forceinline__ void refill(int32_t (&ref)[K], int32_t* pool, int U, 
     }
 }
 
+// fp16 bits of the smallest fp16 value >= x (round toward +infinity; NaN
+// stays NaN): the nearest-even conversion, moved up one step when it fell
+// below x.  Stepping the bits up a positive value, or down a negative one,
+// gives the next larger value, and -0 steps to the smallest subnormal.
+__device__ __forceinline__ uint16_t half_up(float x) {
+    const _Float16 h = (_Float16)x;
+    uint32_t b = __builtin_bit_cast(uint16_t, h);
+    if ((float)h < x) b = (b & 0x8000u) ? (b == 0x8000u ? 1u : b - 1u) : b + 1u;
+    return (uint16_t)b;
+}
+
+// Stores one staged feature: fp32, or fp16 rounded toward +infinity.
+template <bool X16>
+__device__ __forceinline__ void put_feature(void* row, int c, float v) {
+    if constexpr (X16) static_cast<uint16_t*>(row)[c] = half_up(v);
+    else static_cast<float*>(row)[c] = v;
+}
+
 // Copies the used feature columns of tile rows [row0, row0 + rows) into LDS
-// (row-major, row stride Fcp), clears the tile's vote counters and the unit
-// pool, then synchronises.  Element i = r * Fc + c goes to thread i mod
-// blockDim, which steps (r, c) and the row pointer incrementally.
+// (row-major, row stride Fcp elements of fp32, or of fp16 when X16), clears
+// the tile's vote counters and the unit pool, then synchronises.  Element
+// i = r * Fc + c goes to thread i mod blockDim, which steps (r, c) and the
+// row pointer incrementally.
+template <bool X16 = false>
 __device__ __forceinline__ void stage_tile(const JobDesc& j, float* xs, int32_t* vl, int32_t* pool, int64_t row0,
                                            int rows, bool feat_lds) {
     const int tid = threadIdx.x, bd = blockDim.x;
@@ -228,11 +249,12 @@ __device__ __forceinline__ void stage_tile(const JobDesc& j, float* xs, int32_t*
                 const int2 m2 = *reinterpret_cast<const int2*>(imap + 4 * qq[u]);
                 const int m0 = (int16_t)(m2.x & 0xFFFF), m1 = m2.x >> 16, m2v = (int16_t)(m2.y & 0xFFFF),
                           m3 = m2.y >> 16;
-                float* dst = xs + rr[u] * j.Fcp;
-                if (m0 >= 0) dst[m0] = v[u].x;
-                if (m1 >= 0) dst[m1] = v[u].y;
-                if (m2v >= 0) dst[m2v] = v[u].z;
-                if (m3 >= 0) dst[m3] = v[u].w;
+                void* dst = X16 ? static_cast<void*>(reinterpret_cast<uint16_t*>(xs) + rr[u] * j.Fcp)
+                                : static_cast<void*>(xs + rr[u] * j.Fcp);
+                if (m0 >= 0) put_feature<X16>(dst, m0, v[u].x);
+                if (m1 >= 0) put_feature<X16>(dst, m1, v[u].y);
+                if (m2v >= 0) put_feature<X16>(dst, m2v, v[u].z);
+                if (m3 >= 0) put_feature<X16>(dst, m3, v[u].w);
             }
         }
     } else if (feat_lds) {
@@ -243,7 +265,8 @@ __device__ __forceinline__ void stage_tile(const JobDesc& j, float* xs, int32_t*
         const int64_t dld = (int64_t)dq * j.ld;
 #pragma unroll 4
         while (r < rows) {
-            xs[r * j.Fcp + c] = xrow[j.fmap[c]];
+            if constexpr (X16) reinterpret_cast<uint16_t*>(xs)[r * j.Fcp + c] = half_up(xrow[j.fmap[c]]);
+            else xs[r * j.Fcp + c] = xrow[j.fmap[c]];
             r += dq;
             xrow += dld;
             c += dc;
@@ -626,20 +649,37 @@ __device__ __forceinline__ float half_lo(uint32_t v) {
 __device__ __forceinline__ float half_hi(uint32_t v) {
     return (float)__builtin_bit_cast(_Float16, (unsigned short)(v >> 16));
 }
+// The same halves as fp16 values.
+__device__ __forceinline__ _Float16 bits_lo16(uint32_t v) {
+    return __builtin_bit_cast(_Float16, (unsigned short)(v & 0xFFFFu));
+}
+__device__ __forceinline__ _Float16 bits_hi16(uint32_t v) {
+    return __builtin_bit_cast(_Float16, (unsigned short)(v >> 16));
+}
 
 // CLUSTERED block: reads the seven split outcomes (one LDS round trip, as in
 // the BLOCKED walk), tests four exits per 32-bit operation against the
 // outcome mask replicated into every byte, and returns the next reference:
 // the child block or the class of the one exit whose pattern matches.
-// C48: the 48-byte form (fp16 thresholds, widened before the fp32 compare,
-// and 9-bit features); otherwise the 64-byte form.
-template <bool C48, typename Le>
+// C48: the 48-byte form (fp16 thresholds and 9-bit features); otherwise the
+// 64-byte form.  H16 (48-byte form only): `le` compares fp16 thresholds with
+// an fp16 tile; else the thresholds are widened to fp32 first.
+template <bool C48, bool H16, typename Le>
 __device__ __forceinline__ int32_t cluster_step(const uint4 (&q)[4], int32_t xrow, Le&& le) {
-    float thr[7];
+    static_assert(C48 || !H16, "fp16 compares need fp16 thresholds");
+    using Thr = std::conditional_t<H16, _Float16, float>;
+    Thr thr[7];
     uint32_t care_lo, care_hi, val_lo, val_hi, r[5], f[7], child_base, n_child;
+    if constexpr (H16) {
+        thr[0] = bits_lo16(q[0].x); thr[1] = bits_hi16(q[0].x); thr[2] = bits_lo16(q[0].y);
+        thr[3] = bits_hi16(q[0].y); thr[4] = bits_lo16(q[0].z); thr[5] = bits_hi16(q[0].z);
+        thr[6] = bits_lo16(q[0].w);
+    }
     if constexpr (C48) {
-        thr[0] = half_lo(q[0].x); thr[1] = half_hi(q[0].x); thr[2] = half_lo(q[0].y); thr[3] = half_hi(q[0].y);
-        thr[4] = half_lo(q[0].z); thr[5] = half_hi(q[0].z); thr[6] = half_lo(q[0].w);
+        if constexpr (!H16) {
+            thr[0] = half_lo(q[0].x); thr[1] = half_hi(q[0].x); thr[2] = half_lo(q[0].y); thr[3] = half_hi(q[0].y);
+            thr[4] = half_lo(q[0].z); thr[5] = half_hi(q[0].z); thr[6] = half_lo(q[0].w);
+        }
         care_lo = q[1].x; care_hi = q[1].y; val_lo = q[1].z; val_hi = q[1].w;
         r[0] = q[2].x; r[1] = q[2].y; r[2] = q[2].z; r[3] = q[2].w;
         static_assert(fp::kC48FeatPos[0] == 48 && fp::kC48FeatPos[1] == 64 && fp::kC48FeatPos[2] == 73 &&
@@ -690,10 +730,13 @@ __device__ __forceinline__ int32_t cluster_step(const uint4 (&q)[4], int32_t xro
 // the path is resolved from a mask of sides by selects (no divergence inside
 // a block).
 // FMT: 0 BLOCKED 48-byte blocks, 1 BLOCKED 64-byte blocks, 2 CLUSTERED
-// 64-byte blocks, 3 CLUSTERED 48-byte blocks.
+// 64-byte blocks, 3 CLUSTERED 48-byte blocks, 4 CLUSTERED 48-byte blocks
+// over an fp16 tile (features in LDS only).
 template <int K, int FMODE, int FMT>
 __device__ void run_tile_blocked(const JobDesc& j, int nt, int tile, unsigned char* smem) {
-    constexpr bool B48 = FMT == 0 || FMT == 3;
+    constexpr bool B48 = FMT == 0 || FMT >= 3;
+    constexpr bool X16 = FMT == 4;
+    static_assert(!X16 || FMODE != 0, "an fp16 tile lives in LDS (x16 is set only with feat_lds)");
     const bool feat_lds = FMODE == 2 ? (j.feat_lds != 0) : (FMODE == 1);
     const int4* ttab = reinterpret_cast<const int4*>(smem + j.off_ttab);
     const int32_t* fmap_l = reinterpret_cast<const int32_t*>(smem + j.off_fmap);
@@ -709,7 +752,7 @@ __device__ void run_tile_blocked(const JobDesc& j, int nt, int tile, unsigned ch
 
     const int64_t row0 = (int64_t)tile * j.R;
     const int rows_here = (int)min<int64_t>(j.R, j.n_rows - row0);
-    stage_tile(j, xs, vl, pool, row0, rows_here, feat_lds);
+    stage_tile<X16>(j, xs, vl, pool, row0, rows_here, feat_lds);
 
     const int U = rows_here * nt;
     const uint32_t rmagic = 0xFFFFFFFFu / (uint32_t)rows_here;
@@ -720,6 +763,9 @@ __device__ void run_tile_blocked(const JobDesc& j, int nt, int tile, unsigned ch
         const float x = feat_lds ? lds_ptr<float>((uint32_t)xrow)[f] : j.X[(row0 + xrow) * j.ld + fmap_l[f]];
         return x <= thr;
     };
+    // the same over an fp16 tile: exact for thresholds exact in fp16, since
+    // the tile holds each x rounded toward +infinity
+    auto le16 = [&](int32_t xrow, uint32_t f, _Float16 thr) { return lds_ptr<_Float16>((uint32_t)xrow)[f] <= thr; };
     const uint32_t xs_addr = lds_addr(xs), blocks_addr = lds_addr(smem + j.off_top);
     // the block an exit leaves to: rank from the code (48-byte form) or the table
     auto exit_to = [&](const BlockView& b, uint32_t e, uint32_t code) -> int32_t {
@@ -736,7 +782,7 @@ __device__ void run_tile_blocked(const JobDesc& j, int nt, int tile, unsigned ch
         ref[k] = kDone; xrow[k] = 0; vrow[k] = 0; ns[k] = 0; la[k] = 0; bp[k] = nullptr;
     }
     auto take = [&](int k, int r, int4 e) -> int32_t {
-        xrow[k] = feat_lds ? (int32_t)(xs_addr + 4u * __umul24((uint32_t)r, (uint32_t)j.Fcp)) : r;
+        xrow[k] = feat_lds ? (int32_t)(xs_addr + (X16 ? 2u : 4u) * __umul24((uint32_t)r, (uint32_t)j.Fcp)) : r;
         vrow[k] = (int32_t)__umul24((uint32_t)r, (uint32_t)j.C);
         bp[k] = (const global_u32x4*)(words + e.y);
         la[k] = blocks_addr + 16u * (uint32_t)e.z;
@@ -765,8 +811,10 @@ __device__ void run_tile_blocked(const JobDesc& j, int nt, int tile, unsigned ch
         for (int k = 0; k < K; k++) {
             if (ref[k] < 0) continue;
             int32_t nr;
-            if constexpr (FMT >= 2) {
-                nr = cluster_step<FMT == 3>(q[k], xrow[k], le);
+            if constexpr (X16) {
+                nr = cluster_step<true, true>(q[k], xrow[k], le16);
+            } else if constexpr (FMT >= 2) {
+                nr = cluster_step<FMT == 3, false>(q[k], xrow[k], le);
             } else if (const BlockView b = view_block<B48>(q[k]); feat_lds) {
                 // all seven split tests (absent slots are zero words: feature
                 // 0, harmless) packed into a mask of sides, bit s set = slot s
@@ -847,8 +895,14 @@ __global__ __launch_bounds__(1024, (MinWaves<K, LAYOUT>::value)) void packed_ker
         if (LAYOUT == FP_LAYOUT_COMPACT) run_tile_compact<K, FMODE>(j, nt, tile, smem);
         else if (LAYOUT == FP_LAYOUT_BLOCKED && j.block_bytes == 48) run_tile_blocked<K, FMODE, 0>(j, nt, tile, smem);
         else if (LAYOUT == FP_LAYOUT_BLOCKED) run_tile_blocked<K, FMODE, 1>(j, nt, tile, smem);
-        else if (LAYOUT == FP_LAYOUT_CLUSTERED && j.block_bytes == 48) run_tile_blocked<K, FMODE, 3>(j, nt, tile, smem);
-        else if (LAYOUT == FP_LAYOUT_CLUSTERED) run_tile_blocked<K, FMODE, 2>(j, nt, tile, smem);
+        else if (LAYOUT == FP_LAYOUT_CLUSTERED && j.block_bytes == 48) {
+            if constexpr (FMODE == 1) {
+                if (j.x16) run_tile_blocked<K, 1, 4>(j, nt, tile, smem);
+                else run_tile_blocked<K, 1, 3>(j, nt, tile, smem);
+            } else {
+                run_tile_blocked<K, FMODE, 3>(j, nt, tile, smem);
+            }
+        } else if (LAYOUT == FP_LAYOUT_CLUSTERED) run_tile_blocked<K, FMODE, 2>(j, nt, tile, smem);
         else run_tile<K, FMODE>(j, nt, tile, smem);
     }
 }
@@ -881,7 +935,8 @@ __global__ __launch_bounds__(1024, (K <= 2 ? 8 : 4)) void batched_kernel(const J
             for (int tile = w.tile_begin; tile < w.tile_end; tile++) run_tile_compact<K, 2>(j, nt, tile, smem);
         else if (j.layout >= FP_LAYOUT_BLOCKED)
             for (int tile = w.tile_begin; tile < w.tile_end; tile++) {
-                if (j.layout == FP_LAYOUT_CLUSTERED && j.block_bytes == 48) run_tile_blocked<1, 2, 3>(j, nt, tile, smem);
+                if (j.layout == FP_LAYOUT_CLUSTERED && j.block_bytes == 48 && j.x16) run_tile_blocked<1, 2, 4>(j, nt, tile, smem);
+                else if (j.layout == FP_LAYOUT_CLUSTERED && j.block_bytes == 48) run_tile_blocked<1, 2, 3>(j, nt, tile, smem);
                 else if (j.layout == FP_LAYOUT_CLUSTERED) run_tile_blocked<1, 2, 2>(j, nt, tile, smem);
                 else if (j.block_bytes == 48) run_tile_blocked<1, 2, 0>(j, nt, tile, smem);
                 else run_tile_blocked<1, 2, 1>(j, nt, tile, smem);
@@ -1018,7 +1073,7 @@ size_t job_lds_layout(JobDesc* j) {
     j->off_ttab = (int32_t)o;  o += (size_t)j->trees_per_group * 16;
     j->off_fmap = (int32_t)o;  o += j->feat_lds ? 0 : round16((size_t)j->Fc * 4);
     j->off_imap = (int32_t)o;  o += j->stage_rows ? round16((size_t)(j->F + 3) / 4 * 4 * 2) : 0;
-    j->off_xs = (int32_t)o;    o += j->feat_lds ? round16((size_t)j->R * j->Fcp * 4) : 0;
+    j->off_xs = (int32_t)o;    o += j->feat_lds ? round16((size_t)j->R * j->Fcp * (j->x16 ? 2 : 4)) : 0;
     j->off_votes = (int32_t)o; o += round16((size_t)j->R * j->C * 4);
     j->off_pool = (int32_t)o;  o += 16;
     j->lds_bytes = (int32_t)o;
@@ -1075,7 +1130,12 @@ int resolve_job(const fp_packed* p, const fp_tune* t, const float* X, int64_t n_
     j->block_bytes = h.block_bytes;
     if (t->refill_lanes < 0 || t->refill_lanes > 64) return fp_set_error(FP_EINVAL, "refill_lanes %d outside [0, 64]", t->refill_lanes);
     j->refill_min = t->refill_lanes > 0 ? t->refill_lanes : kDefaultRefillLanes;
-    // feature_lds: 1 force LDS staging, -1 read features from memory, 0 automatic
+    // feature_lds: 1 force LDS staging, 2 force it in fp32, -1 read features
+    // from memory, 0 automatic
+    if (t->feature_lds < -1 || t->feature_lds > 2) return fp_set_error(FP_EINVAL, "feature_lds %d outside [-1, 2]", t->feature_lds);
+    // fp16 tile: exact where every threshold is exact in fp16 (the CLUSTERED
+    // 48-byte form)
+    const bool x16_ok = t->feature_lds != 2 && h.layout == FP_LAYOUT_CLUSTERED && h.block_bytes == 48;
     j->F = h.n_features;
     j->cap = 0;
     // LDS need of a tile of r rows, with or without the row tile in LDS
@@ -1083,6 +1143,7 @@ int resolve_job(const fp_packed* p, const fp_tune* t, const float* X, int64_t n_
         j->R = r;
         j->n_tiles = (int32_t)((n_rows + r - 1) / r);
         j->feat_lds = feat;
+        j->x16 = feat && x16_ok;
         // whole-row staging: rows start on 16 bytes and the column map fits 8 KB
         j->stage_rows = feat && ld % 4 == 0 && reinterpret_cast<uintptr_t>(X) % 16 == 0 && h.n_features <= 4096;
         return job_lds_layout(j);
@@ -1099,7 +1160,7 @@ int resolve_job(const fp_packed* p, const fp_tune* t, const float* X, int64_t n_
     };
     size_t need = fit(t->feature_lds >= 0);
     if (need > lds_block) {
-        if (t->feature_lds == 1)
+        if (t->feature_lds >= 1)
             return fp_set_error(FP_E2BIG, "observation tile of %d rows x %d columns does not fit in %zu bytes of LDS",
                                 R, j->Fc, lds_block);
         need = fit(false);

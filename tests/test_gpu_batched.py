@@ -109,6 +109,7 @@ def test_autotune_small(small_jobs):
     assert np.array_equal(v.cpu().numpy(), j["want"][0]) and np.array_equal(c.cpu().numpy(), j["want"][1])
 
 
+@pytest.mark.timeout(900)  # trains 64 forests on the host first (about a minute on 16 threads)
 def test_batched_workload_64_forests():
     """The 64-forest workload (16-2048 trees, 4-784 features, 2-10 classes,
     1-200,000 rows each), every forest autotuned, one persistent graph launch.
@@ -122,6 +123,8 @@ def test_batched_workload_64_forests():
         X, _ = w.predict_rows()
         Xd = torch.from_numpy(X).cuda()
         res = fp.fp_autotune(f, Xd, block_threads=threads, cursors=cursors, sample_rows=16384)
+        if i % 8 == 7:
+            print(f"[batched] {i + 1} forests trained and tuned", flush=True)
         p = fp.fp_pack_forest(f, **res["pack"])
         fp.fp_packed_upload(p)
         fp.fp_packed_set_tune(p, res["tune"])

@@ -204,9 +204,10 @@ def test_strided_rows_and_special_values(small):
 
 
 def test_fp16_threshold_blocks_special_values():
-    """CLUSTERED 48-byte blocks (fp16 thresholds widened in the kernel): a
-    forest whose thresholds are fp16 subnormals and an image forest, with rows
-    on the thresholds, one fp32 ulp either side, and non-finite values."""
+    """CLUSTERED 48-byte blocks (fp16 thresholds): a forest whose thresholds
+    are fp16 subnormals and an image forest, with rows on the thresholds, one
+    fp32 ulp either side, and non-finite values; the default launch walks an
+    fp16 tile, features from memory meet the thresholds widened to fp32."""
     rng = np.random.default_rng(5)
     Xi = rng.integers(0, 120, size=(4000, 6))
     y = ((Xi[:, 0] + Xi[:, 1] * 2 + rng.integers(0, 40, 4000)) // 70).astype(np.int32)
@@ -352,3 +353,63 @@ def test_many_classes_and_features():
             r = 2 if f.n_classes > 1000 else 8  # explicit tiles must fit 4,096 vote counters per row
             for tune in (None, {"rows_per_block": r, "cursors": 1, "block_threads": 256}):
                 assert_same(run(p, X, tune), want, f"C={f.n_classes} F={f.n_features} {kw} {tune}")
+
+
+def test_fp16_tile_rounding_edges():
+    """The fp16 observation tile of the CLUSTERED 48-byte form (features
+    rounded toward +infinity): thresholds across the fp16 range (subnormals,
+    +-65504, integers where the fp16 step is 2) and features on them, one
+    fp32 ulp beside them, halfway to their fp16 neighbours (where nearest-even
+    rounding would land on the threshold) and beyond the fp16 range.  The
+    fp16 tile, the fp32 tile (feature_lds 2) and features from memory all
+    equal the checker; a tile that fits LDS only in fp16 is refused in fp32."""
+    from handmade import depth3_forest
+    rng = np.random.default_rng(21)
+    n_used, T = 512, 74
+    f = depth3_forest(T, [[(7 * t + k) % n_used for k in range(7)] for t in range(T)], 5)
+    bits = np.arange(1 << 16, dtype=np.uint32).astype(np.uint16).view(np.float16)
+    fin = bits[np.isfinite(bits)]
+    special = np.array([0.0, -0.0, 65504, -65504, 2.0 ** -24, -(2.0 ** -24), 2.0 ** -14, 1.0, 2048, 2050, 0.5,
+                        1000.5, -3.25], np.float16)
+    thr = np.concatenate([special, fin[rng.integers(0, fin.size, f.n_trees * 15)]])[:f.n_trees * 15]
+    f.threshold[:] = rng.permutation(thr).astype(np.float32)
+    internal = f.feature >= 0
+    n = 6000
+    X = np.empty((n, f.n_features), np.float32)
+    col_thr = [f.threshold[internal & (f.feature == c)] for c in range(f.n_features)]
+    for c in range(f.n_features):
+        t = rng.choice(col_thr[c], n).astype(np.float16)
+        t32 = t.astype(np.float32).astype(np.float64)
+        with np.errstate(over="ignore"):
+            up = np.nextafter(t, np.float16(np.inf)).astype(np.float64)
+            dn = np.nextafter(t, np.float16(-np.inf)).astype(np.float64)
+        up = np.where(np.isinf(up), 65520.0, up)
+        dn = np.where(np.isinf(dn), -65520.0, dn)
+        cand = np.stack([t32, (t32 + up) / 2, (t32 + dn) / 2, up, dn]).astype(np.float32)
+        x = cand[rng.integers(0, 5, n), np.arange(n)]
+        step = rng.integers(-1, 2, n)
+        x = np.where(step > 0, np.nextafter(x, np.float32(np.inf)),
+                     np.where(step < 0, np.nextafter(x, np.float32(-np.inf)), x))
+        m = rng.random(n)
+        x[m < 0.02] = np.nan
+        x[(m >= 0.02) & (m < 0.03)] = np.float32(1e-40)
+        x[(m >= 0.03) & (m < 0.04)] = np.float32(-1e-40)
+        x[(m >= 0.04) & (m < 0.05)] = np.float32(65519.99)
+        x[(m >= 0.05) & (m < 0.06)] = np.float32(-7e4)
+        x[(m >= 0.06) & (m < 0.07)] = -np.inf
+        x[(m >= 0.07) & (m < 0.08)] = np.inf
+        X[:, c] = x
+    want = oracle.predict(f, X)
+    p = upload(f, layout=fp.FP_LAYOUT_CLUSTERED, bin_size=T, interleave_depth=3)
+    assert decode(fp.fp_packed_host_bytes(p))["h"]["block_bytes"] == 48
+    # 64 rows of 513 fp16 columns fit a workgroup's LDS; in fp32 they do not
+    for tune in (None, {"rows_per_block": 64, "feature_lds": 1}, {"rows_per_block": 16, "feature_lds": 2},
+                 {"rows_per_block": 16, "feature_lds": -1}, {"rows_per_block": 7, "block_threads": 256}):
+        assert_same(run(p, X, tune), want, f"{tune}")
+        assert_same(run(p, X, tune, ld_pad=3), want, f"{tune} padded ld")
+    with pytest.raises(fp.FPError) as e:
+        run(p, X, {"rows_per_block": 64, "feature_lds": 2})
+    assert e.value.code == fp.FP_E2BIG
+    with pytest.raises(fp.FPError) as e:
+        run(p, X, {"feature_lds": 3})
+    assert e.value.code == fp.FP_EINVAL
