@@ -136,6 +136,16 @@ def serve_leg(fp, synth, np, torch, image_forest, seconds, warm, rate, cache, su
         forests.append({"name": name, "pool": pool, "C": f.n_classes, "id": fp.fp_server_add_forest(server, p),
                         "alone": v.cpu().numpy(), "packed": p})
     log("serve forests: " + ", ".join(x["name"] for x in forests))
+    # warm the serving path before the replay: the first launches load the
+    # kernels' code and first touch the staging rings, which took ~0.5 s and
+    # left a backlog reaching past the replay's warm-up second
+    for x in forests:
+        for n in (1, 4096):
+            out = np.empty((n, x["C"]), np.int32)
+            fp.fp_serve_poll(server, fp.fp_serve_submit(server, x["id"], x["pool"][:n], out))
+            if not np.array_equal(out, x["alone"][:n]):
+                raise RuntimeError(f"serve warm-up: {x['name']} votes differ from fp_predict")
+    fp.fp_server_reset_stats(server)
     total = int(rate * (warm + seconds))
     gen = np.random.default_rng(5000)
     arrival = np.cumsum(gen.exponential(1.0 / rate, size=total))

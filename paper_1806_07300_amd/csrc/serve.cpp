@@ -50,6 +50,32 @@ constexpr size_t kTableBytes = 4u << 20;  // per slot: job table + work items
 
 size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
 
+// Writes one byte of every 4 KiB page of a fresh host buffer (several
+// threads for large buffers), so that its pages are mapped before requests
+// stream through it: left to the first pass of requests through the rings,
+// the page faults held submits back by up to half a second.
+void touch_pages(void* p, size_t n) {
+    volatile uint8_t* b = static_cast<uint8_t*>(p);
+    auto run = [b](size_t lo, size_t hi) {
+        for (size_t i = lo; i < hi; i += 4096) b[i] = 0;
+    };
+    const size_t kSlice = size_t(256) << 20;
+    if (n <= kSlice) {
+        run(0, n);
+        return;
+    }
+    const size_t T = std::min<size_t>(8, (n + kSlice - 1) / kSlice);
+    const size_t per = (n / T + 4095) / 4096 * 4096;
+    std::vector<std::thread> th;
+    try {
+        for (size_t t = 1; t < T; t++) th.emplace_back(run, t * per, std::min(n, (t + 1) * per));
+    } catch (const std::system_error&) {
+        for (size_t t = 1 + th.size(); t < T; t++) run(t * per, std::min(n, (t + 1) * per));  // no more threads
+    }
+    run(0, std::min(n, per));
+    for (auto& t : th) t.join();
+}
+
 enum State { kStaging = 0, kWaiting, kQueued, kInflight, kDone, kFailed };
 
 struct Request {
@@ -365,6 +391,8 @@ extern "C" int fp_server_create(const fp_server_opts* opts, fp_server** out) {
         e = hipHostMalloc((void**)&s->h_x, xcap, hipHostMallocDefault);
         if (e == hipSuccess) e = hipHostMalloc((void**)&s->h_v, vcap, hipHostMallocDefault);
         if (e != hipSuccess) return fp_set_error(FP_ENOMEM, "hipHostMalloc staging: %s", hipGetErrorString(e));
+        touch_pages(s->h_x, xcap);
+        touch_pages(s->h_v, vcap);
         s->slots.resize(o.max_inflight);
         for (auto& sl : s->slots) {
             HIPCHK(hipStreamCreateWithFlags(&sl.stream, hipStreamNonBlocking));
