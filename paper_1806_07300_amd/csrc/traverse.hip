@@ -187,8 +187,26 @@ __device__ __forceinline__ void refill(int32_t (&ref)[K], int32_t* pool, int U, 
     }
 }
 
-// fp16 bits of the smallest fp16 value >= x (round toward +infinity; NaN
-// stays NaN): the nearest-even conversion, moved up one step when it fell
+// fp16 bits (low half of each result) of the smallest fp16 values >= a, b,
+// c, d (round toward +infinity; NaN stays NaN, beyond the fp16 range +inf
+// or -65504): the wave's round mode for fp16 results (MODE bits 3:2) is set
+// to +infinity for the four conversions and back to nearest-even, the
+// kernel's mode, after them, inside one block so that no other instruction
+// runs in between.
+__device__ __forceinline__ void half_up4(float a, float b, float c, float d, uint32_t (&h)[4]) {
+    asm volatile(
+        "s_setreg_imm32_b32 hwreg(HW_REG_MODE, 2, 2), 1\n\t"
+        "s_nop 1\n\t"
+        "v_cvt_f16_f32 %0, %4\n\t"
+        "v_cvt_f16_f32 %1, %5\n\t"
+        "v_cvt_f16_f32 %2, %6\n\t"
+        "v_cvt_f16_f32 %3, %7\n\t"
+        "s_setreg_imm32_b32 hwreg(HW_REG_MODE, 2, 2), 0"
+        : "=&v"(h[0]), "=&v"(h[1]), "=&v"(h[2]), "=&v"(h[3])
+        : "v"(a), "v"(b), "v"(c), "v"(d));
+}
+// The same for one value without touching the round mode (the column-wise
+// staging path): the nearest-even conversion, moved up one step when it fell
 // below x.  Stepping the bits up a positive value, or down a negative one,
 // gives the next larger value, and -0 steps to the smallest subnormal.
 __device__ __forceinline__ uint16_t half_up(float x) {
@@ -198,10 +216,10 @@ __device__ __forceinline__ uint16_t half_up(float x) {
     return (uint16_t)b;
 }
 
-// Stores one staged feature: fp32, or fp16 rounded toward +infinity.
+// Stores one staged feature: fp32, or fp16 bits already rounded up.
 template <bool X16>
-__device__ __forceinline__ void put_feature(void* row, int c, float v) {
-    if constexpr (X16) static_cast<uint16_t*>(row)[c] = half_up(v);
+__device__ __forceinline__ void put_feature(void* row, int c, float v, uint32_t h) {
+    if constexpr (X16) static_cast<uint16_t*>(row)[c] = (uint16_t)h;
     else static_cast<float*>(row)[c] = v;
 }
 
@@ -251,10 +269,12 @@ __device__ __forceinline__ void stage_tile(const JobDesc& j, float* xs, int32_t*
                           m3 = m2.y >> 16;
                 void* dst = X16 ? static_cast<void*>(reinterpret_cast<uint16_t*>(xs) + rr[u] * j.Fcp)
                                 : static_cast<void*>(xs + rr[u] * j.Fcp);
-                if (m0 >= 0) put_feature<X16>(dst, m0, v[u].x);
-                if (m1 >= 0) put_feature<X16>(dst, m1, v[u].y);
-                if (m2v >= 0) put_feature<X16>(dst, m2v, v[u].z);
-                if (m3 >= 0) put_feature<X16>(dst, m3, v[u].w);
+                uint32_t h[4] = {0, 0, 0, 0};
+                if constexpr (X16) half_up4(v[u].x, v[u].y, v[u].z, v[u].w, h);
+                if (m0 >= 0) put_feature<X16>(dst, m0, v[u].x, h[0]);
+                if (m1 >= 0) put_feature<X16>(dst, m1, v[u].y, h[1]);
+                if (m2v >= 0) put_feature<X16>(dst, m2v, v[u].z, h[2]);
+                if (m3 >= 0) put_feature<X16>(dst, m3, v[u].w, h[3]);
             }
         }
     } else if (feat_lds) {
