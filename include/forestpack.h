@@ -134,8 +134,10 @@ enum {
      * three-level subtree, with a table that maps the 7 split outcomes to
      * the block's exit.  A block takes 48 bytes when at most 512 features
      * are used and every threshold of the forest is exactly an fp16 value
-     * (stored as fp16, widened to the same fp32 value before the compare;
-     * e.g. pixel data with half-integer thresholds), else 64 bytes.  Needs
+     * (stored as fp16; e.g. pixel data with half-integer thresholds), else
+     * 64 bytes.  The 48-byte form compares in fp16 against a row tile
+     * rounded toward +infinity, which gives the fp32 compare's result for
+     * every such threshold (see feature_lds).  Needs
      * at most 4,096 used features and 32 classes (FP_E2BIG otherwise);
      * line_align is ignored. */
     FP_LAYOUT_CLUSTERED = 4

@@ -26,6 +26,10 @@
 // several tree groups share the rows (order-independent: still exact).
 //
 // Split test everywhere: x <= threshold in fp32 (v_cmp_le_f32; NaN -> right).
+// The CLUSTERED 48-byte form, whose thresholds are all exact in fp16, stages
+// the tile as fp16 values rounded toward +infinity and compares in fp16
+// (v_cmp_le_f16), which decides every test exactly as the fp32 compare: for
+// t exact in fp16, x <= t exactly when the smallest fp16 value >= x is <= t.
 // Built without fast-math and without denormal flushing.
 #include <hip/hip_runtime.h>
 
