@@ -40,7 +40,7 @@ def test_tabular_full_size():
             ("blocked", {"layout": fp.FP_LAYOUT_BLOCKED, "bin_size": 16, "interleave_depth": 3},
              {"rows_per_block": 256, "cursors": 1, "block_threads": 1024, "refill_lanes": 32}),
             ("clustered", {"layout": fp.FP_LAYOUT_CLUSTERED, "bin_size": 16, "interleave_depth": 3},
-             {"rows_per_block": 256, "cursors": 1, "block_threads": 1024, "refill_lanes": 32}),
+             {"rows_per_block": 512, "cursors": 1, "block_threads": 1024, "refill_lanes": 32}),
             ("naive", {"layout": fp.FP_LAYOUT_NAIVE}, {"block_threads": 256}))
     for name, kw, tune in runs:
         p = fp.fp_pack_forest(f, **kw)
