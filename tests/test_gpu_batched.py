@@ -10,6 +10,7 @@ import torch
 import oracle
 import paper_1806_07300_amd as fp
 import synth
+from packed_format import decode
 
 pytestmark = pytest.mark.gpu
 
@@ -107,6 +108,54 @@ def test_autotune_small(small_jobs):
     v, c = fp.fp_predict_tuned(p, res["tune"], j["Xd"])
     torch.cuda.synchronize()
     assert np.array_equal(v.cpu().numpy(), j["want"][0]) and np.array_equal(c.cpu().numpy(), j["want"][1])
+
+
+@pytest.mark.parametrize("threads,cursors", [(1024, 2), (512, 4)])
+def test_batched_fp16_tile(threads, cursors):
+    """Batched launches that walk the CLUSTERED 48-byte form over an fp16 row
+    tile (rounded toward +infinity) beside the same forest on an fp32 tile
+    and a 64-byte clustered forest: every job equals the checker, with rows
+    on thresholds, halfway to their fp16 neighbours and non-finite values."""
+    w = synth.image(n_train=6000, n_trees=16)
+    f = w.forest()
+    X, _ = w.predict_rows(3001)
+    X = X.copy()
+    rng = np.random.default_rng(31)
+    thr = f.threshold[f.feature >= 0].astype(np.float16)
+    m = rng.random(X.shape)
+    sel = m < 0.2
+    t = rng.choice(thr, size=sel.sum())
+    with np.errstate(over="ignore"):
+        up = np.nextafter(t, np.float16(np.inf)).astype(np.float64)
+    X[sel] = ((t.astype(np.float64) + up) / 2).astype(np.float32)  # nearest-even would land on t or up
+    X[(m >= 0.2) & (m < 0.22)] = np.nan
+    X[(m >= 0.22) & (m < 0.24)] = np.float32(1e-40)
+    X[(m >= 0.24) & (m < 0.26)] = np.float32(7e4)
+    want = oracle.predict(f, X)
+    Xg, yg = synth.gaussian_mixture(4000, 12, 3, seed=77)
+    g = synth.train_forest(Xg, yg, n_trees=20, n_classes=3, mtry=3, max_depth=12, seed=78)
+    Xq, _ = synth.gaussian_mixture(2500, 12, 3, seed=79)
+    jobs = []
+    for forest, rows, tune in ((f, X, {"rows_per_block": 40}), (f, X, {"rows_per_block": 16, "feature_lds": 2}),
+                               (g, Xq, {"rows_per_block": 32})):
+        p = fp.fp_pack_forest(forest, layout=fp.FP_LAYOUT_CLUSTERED, bin_size=8, interleave_depth=3)
+        fp.fp_packed_upload(p)
+        fp.fp_packed_set_tune(p, tune)
+        C = forest.n_classes
+        jobs.append({"packed": p, "Xd": torch.from_numpy(rows).cuda(),
+                     "votes": torch.full((len(rows), C), -7, dtype=torch.int32, device="cuda"),
+                     "cls": torch.full((len(rows),), -7, dtype=torch.int32, device="cuda"),
+                     "want": want if forest is f else oracle.predict(g, Xq)})
+    assert decode(fp.fp_packed_host_bytes(jobs[0]["packed"]))["h"]["block_bytes"] == 48
+    assert decode(fp.fp_packed_host_bytes(jobs[2]["packed"]))["h"]["block_bytes"] == 64
+    plan = fp.fp_plan_create([(j["packed"], j["Xd"], j["votes"], j["cls"]) for j in jobs],
+                             block_threads=threads, cursors=cursors)
+    for replay in range(2):
+        for j in jobs:
+            j["votes"].fill_(-1)
+            j["cls"].fill_(-1)
+        fp.fp_predict_batched(plan)
+        check_jobs(jobs, f"fp16 tile, {threads} x {cursors}, replay {replay}")
 
 
 @pytest.mark.timeout(900)  # trains 64 forests on the host first (about a minute on 16 threads)

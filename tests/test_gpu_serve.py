@@ -18,11 +18,14 @@ pytestmark = pytest.mark.gpu
 @pytest.fixture(scope="module")
 def forests():
     out = []
-    specs = [synth.small(), synth.image(n_train=6000, n_trees=16), synth.tabular(n_train=20_000, n_trees=24)]
+    # the image forest twice: node layout, and the clustered 48-byte form the
+    # batched kernel walks over an fp16 row tile
+    specs = [synth.small(), synth.image(n_train=6000, n_trees=16), synth.tabular(n_train=20_000, n_trees=24),
+             synth.image(n_train=6000, n_trees=16)]
     for i, w in enumerate(specs):
         f = w.forest()
         pool, _ = w.predict_rows(20_000)
-        layout = (fp.FP_LAYOUT_PACKED, fp.FP_LAYOUT_COMPACT, fp.FP_LAYOUT_BLOCKED)[i]
+        layout = (fp.FP_LAYOUT_PACKED, fp.FP_LAYOUT_COMPACT, fp.FP_LAYOUT_BLOCKED, fp.FP_LAYOUT_CLUSTERED)[i]
         p = fp.fp_pack_forest(f, layout=layout, bin_size=8, interleave_depth=3)
         fp.fp_packed_upload(p)
         if i == 1:
