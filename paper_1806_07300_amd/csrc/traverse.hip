@@ -228,7 +228,9 @@ __device__ __forceinline__ void put_feature(void* row, int c, float v, uint32_t 
 }
 
 // Copies the used feature columns of tile rows [row0, row0 + rows) into LDS
-// (row-major, row stride Fcp elements of fp32, or of fp16 when X16), clears
+// (fp32 row-major, row stride Fcp; or, when X16, fp16 feature-major, feature
+// stride Fcp, so that lanes reading one feature of consecutive rows share
+// LDS words), clears
 // the tile's vote counters and the unit pool, then synchronises.  Element
 // i = r * Fc + c goes to thread i mod blockDim, which steps (r, c) and the
 // row pointer incrementally.
@@ -271,14 +273,16 @@ __device__ __forceinline__ void stage_tile(const JobDesc& j, float* xs, int32_t*
                 const int2 m2 = *reinterpret_cast<const int2*>(imap + 4 * qq[u]);
                 const int m0 = (int16_t)(m2.x & 0xFFFF), m1 = m2.x >> 16, m2v = (int16_t)(m2.y & 0xFFFF),
                           m3 = m2.y >> 16;
-                void* dst = X16 ? static_cast<void*>(reinterpret_cast<uint16_t*>(xs) + rr[u] * j.Fcp)
+                // fp32: row rr, element m; fp16: element m * Fcp of row rr
+                void* dst = X16 ? static_cast<void*>(reinterpret_cast<uint16_t*>(xs) + rr[u])
                                 : static_cast<void*>(xs + rr[u] * j.Fcp);
+                const int es = X16 ? j.Fcp : 1;
                 uint32_t h[4] = {0, 0, 0, 0};
                 if constexpr (X16) half_up4(v[u].x, v[u].y, v[u].z, v[u].w, h);
-                if (m0 >= 0) put_feature<X16>(dst, m0, v[u].x, h[0]);
-                if (m1 >= 0) put_feature<X16>(dst, m1, v[u].y, h[1]);
-                if (m2v >= 0) put_feature<X16>(dst, m2v, v[u].z, h[2]);
-                if (m3 >= 0) put_feature<X16>(dst, m3, v[u].w, h[3]);
+                if (m0 >= 0) put_feature<X16>(dst, m0 * es, v[u].x, h[0]);
+                if (m1 >= 0) put_feature<X16>(dst, m1 * es, v[u].y, h[1]);
+                if (m2v >= 0) put_feature<X16>(dst, m2v * es, v[u].z, h[2]);
+                if (m3 >= 0) put_feature<X16>(dst, m3 * es, v[u].w, h[3]);
             }
         }
     } else if (feat_lds) {
@@ -289,7 +293,7 @@ __device__ __forceinline__ void stage_tile(const JobDesc& j, float* xs, int32_t*
         const int64_t dld = (int64_t)dq * j.ld;
 #pragma unroll 4
         while (r < rows) {
-            if constexpr (X16) reinterpret_cast<uint16_t*>(xs)[r * j.Fcp + c] = half_up(xrow[j.fmap[c]]);
+            if constexpr (X16) reinterpret_cast<uint16_t*>(xs)[c * j.Fcp + r] = half_up(xrow[j.fmap[c]]);
             else xs[r * j.Fcp + c] = xrow[j.fmap[c]];
             r += dq;
             xrow += dld;
@@ -686,8 +690,9 @@ __device__ __forceinline__ _Float16 bits_hi16(uint32_t v) {
 // outcome mask replicated into every byte, and returns the next reference:
 // the child block or the class of the one exit whose pattern matches.
 // C48: the 48-byte form (fp16 thresholds and 9-bit features); otherwise the
-// 64-byte form.  H16 (48-byte form only): `le` compares fp16 thresholds with
-// an fp16 tile; else the thresholds are widened to fp32 first.
+// 64-byte form.  H16 (48-byte form only): `le` loads a feature of an fp16
+// tile, compared with the fp16 thresholds; else `le` compares with the
+// thresholds widened to fp32.
 template <bool C48, bool H16, typename Le>
 __device__ __forceinline__ int32_t cluster_step(const uint4 (&q)[4], int32_t xrow, Le&& le) {
     static_assert(C48 || !H16, "fp16 compares need fp16 thresholds");
@@ -729,8 +734,17 @@ __device__ __forceinline__ int32_t cluster_step(const uint4 (&q)[4], int32_t xro
         child_base = cfield<132, 24>(r);
     }
     uint32_t g = 0;
+    if constexpr (H16) {
+        // all seven features loaded before any compare: one LDS round trip
+        _Float16 x[7];
 #pragma unroll
-    for (int sl = 0; sl < 7; sl++) g |= (le(xrow, f[sl], thr[sl]) ? 0u : 1u) << sl;
+        for (int sl = 0; sl < 7; sl++) x[sl] = le(xrow, f[sl]);
+#pragma unroll
+        for (int sl = 0; sl < 7; sl++) g |= (x[sl] <= thr[sl] ? 0u : 1u) << sl;
+    } else {
+#pragma unroll
+        for (int sl = 0; sl < 7; sl++) g |= (le(xrow, f[sl], thr[sl]) ? 0u : 1u) << sl;
+    }
     const uint32_t g4 = __builtin_amdgcn_perm(g, g, 0u);  // byte 0 of g copied into every byte
     const uint32_t z_lo = zero_bytes((g4 ^ val_lo) & care_lo), z_hi = zero_bytes((g4 ^ val_hi) & care_hi);
     // a verified block's used exits partition the outcomes: exactly one byte
@@ -787,9 +801,13 @@ __device__ void run_tile_blocked(const JobDesc& j, int nt, int tile, unsigned ch
         const float x = feat_lds ? lds_ptr<float>((uint32_t)xrow)[f] : j.X[(row0 + xrow) * j.ld + fmap_l[f]];
         return x <= thr;
     };
-    // the same over an fp16 tile: exact for thresholds exact in fp16, since
-    // the tile holds each x rounded toward +infinity
-    auto le16 = [&](int32_t xrow, uint32_t f, _Float16 thr) { return lds_ptr<_Float16>((uint32_t)xrow)[f] <= thr; };
+    // the same over an fp16 tile (feature-major, feature stride Fcp): exact
+    // for thresholds exact in fp16, since the tile holds each x rounded
+    // toward +infinity
+    const uint32_t fstride = 2u * (uint32_t)j.Fcp;
+    auto le16 = [&](int32_t xrow, uint32_t f) -> _Float16 {
+        return *lds_ptr<_Float16>((uint32_t)xrow + __umul24(f, fstride));
+    };
     const uint32_t xs_addr = lds_addr(xs), blocks_addr = lds_addr(smem + j.off_top);
     // the block an exit leaves to: rank from the code (48-byte form) or the table
     auto exit_to = [&](const BlockView& b, uint32_t e, uint32_t code) -> int32_t {
@@ -806,7 +824,9 @@ __device__ void run_tile_blocked(const JobDesc& j, int nt, int tile, unsigned ch
         ref[k] = kDone; xrow[k] = 0; vrow[k] = 0; ns[k] = 0; la[k] = 0; bp[k] = nullptr;
     }
     auto take = [&](int k, int r, int4 e) -> int32_t {
-        xrow[k] = feat_lds ? (int32_t)(xs_addr + (X16 ? 2u : 4u) * __umul24((uint32_t)r, (uint32_t)j.Fcp)) : r;
+        xrow[k] = !feat_lds ? r
+                  : X16     ? (int32_t)(xs_addr + 2u * (uint32_t)r)
+                            : (int32_t)(xs_addr + 4u * __umul24((uint32_t)r, (uint32_t)j.Fcp));
         vrow[k] = (int32_t)__umul24((uint32_t)r, (uint32_t)j.C);
         bp[k] = (const global_u32x4*)(words + e.y);
         la[k] = blocks_addr + 16u * (uint32_t)e.z;
@@ -1097,7 +1117,7 @@ size_t job_lds_layout(JobDesc* j) {
     j->off_ttab = (int32_t)o;  o += (size_t)j->trees_per_group * 16;
     j->off_fmap = (int32_t)o;  o += j->feat_lds ? 0 : round16((size_t)j->Fc * 4);
     j->off_imap = (int32_t)o;  o += j->stage_rows ? round16((size_t)(j->F + 3) / 4 * 4 * 2) : 0;
-    j->off_xs = (int32_t)o;    o += j->feat_lds ? round16((size_t)j->R * j->Fcp * (j->x16 ? 2 : 4)) : 0;
+    j->off_xs = (int32_t)o;    o += j->feat_lds ? round16(j->x16 ? (size_t)j->Fc * j->Fcp * 2 : (size_t)j->R * j->Fcp * 4) : 0;
     j->off_votes = (int32_t)o; o += round16((size_t)j->R * j->C * 4);
     j->off_pool = (int32_t)o;  o += 16;
     j->lds_bytes = (int32_t)o;
@@ -1168,6 +1188,10 @@ int resolve_job(const fp_packed* p, const fp_tune* t, const float* X, int64_t n_
         j->n_tiles = (int32_t)((n_rows + r - 1) / r);
         j->feat_lds = feat;
         j->x16 = feat && x16_ok;
+        // fp16 tile: feature-major, the feature stride an odd number of
+        // 4-byte words (rows rounded up to 2 mod 4) so that strided writes
+        // and reads spread over the banks; fp32 tile: row-major, odd stride
+        j->Fcp = j->x16 ? r + (6 - r % 4) % 4 : h.n_used_features | 1;
         // whole-row staging: rows start on 16 bytes and the column map fits 8 KB
         j->stage_rows = feat && ld % 4 == 0 && reinterpret_cast<uintptr_t>(X) % 16 == 0 && h.n_features <= 4096;
         return job_lds_layout(j);
