@@ -97,21 +97,17 @@ static inline uint64_t xo_bounded(xoshiro *r, uint64_t n) {
     return v % n;
 }
 
-/* ---------------- sorting of (value, class) pairs ---------------- */
+/* ---------------- sorting ---------------- */
 static inline uint32_t fkey(float v) {
     uint32_t u; memcpy(&u, &v, 4);
     return (u & 0x80000000u) ? ~u : (u | 0x80000000u);
 }
-/* items: key in the high 32 bits, class in the low bits */
-static void sort_items(uint64_t *a, uint64_t *tmp, int64_t m) {
-    if (m <= 48) {
-        for (int64_t i = 1; i < m; i++) {
-            uint64_t v = a[i]; int64_t j = i - 1;
-            while (j >= 0 && (a[j] >> 32) > (v >> 32)) { a[j + 1] = a[j]; j--; }
-            a[j + 1] = v;
-        }
-        return;
-    }
+static inline float key_to_float(uint32_t k) {
+    uint32_t u = (k & 0x80000000u) ? (k & 0x7FFFFFFFu) : ~k;
+    float v; memcpy(&v, &u, 4); return v;
+}
+/* 64-bit items ordered by their high 32 bits (stable LSD radix, 8-bit digits) */
+static void sort_hi32(uint64_t *a, uint64_t *tmp, int64_t m) {
     uint64_t *src = a, *dst = tmp;
     for (int pass = 0; pass < 4; pass++) {
         int sh = 32 + 8 * pass;
@@ -127,9 +123,81 @@ static void sort_items(uint64_t *a, uint64_t *tmp, int64_t m) {
     }
     if (src != a) memcpy(a, src, (size_t)m * sizeof(uint64_t));
 }
-static inline float key_to_float(uint32_t k) {
-    uint32_t u = (k & 0x80000000u) ? (k & 0x7FFFFFFFu) : ~k;
-    float v; memcpy(&v, &u, 4); return v;
+
+/*
+ * Split keys.  Every training value of feature f is replaced once per
+ * forest by its dense rank among the column's distinct fp32 bit patterns in
+ * ascending order of value (-0 ranks just below +0), and key = rank << 8 |
+ * class.  Ranks order as the values do, so sorting a node's keys by rank
+ * orders its samples by value; vals[f][r] is the value of rank r.  A
+ * boundary between neighbours of ranks ra < rb is a candidate when
+ * vals[ra] < vals[rb], which rules out only -0 | +0 (ra = zneg[f], rb = ra + 1).
+ */
+typedef struct {
+    uint32_t *key;   /* [F][n] */
+    uint32_t *zneg;  /* [F]: rank of -0 when +0 follows it in the column, else UINT32_MAX */
+    float *vals;     /* [F][n]: the column's distinct values, ascending, in the first ranks */
+} cart_ranks;
+
+static int ranks_build(const float *Xt, int64_t n, const int32_t *y, int32_t F, int nt, cart_ranks *rk) {
+    rk->key = (uint32_t *)malloc((size_t)F * (size_t)n * sizeof(uint32_t));
+    rk->vals = (float *)malloc((size_t)F * (size_t)n * sizeof(float));
+    rk->zneg = (uint32_t *)malloc((size_t)F * sizeof(uint32_t));
+    if (!rk->key || !rk->vals || !rk->zneg) return -1;
+    int failed = 0;
+#ifdef _OPENMP
+#pragma omp parallel for schedule(dynamic, 1) num_threads(nt) reduction(| : failed)
+#endif
+    for (int32_t f = 0; f < F; f++) {
+        uint64_t *it = (uint64_t *)malloc((size_t)n * sizeof(uint64_t));
+        uint64_t *tmp = (uint64_t *)malloc((size_t)n * sizeof(uint64_t));
+        if (!it || !tmp) { free(it); free(tmp); failed = 1; continue; }
+        const float *col = Xt + (size_t)f * (size_t)n;
+        for (int64_t i = 0; i < n; i++) it[i] = ((uint64_t)fkey(col[i]) << 32) | (uint64_t)i;
+        sort_hi32(it, tmp, n);
+        uint32_t *key = rk->key + (size_t)f * (size_t)n;
+        float *vals = rk->vals + (size_t)f * (size_t)n;
+        uint32_t r = 0;
+        rk->zneg[f] = UINT32_MAX;
+        for (int64_t k = 0; k < n; k++) {
+            const uint32_t fk = (uint32_t)(it[k] >> 32);
+            if (k == 0) vals[0] = key_to_float(fk);
+            else if (fk != (uint32_t)(it[k - 1] >> 32)) {
+                vals[++r] = key_to_float(fk);
+                if (fk == 0x80000000u && (uint32_t)(it[k - 1] >> 32) == 0x7FFFFFFFu) rk->zneg[f] = r - 1;
+            }
+            const int64_t i = (int64_t)(it[k] & 0xFFFFFFFFu);
+            key[i] = (r << 8) | (uint32_t)y[i];
+        }
+        free(it); free(tmp);
+    }
+    (void)nt;
+    return failed ? -1 : 0;
+}
+
+/* Orders m keys by rank (key >> 8), given every rank lies in [lo, lo + 2^bits):
+ * insertion sort for short runs, else LSD radix over the rank offset. */
+static void sort_keys(uint32_t *a, uint32_t *tmp, int64_t m, uint32_t lo, int bits) {
+    if (m <= 64) {
+        for (int64_t i = 1; i < m; i++) {
+            uint32_t v = a[i]; int64_t j = i - 1;
+            while (j >= 0 && (a[j] >> 8) > (v >> 8)) { a[j + 1] = a[j]; j--; }
+            a[j + 1] = v;
+        }
+        return;
+    }
+    const int d = m < 4096 ? 8 : 11;
+    const uint32_t mask = (1u << d) - 1u;
+    uint32_t cnt[(1 << 11) + 1];
+    uint32_t *src = a, *dst = tmp;
+    for (int sh = 0; sh < bits; sh += d) {
+        memset(cnt, 0, sizeof(uint32_t) * (mask + 2));
+        for (int64_t i = 0; i < m; i++) cnt[((((src[i] >> 8) - lo) >> sh) & mask) + 1]++;
+        for (uint32_t b = 0; b <= mask; b++) cnt[b + 1] += cnt[b];
+        for (int64_t i = 0; i < m; i++) dst[cnt[(((src[i] >> 8) - lo) >> sh) & mask]++] = src[i];
+        uint32_t *t = src; src = dst; dst = t;
+    }
+    if (src != a) memcpy(a, src, (size_t)m * sizeof(uint32_t));
 }
 
 /* score comparison: is (numA/denA) > (numB/denB) ?  all non-negative */
@@ -147,32 +215,38 @@ typedef struct {
 } split_t;
 
 /* Best split of one feature over the node's samples; returns 1 if any. */
-static int best_split_feature(const float *col, const int32_t *y, const int32_t *idx, int64_t m,
-                              int32_t C, const int64_t *tot, uint64_t *items, uint64_t *tmp,
+static int best_split_feature(const uint32_t *key, const float *vals, uint32_t zneg, const int32_t *idx, int64_t m,
+                              int32_t C, const int64_t *tot, uint32_t *items, uint32_t *tmp,
                               int64_t *L, split_t *out) {
+    uint32_t lo = UINT32_MAX, hi = 0;
     for (int64_t i = 0; i < m; i++) {
-        int32_t s = idx[i];
-        items[i] = ((uint64_t)fkey(col[s]) << 32) | (uint32_t)y[s];
+        const uint32_t k = key[idx[i]];
+        items[i] = k;
+        const uint32_t r = k >> 8;
+        lo = r < lo ? r : lo;
+        hi = r > hi ? r : hi;
     }
-    sort_items(items, tmp, m);
-    if ((items[0] >> 32) == (items[m - 1] >> 32)) return 0;
+    if (lo == hi) return 0;
+    int bits = 0;
+    while (bits < 32 && ((hi - lo) >> bits)) bits++;
+    sort_keys(items, tmp, m, lo, bits);
     memset(L, 0, sizeof(int64_t) * (size_t)C);
     uint64_t A = 0; /* sum L_c^2 */
     uint64_t B = 0; /* sum R_c^2 */
     for (int c = 0; c < C; c++) B += (uint64_t)tot[c] * (uint64_t)tot[c];
     int any = 0;
     for (int64_t i = 0; i + 1 < m; i++) {
-        int32_t c = (int32_t)(items[i] & 0xFFFFFFFFu);
-        int64_t Rc = tot[c] - L[c];
+        const uint32_t c = items[i] & 0xFFu;
+        const int64_t Rc = tot[c] - L[c];
         A += 2 * (uint64_t)L[c] + 1;
         B -= 2 * (uint64_t)Rc - 1;
         L[c]++;
-        float a = key_to_float((uint32_t)(items[i] >> 32));
-        float b = key_to_float((uint32_t)(items[i + 1] >> 32));
-        if (!(a < b)) continue;
+        const uint32_t ra = items[i] >> 8, rb = items[i + 1] >> 8;
+        if (ra == rb || (ra == zneg && rb == zneg + 1)) continue; /* equal values, or -0 | +0 */
         uint64_t nL = (uint64_t)(i + 1), nR = (uint64_t)(m - i - 1);
         uint64_t num = A * nR + B * nL, den = nL * nR;
         if (!any || score_greater(num, den, out->num, out->den)) {
+            const float a = vals[ra], b = vals[rb];
             float t = (float)(((double)a + (double)b) * 0.5);
             if (t >= b) t = a;
             out->num = num; out->den = den; out->threshold = t;
@@ -195,20 +269,32 @@ static int tree_grow_cap(cart_tree *t, int64_t need) {
     return 0;
 }
 
-static int train_tree(const float *Xt, int64_t n, const int32_t *y, const cart_params *p,
+/* A node is a multiset of samples: the order of idx inside a node changes
+ * nothing the tree depends on.  It is kept ascending (a counting sort of the
+ * bootstrap draws, then stable partitions), so that the per-node gathers
+ * walk the columns forwards. */
+static int train_tree(const float *Xt, const cart_ranks *rk, int64_t n, const int32_t *y, const cart_params *p,
                       int64_t tree_index, cart_tree *t) {
     const int32_t F = p->n_features, C = p->n_classes;
     xoshiro rng; xo_seed(&rng, p->seed, (uint64_t)tree_index);
     int32_t *idx = (int32_t *)malloc((size_t)n * sizeof(int32_t));
-    uint64_t *items = (uint64_t *)malloc((size_t)n * sizeof(uint64_t));
-    uint64_t *tmp = (uint64_t *)malloc((size_t)n * sizeof(uint64_t));
+    int32_t *side = (int32_t *)malloc((size_t)n * sizeof(int32_t)); /* draw counts, then partition scratch */
+    uint32_t *items = (uint32_t *)malloc((size_t)n * sizeof(uint32_t));
+    uint32_t *tmp = (uint32_t *)malloc((size_t)n * sizeof(uint32_t));
     int32_t *perm = (int32_t *)malloc((size_t)F * sizeof(int32_t));
     int64_t *tot = (int64_t *)malloc((size_t)C * sizeof(int64_t));
     int64_t *L = (int64_t *)malloc((size_t)C * sizeof(int64_t));
     int rc = 0;
-    if (!idx || !items || !tmp || !perm || !tot || !L) { rc = -1; goto done; }
-    if (p->bootstrap) for (int64_t i = 0; i < n; i++) idx[i] = (int32_t)xo_bounded(&rng, (uint64_t)n);
-    else for (int64_t i = 0; i < n; i++) idx[i] = (int32_t)i;
+    if (!idx || !side || !items || !tmp || !perm || !tot || !L) { rc = -1; goto done; }
+    if (p->bootstrap) {
+        memset(side, 0, (size_t)n * sizeof(int32_t));
+        for (int64_t i = 0; i < n; i++) side[xo_bounded(&rng, (uint64_t)n)]++;
+        int64_t k = 0;
+        for (int64_t i = 0; i < n; i++)
+            for (int32_t c = 0; c < side[i]; c++) idx[k++] = (int32_t)i;
+    } else {
+        for (int64_t i = 0; i < n; i++) idx[i] = (int32_t)i;
+    }
 
     memset(t, 0, sizeof *t);
     if (tree_grow_cap(t, 1)) { rc = -1; goto done; }
@@ -234,21 +320,24 @@ static int train_tree(const float *Xt, int64_t n, const int32_t *y, const cart_p
             if (k >= p->mtry && best.found) break;
             int32_t f = perm[k];
             split_t cand; memset(&cand, 0, sizeof cand);
-            if (!best_split_feature(Xt + (size_t)f * (size_t)n, y, idx + lo, m, C, tot, items, tmp, L, &cand))
+            if (!best_split_feature(rk->key + (size_t)f * (size_t)n, rk->vals + (size_t)f * (size_t)n, rk->zneg[f], idx + lo, m,
+                                    C, tot, items, tmp, L, &cand))
                 continue;
             if (!best.found || score_greater(cand.num, cand.den, best.num, best.den)) {
                 best = cand; best.found = 1; best.feature = f;
             }
         }
         if (!best.found) continue;
-        /* partition idx[lo,hi) by x[f] <= thr */
+        /* stable partition of idx[lo,hi) by x[f] <= thr */
         const float *col = Xt + (size_t)best.feature * (size_t)n;
-        int64_t i = lo, j = hi - 1;
-        while (i <= j) {
-            if (col[idx[i]] <= best.threshold) i++;
-            else { int32_t s = idx[i]; idx[i] = idx[j]; idx[j] = s; j--; }
+        int64_t nl = 0, nr = 0;
+        for (int64_t i = lo; i < hi; i++) {
+            const int32_t s = idx[i];
+            if (col[s] <= best.threshold) idx[lo + nl++] = s;
+            else side[nr++] = s;
         }
-        int64_t mid = i;
+        memcpy(idx + lo + nl, side, (size_t)nr * sizeof(int32_t));
+        int64_t mid = lo + nl;
         if (tree_grow_cap(t, t->n_nodes + 2)) { rc = -1; goto done; }
         int64_t l = t->n_nodes, r = l + 1;
         t->n_nodes += 2;
@@ -258,7 +347,7 @@ static int train_tree(const float *Xt, int64_t n, const int32_t *y, const cart_p
         t->lo[r] = mid; t->hi[r] = hi; t->depth[r] = t->depth[q] + 1;
     }
 done:
-    free(idx); free(items); free(tmp); free(perm); free(tot); free(L);
+    free(idx); free(side); free(items); free(tmp); free(perm); free(tot); free(L);
     return rc;
 }
 
@@ -274,34 +363,46 @@ void cart_free(cart_forest *f) {
     free(f);
 }
 
-/* Returns 0 on success, -1 on allocation failure, -2 on invalid arguments. */
+/* Returns 0 on success, -1 on allocation failure, -2 on invalid arguments
+ * (including NaN training values and more than 256 classes). */
 int cart_train(const float *X, int64_t n, int64_t ld, const int32_t *y, const cart_params *p,
                cart_forest **out) {
     *out = NULL;
     /* n <= 4e6 keeps the exact split score (at most n^3/4) inside 64 bits */
     if (!X || !y || !p || n < 1 || n > 4000000LL || ld < p->n_features || p->n_trees < 1 ||
-        p->n_features < 1 || p->n_classes < 1 || p->mtry < 1 || p->min_samples_split < 2)
+        p->n_features < 1 || p->n_classes < 1 || p->n_classes > 256 || p->mtry < 1 || p->min_samples_split < 2)
         return -2;
     for (int64_t i = 0; i < n; i++) if (y[i] < 0 || y[i] >= p->n_classes) return -2;
     const int32_t F = p->n_features;
     /* feature-major copy so that per-node gathers stay within one column */
     float *Xt = (float *)malloc((size_t)n * (size_t)F * sizeof(float));
     if (!Xt) return -1;
+    int nan_seen = 0;
     for (int64_t i = 0; i < n; i++)
-        for (int32_t f = 0; f < F; f++) Xt[(size_t)f * (size_t)n + (size_t)i] = X[(size_t)i * (size_t)ld + f];
-    cart_forest *fo = (cart_forest *)calloc(1, sizeof *fo);
-    if (!fo) { free(Xt); return -1; }
-    fo->n_trees = p->n_trees; fo->n_features = F; fo->n_classes = p->n_classes;
-    fo->trees = (cart_tree *)calloc((size_t)p->n_trees, sizeof(cart_tree));
-    if (!fo->trees) { free(Xt); free(fo); return -1; }
-    int failed = 0;
+        for (int32_t f = 0; f < F; f++) {
+            const float v = X[(size_t)i * (size_t)ld + f];
+            nan_seen |= v != v;
+            Xt[(size_t)f * (size_t)n + (size_t)i] = v;
+        }
+    if (nan_seen) { free(Xt); return -2; }
 #ifdef _OPENMP
     int nt = p->n_threads > 0 ? p->n_threads : omp_get_max_threads();
+#else
+    int nt = 1;
+#endif
+    cart_ranks rk = {NULL, NULL, NULL};
+    if (ranks_build(Xt, n, y, F, nt, &rk)) { free(Xt); free(rk.key); free(rk.zneg); free(rk.vals); return -1; }
+    cart_forest *fo = (cart_forest *)calloc(1, sizeof *fo);
+    if (fo) fo->trees = (cart_tree *)calloc((size_t)p->n_trees, sizeof(cart_tree));
+    if (!fo || !fo->trees) { free(fo); free(Xt); free(rk.key); free(rk.zneg); free(rk.vals); return -1; }
+    fo->n_trees = p->n_trees; fo->n_features = F; fo->n_classes = p->n_classes;
+    int failed = 0;
+#ifdef _OPENMP
 #pragma omp parallel for schedule(dynamic, 1) num_threads(nt) reduction(| : failed)
 #endif
     for (int32_t t = 0; t < p->n_trees; t++)
-        if (train_tree(Xt, n, y, p, (int64_t)p->tree_offset + t, &fo->trees[t])) failed = 1;
-    free(Xt);
+        if (train_tree(Xt, &rk, n, y, p, (int64_t)p->tree_offset + t, &fo->trees[t])) failed = 1;
+    free(Xt); free(rk.key); free(rk.zneg); free(rk.vals);
     if (failed) { cart_free(fo); return -1; }
     *out = fo;
     return 0;

@@ -222,3 +222,106 @@ def test_chunked_training_is_identical():
     assert seen == [(3, 10), (6, 10), (9, 10), (10, 10)]
     for k in ("tree_node_offset", "feature", "threshold", "left", "right", "leaf_class", "cardinality"):
         assert np.array_equal(getattr(a, k), getattr(b, k)), k
+
+
+# --- the node's feature order, restated from the published generators -----
+# SplitMix64 (Steele, Lea, Flood) seeds xoshiro256** (Blackman, Vigna); the
+# tree's stream starts from (forest seed, tree index) and, without bootstrap,
+# its first draws are the root's Fisher-Yates shuffle of the feature indices.
+M64 = (1 << 64) - 1
+
+
+def _splitmix(x):
+    x = (x + 0x9E3779B97F4A7C15) & M64
+    z = x
+    z = ((z ^ (z >> 30)) * 0xBF58476D1CE4E5B9) & M64
+    z = ((z ^ (z >> 27)) * 0x94D049BB133111EB) & M64
+    return x, z ^ (z >> 31)
+
+
+def _rotl(v, k):
+    return ((v << k) | (v >> (64 - k))) & M64
+
+
+def _root_feature_order(seed, tree, F):
+    x = (seed ^ ((0xD1B54A32D192ED03 * (tree + 1)) & M64)) & M64
+    s = []
+    for _ in range(4):
+        x, z = _splitmix(x)
+        s.append(z)
+
+    def nxt():
+        r = (_rotl((s[1] * 5) & M64, 7) * 9) & M64
+        t = (s[1] << 17) & M64
+        s[2] ^= s[0]; s[3] ^= s[1]; s[1] ^= s[2]; s[0] ^= s[3]
+        s[2] ^= t
+        s[3] = _rotl(s[3], 45)
+        return r
+
+    def bounded(n):  # rejection of the biased low range
+        lim = (1 << 64) % n
+        while True:
+            v = nxt()
+            if v >= lim:
+                return v % n
+
+    perm = list(range(F))
+    for i in range(F - 1, 0, -1):
+        j = bounded(i + 1)
+        perm[i], perm[j] = perm[j], perm[i]
+    return perm
+
+
+@pytest.mark.parametrize("seed", range(16))
+def test_cross_feature_tie_keeps_first_in_shuffled_order(seed):
+    """Features 0, 1 and 2 split the rows identically (1 is 0 scaled, 2 is 0
+    negated and so splits the same rows from the other side): three
+    candidates with the same exact Gini score.  The root must split on the
+    tied feature that comes first in the node's shuffled order, whichever
+    that is for this seed; feature 3 is noise with a worse score."""
+    rng = np.random.default_rng(100 + seed)
+    x0 = rng.permutation(np.arange(40, dtype=np.float32))
+    y = (x0 >= 17).astype(np.int32)
+    noise = rng.standard_normal(40).astype(np.float32)
+    X = np.stack([x0, 4.0 * x0, -x0, noise], axis=1).astype(np.float32)
+    f = synth.train_forest(X, y, n_trees=1, n_classes=2, mtry=4, max_depth=1, bootstrap=False, seed=seed)
+    order = _root_feature_order(seed, 0, 4)
+    first_tied = next(k for k in order if k in (0, 1, 2))
+    assert f.feature[0] == first_tied, (order, int(f.feature[0]))
+    # a later tied feature would have been kept by a rule that prefers the last
+    assert f.feature[0] != [k for k in order if k in (0, 1, 2)][-1]
+
+
+@pytest.mark.parametrize("seed", range(12))
+def test_mtry_fallback_searches_past_constant_features(seed):
+    """Three of four features are constant: with mtry = 1 the shuffled list's
+    first feature is usually one of them, and the search must continue down
+    the list until the one separating feature is found (a leaf would be the
+    mistake)."""
+    rng = np.random.default_rng(seed)
+    X = np.zeros((30, 4), np.float32)
+    X[:, 0], X[:, 1], X[:, 2] = 1.0, -2.0, 5.0
+    X[:, 3] = rng.standard_normal(30).astype(np.float32)
+    y = (X[:, 3] > 0).astype(np.int32)
+    f = synth.train_forest(X, y, n_trees=1, n_classes=2, mtry=1, max_depth=1, bootstrap=False, seed=seed)
+    assert f.feature[0] == 3
+    assert X[y == 0, 3].max() <= f.threshold[0] < X[y == 1, 3].min()
+
+
+def test_shuffle_restatement_matches_the_trainer():
+    """The restated shuffle above is the trainer's: with mtry = 1 and every
+    feature separating the rows, the root splits on the order's first entry."""
+    rng = np.random.default_rng(4)
+    X = rng.standard_normal((50, 6)).astype(np.float32)
+    y = (X.sum(1) > 0).astype(np.int32)
+    for seed in range(20):
+        f = synth.train_forest(X, y, n_trees=1, n_classes=2, mtry=1, max_depth=1, bootstrap=False, seed=seed)
+        assert f.feature[0] == _root_feature_order(seed, 0, 6)[0], seed
+
+
+def test_training_rejects_nan():
+    X = np.zeros((10, 2), np.float32)
+    X[3, 1] = np.nan
+    y = np.arange(10, dtype=np.int32) % 2
+    with pytest.raises(RuntimeError):
+        synth.train_forest(X, y, n_trees=1, n_classes=2, mtry=2, bootstrap=False, seed=0)
