@@ -63,6 +63,13 @@ def _load():
         lib.cart_train.argtypes = [vp, ctypes.c_int64, ctypes.c_int64, vp,
                                    ctypes.POINTER(_Params), ctypes.POINTER(vp)]
         lib.cart_train.restype = ctypes.c_int
+        lib.cart_data_create.argtypes = [vp, ctypes.c_int64, ctypes.c_int64, ctypes.c_int32, vp, ctypes.c_int32,
+                                         ctypes.c_int32, ctypes.POINTER(vp)]
+        lib.cart_data_create.restype = ctypes.c_int
+        lib.cart_train_prepared.argtypes = [vp, ctypes.POINTER(_Params), ctypes.POINTER(vp)]
+        lib.cart_train_prepared.restype = ctypes.c_int
+        lib.cart_data_free.argtypes = [vp]
+        lib.cart_data_free.restype = None
         lib.cart_total_nodes.argtypes = [vp]
         lib.cart_total_nodes.restype = ctypes.c_int64
         lib.cart_export.argtypes = [vp] * 9
@@ -136,37 +143,45 @@ def train_forest(X: np.ndarray, y: np.ndarray, *, n_trees: int, n_classes: int, 
     in chunks; with ``progress`` set, trees are trained in chunks of that many
     and ``progress(done, total)`` is called after each chunk."""
     chunk = max(1, int(getattr(progress, "chunk", 64))) if progress is not None else n_trees
-    if chunk < n_trees:
-        parts = []
-        for t0 in range(0, n_trees, chunk):
-            k = min(chunk, n_trees - t0)
-            parts.append(train_forest(X, y, n_trees=k, n_classes=n_classes, mtry=mtry, max_depth=max_depth,
-                                      bootstrap=bootstrap, seed=seed, min_samples_split=min_samples_split,
-                                      n_threads=n_threads, tree_offset=tree_offset + t0))
-            progress(t0 + k, n_trees)
-        return concat_forests(parts)
     lib = _load()
     X = np.ascontiguousarray(X, dtype=np.float32)
     y = np.ascontiguousarray(y, dtype=np.int32)
     n, F = X.shape
-    p = _Params(n_trees, F, n_classes, mtry, max_depth, min_samples_split, int(bool(bootstrap)),
-                n_threads, tree_offset, 0, seed & 0xFFFFFFFFFFFFFFFF)
-    h = ctypes.c_void_p()
-    rc = lib.cart_train(X.ctypes.data, n, F, y.ctypes.data, ctypes.byref(p), ctypes.byref(h))
+    data = ctypes.c_void_p()
+    rc = lib.cart_data_create(X.ctypes.data, n, F, F, y.ctypes.data, n_classes, n_threads, ctypes.byref(data))
     if rc != 0:
-        raise RuntimeError(f"cart_train failed with code {rc}")
+        raise RuntimeError(f"cart_data_create failed with code {rc}")
     try:
-        total = lib.cart_total_nodes(h)
-        off = np.zeros(n_trees + 1, np.int64)
-        arrs = dict(feature=np.empty(total, np.int32), threshold=np.empty(total, np.float32),
-                    left=np.empty(total, np.int32), right=np.empty(total, np.int32),
-                    leaf_class=np.empty(total, np.int32), cardinality=np.empty(total, np.int64),
-                    depth=np.empty(total, np.int32))
-        lib.cart_export(h, off.ctypes.data, *(arrs[k].ctypes.data for k in
-                                                ("feature", "threshold", "left", "right",
-                                                 "leaf_class", "cardinality", "depth")))
+        parts = []
+        for t0 in range(0, n_trees, chunk):
+            k = min(chunk, n_trees - t0)
+            p = _Params(k, F, n_classes, mtry, max_depth, min_samples_split, int(bool(bootstrap)),
+                        n_threads, tree_offset + t0, 0, seed & 0xFFFFFFFFFFFFFFFF)
+            h = ctypes.c_void_p()
+            rc = lib.cart_train_prepared(data, ctypes.byref(p), ctypes.byref(h))
+            if rc != 0:
+                raise RuntimeError(f"cart_train_prepared failed with code {rc}")
+            try:
+                parts.append(_export(lib, h, k, F, n_classes))
+            finally:
+                lib.cart_free(h)
+            if progress is not None:
+                progress(t0 + k, n_trees)
     finally:
-        lib.cart_free(h)
+        lib.cart_data_free(data)
+    return parts[0] if len(parts) == 1 else concat_forests(parts)
+
+
+def _export(lib, h, n_trees, F, n_classes) -> Forest:
+    total = lib.cart_total_nodes(h)
+    off = np.zeros(n_trees + 1, np.int64)
+    arrs = dict(feature=np.empty(total, np.int32), threshold=np.empty(total, np.float32),
+                left=np.empty(total, np.int32), right=np.empty(total, np.int32),
+                leaf_class=np.empty(total, np.int32), cardinality=np.empty(total, np.int64),
+                depth=np.empty(total, np.int32))
+    lib.cart_export(h, off.ctypes.data, *(arrs[k].ctypes.data for k in
+                                            ("feature", "threshold", "left", "right",
+                                             "leaf_class", "cardinality", "depth")))
     return Forest(n_trees, F, n_classes, off, **arrs)
 
 
@@ -365,7 +380,13 @@ class Workload:
                          max_depth=self.max_depth, bootstrap=True, seed=self.forest_seed,
                          n_threads=n_threads, progress=progress)
         if path:
-            f.save(path)
+            try:  # np.savez appends .npz only when missing: save to a temporary name, then rename
+                f.save(path + ".tmp.npz")
+                os.replace(path + ".tmp.npz", path)
+            except OSError as e:  # a full disk only costs the cache
+                print(f"[synth] forest cache not written ({e})", flush=True)
+                if os.path.exists(path + ".tmp.npz"):
+                    os.remove(path + ".tmp.npz")
         return f
 
 

@@ -363,49 +363,98 @@ void cart_free(cart_forest *f) {
     free(f);
 }
 
-/* Returns 0 on success, -1 on allocation failure, -2 on invalid arguments
- * (including NaN training values and more than 256 classes). */
-int cart_train(const float *X, int64_t n, int64_t ld, const int32_t *y, const cart_params *p,
-               cart_forest **out) {
+/* Training data prepared once for any number of cart_train_prepared calls
+ * (a forest trained chunk by chunk): the feature-major copy and the split
+ * keys.  The labels stay the caller's (borrowed until cart_data_free). */
+typedef struct {
+    int64_t n;
+    int32_t F, C;
+    float *Xt;
+    const int32_t *y;
+    cart_ranks rk;
+} cart_data;
+
+void cart_data_free(cart_data *d) {
+    if (!d) return;
+    free(d->Xt); free(d->rk.key); free(d->rk.zneg); free(d->rk.vals);
+    free(d);
+}
+
+/* Returns 0, -1 on allocation failure, -2 on invalid arguments (including
+ * NaN training values, labels outside [0, n_classes) and more than 256
+ * classes). */
+int cart_data_create(const float *X, int64_t n, int64_t ld, int32_t n_features, const int32_t *y,
+                     int32_t n_classes, int32_t n_threads, cart_data **out) {
     *out = NULL;
     /* n <= 4e6 keeps the exact split score (at most n^3/4) inside 64 bits */
-    if (!X || !y || !p || n < 1 || n > 4000000LL || ld < p->n_features || p->n_trees < 1 ||
-        p->n_features < 1 || p->n_classes < 1 || p->n_classes > 256 || p->mtry < 1 || p->min_samples_split < 2)
+    if (!X || !y || n < 1 || n > 4000000LL || n_features < 1 || ld < n_features || n_classes < 1 ||
+        n_classes > 256)
         return -2;
-    for (int64_t i = 0; i < n; i++) if (y[i] < 0 || y[i] >= p->n_classes) return -2;
-    const int32_t F = p->n_features;
+    for (int64_t i = 0; i < n; i++) if (y[i] < 0 || y[i] >= n_classes) return -2;
+    const int32_t F = n_features;
+    cart_data *d = (cart_data *)calloc(1, sizeof *d);
+    if (!d) return -1;
+    d->n = n; d->F = F; d->C = n_classes; d->y = y;
     /* feature-major copy so that per-node gathers stay within one column */
-    float *Xt = (float *)malloc((size_t)n * (size_t)F * sizeof(float));
-    if (!Xt) return -1;
+    d->Xt = (float *)malloc((size_t)n * (size_t)F * sizeof(float));
+    if (!d->Xt) { cart_data_free(d); return -1; }
     int nan_seen = 0;
     for (int64_t i = 0; i < n; i++)
         for (int32_t f = 0; f < F; f++) {
             const float v = X[(size_t)i * (size_t)ld + f];
             nan_seen |= v != v;
-            Xt[(size_t)f * (size_t)n + (size_t)i] = v;
+            d->Xt[(size_t)f * (size_t)n + (size_t)i] = v;
         }
-    if (nan_seen) { free(Xt); return -2; }
+    if (nan_seen) { cart_data_free(d); return -2; }
 #ifdef _OPENMP
-    int nt = p->n_threads > 0 ? p->n_threads : omp_get_max_threads();
+    int nt = n_threads > 0 ? n_threads : omp_get_max_threads();
 #else
     int nt = 1;
+    (void)n_threads;
 #endif
-    cart_ranks rk = {NULL, NULL, NULL};
-    if (ranks_build(Xt, n, y, F, nt, &rk)) { free(Xt); free(rk.key); free(rk.zneg); free(rk.vals); return -1; }
+    if (ranks_build(d->Xt, n, y, F, nt, &d->rk)) { cart_data_free(d); return -1; }
+    *out = d;
+    return 0;
+}
+
+/* Trees [tree_offset, tree_offset + n_trees) of the seeded forest on
+ * prepared data.  Returns 0, -1 on allocation failure, -2 on invalid
+ * arguments. */
+int cart_train_prepared(const cart_data *d, const cart_params *p, cart_forest **out) {
+    *out = NULL;
+    if (!d || !p || p->n_trees < 1 || p->n_features != d->F || p->n_classes != d->C || p->mtry < 1 ||
+        p->min_samples_split < 2)
+        return -2;
+#ifdef _OPENMP
+    int nt = p->n_threads > 0 ? p->n_threads : omp_get_max_threads();
+#endif
     cart_forest *fo = (cart_forest *)calloc(1, sizeof *fo);
     if (fo) fo->trees = (cart_tree *)calloc((size_t)p->n_trees, sizeof(cart_tree));
-    if (!fo || !fo->trees) { free(fo); free(Xt); free(rk.key); free(rk.zneg); free(rk.vals); return -1; }
-    fo->n_trees = p->n_trees; fo->n_features = F; fo->n_classes = p->n_classes;
+    if (!fo || !fo->trees) { free(fo); return -1; }
+    fo->n_trees = p->n_trees; fo->n_features = d->F; fo->n_classes = p->n_classes;
     int failed = 0;
 #ifdef _OPENMP
 #pragma omp parallel for schedule(dynamic, 1) num_threads(nt) reduction(| : failed)
 #endif
     for (int32_t t = 0; t < p->n_trees; t++)
-        if (train_tree(Xt, &rk, n, y, p, (int64_t)p->tree_offset + t, &fo->trees[t])) failed = 1;
-    free(Xt); free(rk.key); free(rk.zneg); free(rk.vals);
+        if (train_tree(d->Xt, &d->rk, d->n, d->y, p, (int64_t)p->tree_offset + t, &fo->trees[t])) failed = 1;
     if (failed) { cart_free(fo); return -1; }
     *out = fo;
     return 0;
+}
+
+/* Prepare and train in one call.  Returns as cart_data_create /
+ * cart_train_prepared. */
+int cart_train(const float *X, int64_t n, int64_t ld, const int32_t *y, const cart_params *p,
+               cart_forest **out) {
+    *out = NULL;
+    if (!p) return -2;
+    cart_data *d = NULL;
+    int rc = cart_data_create(X, n, ld, p->n_features, y, p->n_classes, p->n_threads, &d);
+    if (rc) return rc;
+    rc = cart_train_prepared(d, p, out);
+    cart_data_free(d);
+    return rc;
 }
 
 int64_t cart_total_nodes(const cart_forest *f) {
