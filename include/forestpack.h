@@ -282,6 +282,16 @@ int fp_infer_cardinality(const fp_forest_view *forest, const float *X_dev, int64
  *   lds_bytes       LDS one workgroup may use (0: half of a CU's, so that two
  *                   workgroups share a CU; capped at the device's per-block
  *                   limit); more LDS fits more observations per tile
+ *   tree_passes     the bins are split into this many consecutive groups
+ *                   that run one after the other, each group walked by every
+ *                   workgroup over all rows in a launch of its own, the
+ *                   votes added up in place (0 or 1: one pass).  A forest
+ *                   larger than the caches is then read from memory about
+ *                   once per pass instead of once per row tile: only one
+ *                   group's bins are in use at a time (Sec. III-A, Bin: keep
+ *                   the well-used nodes of few trees cached).  Clamped so
+ *                   that tree_passes x tree_groups <= the number of bins.
+ *                   Batched plans run the passes' groups concurrently.
  * Zero fields mean "library default".  Naive layout uses block_threads only.
  */
 typedef struct fp_tune {
@@ -293,26 +303,69 @@ typedef struct fp_tune {
     int32_t feature_lds;
     int32_t refill_lanes;
     int32_t lds_bytes;
+    int32_t tree_passes;
+    int32_t reserved;
 } fp_tune;
 
-/* Store `tune` as the launch parameters fp_predict uses for p (NULL: defaults). */
+/* Store `tune` as p's own launch parameters (NULL: library defaults): the
+ * ones fp_predict uses for a batch size with no tune recorded by
+ * fp_tune_launch, and batched plans and the server use for p's jobs.
+ * fp_packed_get_tune returns them.  Errors: FP_EINVAL (NULL p / out). */
 int fp_packed_set_tune(fp_packed *p, const fp_tune *tune);
 int fp_packed_get_tune(const fp_packed *p, fp_tune *out);
 
 /*
- * Classify n_rows observations with the uploaded forest p.
+ * Classify n_rows observations with the uploaded forest p: every row walks
+ * every tree (Sec. III), its votes are counted per class and its class is
+ * their argmax (Sec. III-A: packing leaves this result unchanged).
  *   X_dev     device fp32 [n_rows][ld], row-major; ld >= n_features
  *   votes_dev device int32 [n_rows][n_classes], overwritten
  *   class_dev device int32 [n_rows] (argmax, lowest index on ties) or NULL
+ * Launch parameters: the tune recorded by fp_tune_launch for p's bytes and
+ * the batch's size bucket ceil(log2(n_rows)) -- in this process or, with the
+ * FP_TUNE_CACHE environment variable naming a file, by an earlier process --
+ * else p's own (fp_packed_set_tune), else library defaults.
  * n_rows == 0 is a no-op.  Errors: FP_EINVAL (ld < F, null with n_rows > 0,
  * n_rows > 2^31-1), FP_ENODEV (not uploaded, other device), FP_EHIP.
  */
 int fp_predict(const fp_packed *p, const float *X_dev, int64_t n_rows, int64_t ld,
                int32_t *votes_dev, int32_t *class_dev, void *stream);
 
-/* fp_predict with explicit launch parameters (NULL: those of p). */
+/* The launch parameters fp_predict would use for a batch of n_rows rows of
+ * p (for inspection).  *source (may be NULL): 2 a tune recorded by
+ * fp_tune_launch (this process or the FP_TUNE_CACHE file), 1 p's own
+ * (fp_packed_set_tune), 0 library defaults (*out all zero).  Errors:
+ * FP_EINVAL (NULL p / out). */
+int fp_predict_tune_get(const fp_packed *p, int64_t n_rows, fp_tune *out, int32_t *source);
+
+/* fp_predict with explicit launch parameters (NULL: p's own, as set by
+ * fp_packed_set_tune); no tune record is consulted.  Same arguments, layout,
+ * ownership and errors as fp_predict, plus FP_EINVAL for launch parameters
+ * outside their ranges and FP_E2BIG when the row tile or tables do not fit
+ * the workgroup's LDS. */
 int fp_predict_tuned(const fp_packed *p, const fp_tune *tune, const float *X_dev, int64_t n_rows,
                      int64_t ld, int32_t *votes_dev, int32_t *class_dev, void *stream);
+
+/*
+ * The design experiment of Sec. III-A (Fig. 2) for a forest already packed:
+ * times candidate launch parameters of p (rows per workgroup, workgroup
+ * size, cursors, refill threshold, tree groups) on the first min(n_rows,
+ * 2^18) rows of X_dev, records the fastest for p's bytes and the size bucket
+ * ceil(log2(n_rows)) in the process-wide tune table (fp_predict then uses it
+ * for batches of that bucket; fp_plan_create for jobs of that bucket when
+ * block_threads and cursors match) and, when the FP_TUNE_CACHE environment
+ * variable names a file, appends it there for later processes (a text file,
+ * one record per line; a write failure only loses the record).
+ *   block_threads, cursors  0: searched; > 0: kept fixed (a batched plan fixes
+ *                           both for all its jobs)
+ *   out                     receives the chosen parameters (may be NULL)
+ * Votes never depend on the candidate.  The library allocates and frees a
+ * temporary device buffer for the votes and synchronises `stream`.
+ * Errors: FP_EINVAL (NULL, n_rows < 1, ld < F, naive layout, bad
+ * block_threads / cursors), FP_E2BIG (no candidate fits), FP_ENOMEM, FP_EHIP.
+ */
+int fp_tune_launch(fp_packed *p, const float *X_dev, int64_t n_rows, int64_t ld, int32_t block_threads,
+                   int32_t cursors, fp_tune *out, void *stream);
 
 
 /* ------------------------------------------------------------------------ */
@@ -321,39 +374,61 @@ int fp_predict_tuned(const fp_packed *p, const fp_tune *tune, const float *X_dev
 /*
  * Sec. III-A chooses the stripe width B and the interleave depth D with a
  * design experiment on the target processor (Fig. 2).  fp_autotune runs that
- * experiment on the GPU: it packs the forest with candidate layouts (PACKED,
- * COMPACT, BLOCKED) and (B, D), times candidate launch mappings
- * (observations per workgroup, cursors per lane, workgroup size, tree
- * groups, refill lanes) on a sample of the caller's rows with HIP events,
- * and returns the fastest combination.  Votes are never changed by
- * any candidate.  Results are cached per (forest fingerprint, sample size,
- * options) for the life of the process.
+ * experiment on the GPU with the paper's cost model as its prior:
+ *   1. it packs the forest in every candidate layout (PACKED, COMPACT,
+ *      BLOCKED, CLUSTERED) and (B, D) (B in {T, 64, 16}, D in 0..7; block
+ *      layouts interleave whole three-level blocks, so only D = 0, 3, 6) and
+ *      scores each with Eq. 2's estimate from the packed header's statistics:
+ *      (expected fetches per walk - well-used fetches) / EU, where EU =
+ *      1 + b(1 + b(1 + b)) for node layouts (b the mean split bias), the
+ *      interleaved levels 0..D are the well-used fetches, and a block counts
+ *      as one fetch with EU 1;
+ *   2. within each layout it times the top_k candidates by that score (one
+ *      launch shape per layout kind);
+ *   3. on the fastest packing it searches the launch mapping (rows per
+ *      workgroup, workgroup size, cursors, refill threshold, tree groups)
+ *      as fp_tune_launch does.
+ * Times are HIP-event times on the first min(n_rows, sample_rows) rows.
+ * Votes never depend on any candidate.  Results are kept per (forest
+ * fingerprint, sample size, options) for the process and, when the
+ * FP_TUNE_CACHE environment variable names a file, appended to it and read
+ * back by later processes.
  *
- *   X_dev, n_rows, ld  device fp32 rows used for timing (the first
- *                      min(n_rows, sample_rows) rows are used)
+ *   X_dev, n_rows, ld  device fp32 rows used for timing
  *   opts               NULL for defaults; block_threads / cursors > 0 fix
  *                      those parameters (a batched plan needs one workgroup
  *                      size and cursor count for all forests)
+ *   opts->trials       NULL, or caller memory for max_trials entries: one per
+ *                      packed candidate (model score, time if timed)
  * The library allocates and frees its own temporary device buffers.
  * Errors: FP_EINVAL, FP_ECORRUPT (forest), FP_ENOMEM, FP_EHIP.
  */
+typedef struct fp_autotune_trial {
+    fp_pack_opts pack;      /* the candidate packing */
+    double model_cost;      /* Eq. 2 estimate: T x (expected fetches - well-used) / EU */
+    double ms;              /* timed launch over the sample, -1 if not timed */
+} fp_autotune_trial;
+
 typedef struct fp_autotune_opts {
-    int32_t block_threads;  /* 0: search 256, 512, 1024 */
-    int32_t cursors;        /* 0: search 2, 4 */
+    int32_t block_threads;  /* 0: searched (256, 512, 1024) */
+    int32_t cursors;        /* 0: searched (1, 2, 4) */
     int32_t reps;           /* timed launches per candidate (0: 3) */
-    int32_t reserved;
+    int32_t top_k;          /* packings timed per layout, best model score first (0: 2) */
     int64_t sample_rows;    /* 0: 65536 */
-    int64_t reserved2;      /* candidates are timed with the default LDS budget
-                               (half of a CU), the one fp_plan_create uses */
+    fp_autotune_trial *trials; /* nullable: the candidate table */
+    int32_t max_trials;     /* entries trials can hold */
+    int32_t reserved;
 } fp_autotune_opts;
 
 typedef struct fp_autotune_result {
-    fp_pack_opts pack;      /* best layout (PACKED, COMPACT or BLOCKED), bin size, interleave depth */
+    fp_pack_opts pack;      /* best layout, bin size, interleave depth */
     fp_tune tune;           /* best launch parameters */
     double best_ms;         /* time of one launch over the sample, best candidate */
-    double default_ms;      /* same, library defaults (B = T, D = 4) */
-    int32_t n_tried;        /* candidates timed */
-    int32_t cache_hit;      /* 1: answered from the cache, nothing timed */
+    double default_ms;      /* same, library defaults (PACKED, B = T, D = 4) */
+    int32_t n_tried;        /* launches timed (packings and launch mappings) */
+    int32_t cache_hit;      /* 1: answered from the table or file, nothing timed */
+    int32_t n_candidates;   /* packings scored by the model */
+    int32_t n_trials;       /* entries written to opts->trials */
 } fp_autotune_result;
 
 int fp_autotune(const fp_forest_view *forest, const float *X_dev, int64_t n_rows, int64_t ld,
@@ -396,20 +471,30 @@ typedef struct fp_plan_opts {
     int32_t use_graph;      /* 1 (default when opts is NULL): capture a hipGraph; 0: plain launches */
     int32_t items_per_block;/* work items per persistent workgroup to aim for (0: 4) */
     int64_t lds_budget;     /* LDS bytes per workgroup (0: half of a CU's LDS) */
+    int32_t autotune;       /* 1 (default when opts is NULL): each job with rows
+                               uses the tune recorded for (its forest, its size
+                               bucket, block_threads, cursors) and, if there is
+                               none, runs fp_tune_launch on its own rows first;
+                               0: each job uses its forest's own tune */
+    int32_t reserved;
 } fp_plan_opts;
 
 typedef struct fp_plan fp_plan;
 
 typedef struct fp_plan_info {
     int32_t n_jobs, n_items, blocks, block_threads;
-    int32_t cursors, graph, lds_bytes, reserved;
+    int32_t cursors, graph, lds_bytes, jobs_tuned; /* jobs timed by fp_tune_launch at creation */
     double total_cost;      /* sum of estimated node visits */
+    int32_t jobs_cached;    /* jobs whose tune came from the tune table or file */
+    int32_t reserved;
 } fp_plan_info;
 
-/* Build the work list and (optionally) the graph.  The library allocates the
- * plan's device tables (released by fp_plan_free).  Errors: FP_EINVAL (bad
- * job), FP_ENODEV (forest not uploaded / other device), FP_E2BIG (LDS),
- * FP_ENOMEM, FP_EHIP. */
+/* Build the work list and (optionally) the graph (opts NULL: defaults,
+ * autotune on).  With autotune the library times launch candidates of jobs
+ * that have no recorded tune, on their own rows (synchronising the device).
+ * The library allocates the plan's device tables (released by fp_plan_free).
+ * Errors: FP_EINVAL (bad job), FP_ENODEV (forest not uploaded / other
+ * device), FP_E2BIG (LDS), FP_ENOMEM, FP_EHIP. */
 int fp_plan_create(const fp_job *jobs, int32_t n_jobs, const fp_plan_opts *opts, fp_plan **out);
 
 /* Run every job of the plan on `stream` (graph replay or plain launches). */
@@ -440,6 +525,19 @@ void fp_plan_free(fp_plan *plan);
  * valid until fp_serve_poll returns FP_OK for the ticket (or the server is
  * destroyed).  fp_serve_submit / fp_serve_poll may be called from any thread.
  */
+enum {
+    FP_EXECUTOR_HIP = 0,  /* launches on the current HIP device (the product path) */
+    /* A CPU stand-in for the device, for testing the scheduler (admission,
+     * coalescing, retries, time-outs) on hosts without a GPU: the "device"
+     * rings are host memory, a launch completes fake_delay_us after it is
+     * issued, and its "votes" are not a classification but a checksum of
+     * each row: votes[i][c] = (h ^ (c * 0x9E3779B9)) & 0x7FFFFFFF with h the
+     * 32-bit FNV-1a hash (offset 2166136261, prime 16777619) of row i's
+     * n_features fp32 values as little-endian bytes.  Forests need not be
+     * uploaded; fake_fail_every = k > 0 makes every k-th launch fail. */
+    FP_EXECUTOR_CPU_FAKE = 1
+};
+
 typedef struct fp_server_opts {
     int64_t hbm_budget_bytes;    /* device staging for in-flight rows + votes (0: 1 GiB) */
     int64_t max_rows_per_launch; /* coalescing cap per launch (0: 262144) */
@@ -447,6 +545,12 @@ typedef struct fp_server_opts {
     int32_t max_queue;           /* pending requests before FP_EAGAIN (0: 1 << 20) */
     int32_t block_threads;       /* workgroup size of the launches (0: 1024) */
     int32_t cursors;             /* cursors per lane (0: 2) */
+    int32_t max_retries;         /* a request whose launch failed is queued again at
+                                    the head this many times before it fails (0: 2;
+                                    -1: never retried) */
+    int32_t executor;            /* FP_EXECUTOR_HIP (0) or FP_EXECUTOR_CPU_FAKE */
+    int32_t fake_delay_us;       /* CPU fake: microseconds from issue to completion */
+    int32_t fake_fail_every;     /* CPU fake: every k-th launch fails (0: none) */
 } fp_server_opts;
 
 typedef struct fp_serve_stats {
@@ -455,17 +559,24 @@ typedef struct fp_serve_stats {
     double mean_ms, p50_ms, p99_ms, max_ms; /* submit -> result ready, completed requests */
     double mean_rows_per_launch;
     double elapsed_s;                       /* since creation or the last reset */
+    int64_t failed_launches;                /* launches whose issue or completion failed */
+    int64_t retried;                        /* requests queued again after a failed launch */
+    int64_t failed;                         /* requests that failed after their retries */
 } fp_serve_stats;
 
 typedef struct fp_server fp_server;
 
 /* Allocates the HBM staging arena, its pinned host mirror, streams and the
- * scheduler thread.  Errors: FP_EINVAL, FP_ENOMEM, FP_EHIP. */
+ * scheduler thread (the CPU fake executor: host rings and the thread only).
+ * Errors: FP_EINVAL, FP_ENOMEM, FP_EHIP. */
 int fp_server_create(const fp_server_opts *opts, fp_server **out);
 
-/* Register an uploaded packed forest (layout PACKED) on the server's device;
- * *forest_id receives its id.  Its fp_tune (rows_per_block, tree_groups,
- * lds_top_nodes, feature_lds) is used for its requests. */
+/* Register a packed forest (any packed layout, not NAIVE), uploaded on the
+ * server's device (the CPU fake executor needs no upload); *forest_id
+ * receives its id.  Its fp_tune (rows_per_block, tree_groups, tree_passes,
+ * lds_top_nodes, feature_lds, refill_lanes) is used for its requests; its
+ * tables must fit the server's LDS budget.  Errors: FP_EINVAL (NULL, naive
+ * layout), FP_ENODEV (not uploaded, other device), FP_E2BIG (LDS). */
 int fp_server_add_forest(fp_server *s, const fp_packed *forest, int32_t *forest_id);
 
 /* Queue a request: rows X_host [n_rows][ld] (host fp32, copied before return).
@@ -476,7 +587,8 @@ int fp_serve_submit(fp_server *s, int32_t forest_id, const float *X_host, int64_
 
 /* Wait up to timeout_us (0: just test, < 0: forever) for a ticket.  FP_OK:
  * votes written, ticket retired.  FP_ENOTREADY: not yet.  FP_EINVAL: unknown
- * ticket.  FP_EHIP: the request's launch failed. */
+ * ticket.  FP_EHIP: the request's launches failed max_retries + 1 times (the
+ * ticket is retired). */
 int fp_serve_poll(fp_server *s, uint64_t ticket, int64_t timeout_us);
 
 int fp_server_stats(fp_server *s, fp_serve_stats *out);

@@ -61,20 +61,26 @@ class fp_packed_info(ctypes.Structure):
 class fp_tune(ctypes.Structure):
     _fields_ = [("rows_per_block", _i32), ("cursors", _i32), ("tree_groups", _i32),
                 ("block_threads", _i32), ("lds_top_nodes", _i32), ("feature_lds", _i32),
-                ("refill_lanes", _i32), ("lds_bytes", _i32)]
+                ("refill_lanes", _i32), ("lds_bytes", _i32), ("tree_passes", _i32), ("reserved", _i32)]
 
 
 TUNE_FIELDS = [f for f, _ in fp_tune._fields_ if f != "reserved"]
 
 
+class fp_autotune_trial(ctypes.Structure):
+    _fields_ = [("pack", fp_pack_opts), ("model_cost", ctypes.c_double), ("ms", ctypes.c_double)]
+
+
 class fp_autotune_opts(ctypes.Structure):
-    _fields_ = [("block_threads", _i32), ("cursors", _i32), ("reps", _i32), ("reserved", _i32),
-                ("sample_rows", _i64), ("reserved2", _i64)]
+    _fields_ = [("block_threads", _i32), ("cursors", _i32), ("reps", _i32), ("top_k", _i32),
+                ("sample_rows", _i64), ("trials", ctypes.POINTER(fp_autotune_trial)), ("max_trials", _i32),
+                ("reserved", _i32)]
 
 
 class fp_autotune_result(ctypes.Structure):
     _fields_ = [("pack", fp_pack_opts), ("tune", fp_tune), ("best_ms", ctypes.c_double),
-                ("default_ms", ctypes.c_double), ("n_tried", _i32), ("cache_hit", _i32)]
+                ("default_ms", ctypes.c_double), ("n_tried", _i32), ("cache_hit", _i32),
+                ("n_candidates", _i32), ("n_trials", _i32)]
 
 
 class fp_job(ctypes.Structure):
@@ -83,25 +89,30 @@ class fp_job(ctypes.Structure):
 
 class fp_plan_opts(ctypes.Structure):
     _fields_ = [("block_threads", _i32), ("cursors", _i32), ("use_graph", _i32), ("items_per_block", _i32),
-                ("lds_budget", _i64)]
+                ("lds_budget", _i64), ("autotune", _i32), ("reserved", _i32)]
+
+
+FP_EXECUTOR_HIP, FP_EXECUTOR_CPU_FAKE = 0, 1
 
 
 class fp_server_opts(ctypes.Structure):
     _fields_ = [("hbm_budget_bytes", _i64), ("max_rows_per_launch", _i64), ("max_inflight", _i32),
-                ("max_queue", _i32), ("block_threads", _i32), ("cursors", _i32)]
+                ("max_queue", _i32), ("block_threads", _i32), ("cursors", _i32), ("max_retries", _i32),
+                ("executor", _i32), ("fake_delay_us", _i32), ("fake_fail_every", _i32)]
 
 
 class fp_serve_stats(ctypes.Structure):
     _fields_ = [("submitted", _i64), ("completed", _i64), ("rejected", _i64), ("launches", _i64), ("rows", _i64),
                 ("pending", _i64), ("inflight", _i64), ("mean_ms", ctypes.c_double), ("p50_ms", ctypes.c_double),
                 ("p99_ms", ctypes.c_double), ("max_ms", ctypes.c_double),
-                ("mean_rows_per_launch", ctypes.c_double), ("elapsed_s", ctypes.c_double)]
+                ("mean_rows_per_launch", ctypes.c_double), ("elapsed_s", ctypes.c_double),
+                ("failed_launches", _i64), ("retried", _i64), ("failed", _i64)]
 
 
 class fp_plan_info(ctypes.Structure):
     _fields_ = [("n_jobs", _i32), ("n_items", _i32), ("blocks", _i32), ("block_threads", _i32),
-                ("cursors", _i32), ("graph", _i32), ("lds_bytes", _i32), ("reserved", _i32),
-                ("total_cost", ctypes.c_double)]
+                ("cursors", _i32), ("graph", _i32), ("lds_bytes", _i32), ("jobs_tuned", _i32),
+                ("total_cost", ctypes.c_double), ("jobs_cached", _i32), ("reserved", _i32)]
 
 _lib = None
 
@@ -132,6 +143,8 @@ def lib():
             "fp_packed_get_tune": ([_vp, ctypes.POINTER(fp_tune)], ctypes.c_int),
             "fp_predict": ([_vp, _vp, _i64, _i64, _vp, _vp, _vp], ctypes.c_int),
             "fp_predict_tuned": ([_vp, ctypes.POINTER(fp_tune), _vp, _i64, _i64, _vp, _vp, _vp], ctypes.c_int),
+            "fp_tune_launch": ([_vp, _vp, _i64, _i64, _i32, _i32, ctypes.POINTER(fp_tune), _vp], ctypes.c_int),
+            "fp_predict_tune_get": ([_vp, _i64, ctypes.POINTER(fp_tune), ctypes.POINTER(_i32)], ctypes.c_int),
             "fp_autotune": ([ctypes.POINTER(fp_forest_view), _vp, _i64, _i64, ctypes.POINTER(fp_autotune_opts),
                              ctypes.POINTER(fp_autotune_result), _vp], ctypes.c_int),
             "fp_plan_create": ([ctypes.POINTER(fp_job), _i32, ctypes.POINTER(fp_plan_opts), ctypes.POINTER(_vp)],
@@ -354,6 +367,25 @@ def fp_predict_tuned(p: Packed, tune, X, votes=None, cls=None, stream=None, want
     return votes, cls
 
 
+def fp_tune_launch(p: Packed, X, block_threads: int = 0, cursors: int = 0, stream=None) -> dict:
+    """Time launch candidates of p on rows X (CUDA fp32) and record the fastest
+    for X's size bucket (process table, and the FP_TUNE_CACHE file if set)."""
+    info = fp_packed_info_get(p)
+    n, ld = _check_rows(X, info["n_features"])
+    t = fp_tune()
+    _check(lib().fp_tune_launch(p.handle, _vp(X.data_ptr()), n, ld, block_threads, cursors, ctypes.byref(t),
+                                _stream_ptr(stream)), "fp_tune_launch")
+    return {k: getattr(t, k) for k in TUNE_FIELDS}
+
+
+def fp_predict_tune_get(p: Packed, n_rows: int):
+    """(tune dict, source) fp_predict would use for n_rows rows: source 2 a
+    recorded tune, 1 the forest's own, 0 library defaults."""
+    t, src = fp_tune(), _i32()
+    _check(lib().fp_predict_tune_get(p.handle, n_rows, ctypes.byref(t), ctypes.byref(src)), "fp_predict_tune_get")
+    return {k: getattr(t, k) for k in TUNE_FIELDS}, src.value
+
+
 def fp_infer_cardinality(forest, X, stream=None):
     """Per-node counts of the rows of X (CUDA fp32 [n, >= F]) that reach each
     node, int64 [tree_node_offset[T]]: a forest's access statistics inferred
@@ -388,21 +420,27 @@ def fp_probe_gather(buf, fetch_bytes: int = 16, chains: int = 1, steps: int = 25
 # autotuning
 # ---------------------------------------------------------------------------
 def fp_autotune(forest, X, block_threads: int = 0, cursors: int = 0, reps: int = 3, sample_rows: int = 0,
-                stream=None) -> dict:
-    """Time candidate (bin size, interleave depth) packings and launch mappings on
-    rows X (CUDA fp32); returns {"pack": {...}, "tune": {...}, "best_ms", "default_ms", ...}."""
+                top_k: int = 0, stream=None) -> dict:
+    """Score candidate packings with the cost model, time the best few per
+    layout and search the launch mapping of the fastest, on rows X (CUDA
+    fp32); returns {"pack": {...}, "tune": {...}, "best_ms", "default_ms",
+    "n_tried", "cache_hit", "trials": [{"pack", "model_cost", "ms"}, ...]}."""
     view, keep = _view_from(forest)
     n, ld = _check_rows(X, int(forest.n_features))
-    opts = fp_autotune_opts(block_threads, cursors, reps, 0, sample_rows, 0)
+    cap = 256
+    trials = (fp_autotune_trial * cap)()
+    opts = fp_autotune_opts(block_threads, cursors, reps, top_k, sample_rows, trials, cap, 0)
     res = fp_autotune_result()
     _check(lib().fp_autotune(ctypes.byref(view), _vp(X.data_ptr()), n, ld, ctypes.byref(opts), ctypes.byref(res),
                              _stream_ptr(stream)), "fp_autotune")
     del keep
-    return {"pack": {"layout": res.pack.layout, "bin_size": res.pack.bin_size,
-                     "interleave_depth": res.pack.interleave_depth, "line_align": res.pack.line_align},
-            "tune": {k: getattr(res.tune, k) for k in TUNE_FIELDS},
+    pk = lambda p: {"layout": p.layout, "bin_size": p.bin_size, "interleave_depth": p.interleave_depth,
+                    "line_align": p.line_align}
+    return {"pack": pk(res.pack), "tune": {k: getattr(res.tune, k) for k in TUNE_FIELDS},
             "best_ms": res.best_ms, "default_ms": res.default_ms, "n_tried": res.n_tried,
-            "cache_hit": bool(res.cache_hit)}
+            "cache_hit": bool(res.cache_hit), "n_candidates": res.n_candidates,
+            "trials": [{"pack": pk(trials[i].pack), "model_cost": trials[i].model_cost, "ms": trials[i].ms}
+                       for i in range(res.n_trials)]}
 
 
 # ---------------------------------------------------------------------------
@@ -423,8 +461,10 @@ class Plan:
 
 
 def fp_plan_create(jobs, block_threads: int = 0, cursors: int = 0, use_graph: bool = True,
-                   items_per_block: int = 0, lds_budget: int = 0) -> Plan:
-    """jobs: list of (Packed, X, votes, cls-or-None) with CUDA tensors; pointers are fixed in the plan."""
+                   items_per_block: int = 0, lds_budget: int = 0, autotune: bool = False,
+                   default_opts: bool = False) -> Plan:
+    """jobs: list of (Packed, X, votes, cls-or-None) with CUDA tensors; pointers are fixed in the plan.
+    default_opts passes NULL options (library defaults, autotune on)."""
     arr = (fp_job * len(jobs))()
     keep = []
     for i, (p, X, votes, cls) in enumerate(jobs):
@@ -432,9 +472,11 @@ def fp_plan_create(jobs, block_threads: int = 0, cursors: int = 0, use_graph: bo
         arr[i] = fp_job(p.handle.value, X.data_ptr(), n, ld, votes.data_ptr(),
                         cls.data_ptr() if cls is not None else None)
         keep.append((p, X, votes, cls))
-    opts = fp_plan_opts(block_threads, cursors, int(bool(use_graph)), items_per_block, lds_budget)
+    opts = fp_plan_opts(block_threads, cursors, int(bool(use_graph)), items_per_block, lds_budget,
+                        int(bool(autotune)), 0)
     out = _vp()
-    _check(lib().fp_plan_create(arr, len(jobs), ctypes.byref(opts), ctypes.byref(out)), "fp_plan_create")
+    _check(lib().fp_plan_create(arr, len(jobs), None if default_opts else ctypes.byref(opts), ctypes.byref(out)),
+           "fp_plan_create")
     return Plan(out.value, keep)
 
 
@@ -474,8 +516,10 @@ class Server:
 
 
 def fp_server_create(hbm_budget_bytes: int = 0, max_rows_per_launch: int = 0, max_inflight: int = 0,
-                     max_queue: int = 0, block_threads: int = 0, cursors: int = 0) -> Server:
-    opts = fp_server_opts(hbm_budget_bytes, max_rows_per_launch, max_inflight, max_queue, block_threads, cursors)
+                     max_queue: int = 0, block_threads: int = 0, cursors: int = 0, max_retries: int = 0,
+                     executor: int = FP_EXECUTOR_HIP, fake_delay_us: int = 0, fake_fail_every: int = 0) -> Server:
+    opts = fp_server_opts(hbm_budget_bytes, max_rows_per_launch, max_inflight, max_queue, block_threads, cursors,
+                          max_retries, executor, fake_delay_us, fake_fail_every)
     out = _vp()
     _check(lib().fp_server_create(ctypes.byref(opts), ctypes.byref(out)), "fp_server_create")
     return Server(out.value)

@@ -1,25 +1,23 @@
 // Autotuner: the design experiment of Sec. III-A (Fig. 2 sweeps stripe width
-// and interleave depth) run on the GPU, extended to the launch mapping.
+// and interleave depth) run on the GPU, with the paper's cost model (Eqs.
+// 1-2 and the expected uses EU of a fetched line, Sec. III-A) as its prior.
 //
-// Coordinate descent, three passes, every candidate timed with HIP events on
-// a sample of the caller's rows:
-//   1. launch mapping (workgroup size, cursors, observations per workgroup)
-//      on the default packing (one bin of all trees, interleave depth 4);
-//   2. packing: layout (16-byte nodes or compact 8-byte deep nodes), interleave
-//      depth 0..7 and bin sizes T, 64, 16 with that mapping;
-//   3. launch mapping again on the best packing, plus tree groups (several
-//      workgroups per observation tile, one per group of bins).
-// Votes never depend on the candidate; only time does.
+//   1. every candidate packing -- layout (PACKED, COMPACT, BLOCKED,
+//      CLUSTERED), bin size B and interleave depth D -- is packed on the
+//      host and scored with Eq. 2's estimate from its header statistics;
+//   2. per layout, only the top_k packings by score are timed (HIP events
+//      on a sample of the caller's rows), with one launch shape per layout
+//      kind;
+//   3. the launch mapping of the fastest packing is searched as
+//      fp_tune_launch does (tune.cpp).
+// Votes never depend on the candidate; only time does.  Results are kept
+// in the process-wide tune table and the FP_TUNE_CACHE file (tune.cpp).
 #include <hip/hip_runtime_api.h>
 
 #include <algorithm>
 #include <cstring>
-#include <map>
 #include <memory>
-#include <mutex>
 #include <new>
-#include <set>
-#include <tuple>
 #include <vector>
 
 #include "fp_internal.h"
@@ -28,16 +26,13 @@ namespace {
 
 using fp::DevBuf;
 
-std::mutex g_cache_mu;
-std::map<uint64_t, fp_autotune_result> g_cache;
-
 uint64_t mix(uint64_t h, const void* p, size_t n) {
     const uint8_t* b = static_cast<const uint8_t*>(p);
     for (size_t i = 0; i < n; i++) h = (h ^ b[i]) * 0x100000001b3ull;
     return h;
 }
 
-uint64_t fingerprint(const fp_forest_view* v, int64_t sample, int threads, int K, int reps) {
+uint64_t fingerprint(const fp_forest_view* v, int64_t sample, int threads, int K, int reps, int top_k) {
     uint64_t h = 0xcbf29ce484222325ull;
     int32_t dims[3] = {v->n_trees, v->n_features, v->n_classes};
     h = mix(h, dims, sizeof dims);
@@ -48,13 +43,40 @@ uint64_t fingerprint(const fp_forest_view* v, int64_t sample, int threads, int K
     h = mix(h, v->left, 4 * (size_t)n);
     h = mix(h, v->right, 4 * (size_t)n);
     h = mix(h, v->leaf_class, 4 * (size_t)n);
-    int64_t cfg[4] = {sample, threads, K, reps};
+    if (v->cardinality) h = mix(h, v->cardinality, 8 * (size_t)n);
+    int64_t cfg[6] = {sample, threads, K, reps, top_k, 2 /* autotuner revision */};
     return mix(h, cfg, sizeof cfg);
 }
 
 struct PackedPtr {
     fp_packed* p = nullptr;
     ~PackedPtr() { fp_packed_free(p); }
+};
+
+bool block_layout(int L) { return L == FP_LAYOUT_BLOCKED || L == FP_LAYOUT_CLUSTERED; }
+
+// Eq. 2 with the EU of Sec. III-A, per row: T x (fetches - well-used) / EU.
+// Node layouts fetch nodes; the interleaved depths 0..D are the well-used
+// ones and EU = 1 + b(1 + b(1 + b)) for the forest's mean split bias b.  A
+// block layout fetches blocks (EU 1: one fetch serves the block's nodes);
+// its interleaved block levels 0..D/3 are the well-used ones.
+double model_cost(const fp::Header& h, int L, int D) {
+    const double f = h.expected_fetches, b = h.mean_bias;
+    double wun, eu;
+    if (block_layout(L)) {
+        wun = std::min((double)(D / 3 + 1), f);
+        eu = 1.0;
+    } else {
+        wun = std::min((double)(D + 1), h.expected_depth);
+        eu = 1.0 + b * (1.0 + b * (1.0 + b));
+    }
+    return (double)h.n_trees * std::max(0.0, f - wun) / eu;
+}
+
+struct Cand {
+    fp_pack_opts pack;
+    double cost;
+    double ms;
 };
 
 }  // namespace
@@ -66,22 +88,21 @@ extern "C" int fp_autotune(const fp_forest_view* forest, const float* X, int64_t
     if (!X || n_rows < 1) return fp_set_error(FP_EINVAL, "autotuning needs at least one device row");
     if (ld < forest->n_features) return fp_set_error(FP_EINVAL, "ld %lld < n_features %d", (long long)ld, forest->n_features);
     if (!forest->tree_node_offset || forest->n_trees < 1) return fp_set_error(FP_EINVAL, "empty forest view");
+    if (opts && (opts->max_trials < 0 || (opts->max_trials > 0 && !opts->trials)))
+        return fp_set_error(FP_EINVAL, "trials is NULL with max_trials %d", opts->max_trials);
     memset(out, 0, sizeof *out);
     const int fixed_threads = opts ? opts->block_threads : 0;
     const int fixed_K = opts ? opts->cursors : 0;
     const int reps = opts && opts->reps > 0 ? opts->reps : 3;
+    const int top_k = opts && opts->top_k > 0 ? opts->top_k : 2;
     const int64_t sample = std::min<int64_t>(n_rows, opts && opts->sample_rows > 0 ? opts->sample_rows : 65536);
     hipStream_t stream = static_cast<hipStream_t>(stream_v);
 
-    const uint64_t key = fingerprint(forest, sample, fixed_threads, fixed_K, reps);
-    {
-        std::lock_guard<std::mutex> lk(g_cache_mu);
-        auto it = g_cache.find(key);
-        if (it != g_cache.end()) {
-            *out = it->second;
-            out->cache_hit = 1;
-            return FP_OK;
-        }
+    const uint64_t key = fingerprint(forest, sample, fixed_threads, fixed_K, reps, top_k);
+    if (fp::autotune_cache_get(key, out)) {
+        out->cache_hit = 1;
+        out->n_trials = 0;
+        return FP_OK;
     }
 
     try {
@@ -101,25 +122,17 @@ extern "C" int fp_autotune(const fp_forest_view* forest, const float* X, int64_t
             }
         } evg{e0, e1};
 
-        // pack + upload with memoisation over (bin size, depth)
-        std::map<std::tuple<int, int, int>, std::unique_ptr<PackedPtr>> packs;
-        PackedPtr* current = nullptr;
-        auto use_pack = [&](int layout, int B, int D) -> int {
-            auto k = std::make_tuple(layout, B, D);
-            if (!packs.count(k)) {
-                std::unique_ptr<PackedPtr> pp(new PackedPtr());
-                fp_pack_opts po{layout, B, D, 0, FP_ORDER_DEFAULT};
-                int r = fp_pack_forest(forest, &po, &pp->p);
-                if (r) return r;
-                packs[k] = std::move(pp);
-            }
-            current = packs[k].get();
-            const size_t bytes = current->p->bytes.size();
-            int r = packed_buf.ensure(bytes);
+        std::unique_ptr<PackedPtr> current;
+        // pack (and with upload, copy to the device buffer); FP_E2BIG when the
+        // layout's encoding cannot hold this forest
+        auto pack = [&](const fp_pack_opts& po, bool upload) -> int {
+            current.reset(new PackedPtr());
+            int r = fp_pack_forest(forest, &po, &current->p);
+            if (r || !upload) return r;
+            r = packed_buf.ensure(current->p->bytes.size());
             if (r) return r;
             return fp_packed_upload(current->p, packed_buf.p, packed_buf.cap, stream);
         };
-        int max_depth = 0;
         auto time_one = [&](const fp_tune& t, double* ms) -> int {
             int r = fp_predict_tuned(current->p, &t, X, sample, ld, static_cast<int32_t*>(votes.p), nullptr, stream);
             if (r) return r;
@@ -138,92 +151,84 @@ extern "C" int fp_autotune(const fp_forest_view* forest, const float* X, int64_t
         };
 
         const int T = forest->n_trees;
-        rc = use_pack(FP_LAYOUT_PACKED, T, 4);
+        // reference: library defaults (one bin of all trees, interleave depth 4)
+        rc = pack(fp_pack_opts{FP_LAYOUT_PACKED, T, 4, 0, FP_ORDER_DEFAULT}, true);
         if (rc) return rc;
-        max_depth = current->p->hdr.max_depth;
-        // library defaults, for reference
-        fp_tune def{};
-        rc = time_one(def, &out->default_ms);
+        const int max_depth = current->p->hdr.max_depth;
+        rc = time_one(fp_tune{}, &out->default_ms);
         if (rc) return rc;
 
-        std::vector<int> thr_set = fixed_threads > 0 ? std::vector<int>{fixed_threads} : std::vector<int>{256, 512, 1024};
-        std::vector<int> k_set = fixed_K > 0 ? std::vector<int>{fixed_K} : std::vector<int>{2, 4};
-        double best = 1e30;
-        fp_tune best_t{};
-        int best_B = T, best_D = 4, best_L = FP_LAYOUT_PACKED;
-        auto try_tune = [&](const fp_tune& t) -> int {
-            double ms = 0;
-            int r = time_one(t, &ms);
-            if (r == FP_E2BIG) return FP_OK;  // does not fit: skip the candidate
-            if (r) return r;
-            if (ms < best) {
-                best = ms;
-                best_t = t;
-            }
-            return FP_OK;
-        };
-        // pass 1: launch mapping on the default packing
-        for (int th : thr_set)
-            for (int K : k_set)
-                for (int R : {16, 32, 64}) {
-                    fp_tune t{};
-                    t.rows_per_block = R;
-                    t.cursors = K;
-                    t.block_threads = th;
-                    t.tree_groups = 1;
-                    rc = try_tune(t);
-                    if (rc) return rc;
-                }
-        // pass 2: packing (layout, bin size, interleave depth)
-        std::set<std::tuple<int, int, int>> tried{{FP_LAYOUT_PACKED, T, 4}};
+        // 1. every candidate packing, scored by the model
+        std::vector<Cand> cands;
+        std::vector<int> bins{T};
+        for (int B : {64, 16})
+            if (B < T) bins.push_back(B);
         for (int L : {FP_LAYOUT_PACKED, FP_LAYOUT_COMPACT, FP_LAYOUT_BLOCKED, FP_LAYOUT_CLUSTERED})
-            for (int B : {T, 64, 16}) {
-                if (B > T) continue;
+            for (int B : bins)
                 for (int D = 0; D <= std::min(7, max_depth); D++) {
-                    // BLOCKED interleaves whole blocks (three levels): only D / 3 matters
-                    if (L >= FP_LAYOUT_BLOCKED && D % 3) continue;
-                    if (!tried.insert(std::make_tuple(L, B, D)).second) continue;
-                    rc = use_pack(L, B, D);
-                    if (rc == FP_E2BIG) continue;  // the compact encoding does not fit this forest
+                    if (block_layout(L) && D % 3) continue;  // whole three-level blocks are interleaved
+                    const fp_pack_opts po{L, B, D, 0, FP_ORDER_DEFAULT};
+                    rc = pack(po, false);
+                    if (rc == FP_E2BIG) break;  // this layout's encoding does not fit the forest
                     if (rc) return rc;
-                    const double before = best;
-                    rc = try_tune(best_t);
-                    if (rc) return rc;
-                    if (best < before) {
-                        best_L = L;
-                        best_B = B;
-                        best_D = D;
-                    }
+                    cands.push_back(Cand{po, model_cost(current->p->hdr, L, D), -1.0});
+                }
+        out->n_candidates = (int32_t)cands.size();
+
+        // 2. per layout, the top_k packings by model score, timed with one
+        // launch shape per layout kind
+        const int th = fixed_threads > 0 ? fixed_threads : 1024;
+        double best = 1e30;
+        size_t best_c = 0;
+        for (int L : {FP_LAYOUT_PACKED, FP_LAYOUT_COMPACT, FP_LAYOUT_BLOCKED, FP_LAYOUT_CLUSTERED}) {
+            std::vector<size_t> idx;
+            for (size_t i = 0; i < cands.size(); i++)
+                if (cands[i].pack.layout == L) idx.push_back(i);
+            std::stable_sort(idx.begin(), idx.end(), [&](size_t a, size_t b) { return cands[a].cost < cands[b].cost; });
+            if ((int)idx.size() > top_k) idx.resize(top_k);
+            for (size_t i : idx) {
+                rc = pack(cands[i].pack, true);
+                if (rc) return rc;
+                fp_tune t{};
+                t.rows_per_block = 32;
+                t.block_threads = th;
+                t.cursors = block_layout(L) ? 1 : (fixed_K > 0 ? fixed_K : 2);
+                t.refill_lanes = block_layout(L) ? 32 : 16;
+                double ms = 0.0;
+                rc = time_one(t, &ms);
+                if (rc == FP_E2BIG) continue;
+                if (rc) return rc;
+                cands[i].ms = ms;
+                if (ms < best) {
+                    best = ms;
+                    best_c = i;
                 }
             }
-        // pass 3: launch mapping again on the best packing, with tree groups
-        rc = use_pack(best_L, best_B, best_D);
-        if (rc) return rc;
-        const fp_tune base = best_t;
-        const int n_bins = current->p->hdr.n_bins;
-        for (int R : {8, 16, 32, 64, 128})
-            for (int G : {1, 2, 4, 8}) {
-                if (G > n_bins || (R == base.rows_per_block && G == 1)) continue;
-                fp_tune t = base;
-                t.rows_per_block = R;
-                t.tree_groups = G;
-                rc = try_tune(t);
-                if (rc) return rc;
-            }
-        // pass 4: how many idle lanes a wavefront waits for before refilling
-        const fp_tune mapped = best_t;
-        for (int rl : {4, 8, 32, 48}) {
-            fp_tune t = mapped;
-            t.refill_lanes = rl;
-            rc = try_tune(t);
-            if (rc) return rc;
         }
-        out->pack = fp_pack_opts{best_L, best_B, best_D, 0, FP_ORDER_DEFAULT};
-        out->tune = best_t;
-        out->best_ms = best;
+        if (best >= 1e30) return fp_set_error(FP_E2BIG, "no candidate packing fits the workgroup's LDS");
+
+        // 3. the launch mapping of the fastest packing
+        rc = pack(cands[best_c].pack, true);
+        if (rc) return rc;
+        fp_tune tuned{};
+        double tuned_ms = 0.0;
+        int32_t tried = 0;
+        rc = fp::search_launch(current->p, X, sample, ld, fixed_threads, fixed_K, stream, &tuned, &tuned_ms, &tried);
+        if (rc) return rc;
+        out->n_tried += tried;
+        out->pack = cands[best_c].pack;
+        out->tune = tuned;
+        out->best_ms = std::min(best, tuned_ms);
+        if (opts && opts->trials) {
+            const int32_t n = std::min<int32_t>(opts->max_trials, (int32_t)cands.size());
+            for (int32_t i = 0; i < n; i++)
+                opts->trials[i] = fp_autotune_trial{cands[i].pack, cands[i].cost, cands[i].ms};
+            out->n_trials = n;
+        }
         if (hipStreamSynchronize(stream) != hipSuccess) return fp_set_error(FP_EHIP, "hipStreamSynchronize failed");
-        std::lock_guard<std::mutex> lk(g_cache_mu);
-        g_cache[key] = *out;
+        fp_autotune_result rec = *out;
+        rec.n_trials = 0;
+        fp::autotune_cache_put(key, rec);
         return FP_OK;
     } catch (const std::bad_alloc&) {
         return fp_set_error(FP_ENOMEM, "out of host memory");

@@ -14,7 +14,7 @@
 namespace fp {
 
 // ---------------------------------------------------------------------------
-// Packed buffer format (version 1).  Little-endian; every section starts on a
+// Packed buffer format (version kFormatVersion below).  Little-endian; every section starts on a
 // 256-byte boundary so that the device copy keeps 128-byte line alignment.
 //
 //   [Header 256 B]
@@ -219,7 +219,24 @@ struct JobDesc {
     int32_t stage_rows;        // 1: stage tiles with whole-row 16-byte loads through imap
     int32_t off_imap;          // LDS: column -> compacted feature (int16, -1 unused), 4 * ceil(F / 4) entries
     int32_t x16;               // 1: the LDS tile holds fp16 features rounded toward +inf (CLUSTERED 48-byte form)
+    int32_t passes;            // consecutive launches over the groups (tree_passes), 1 in batched launches
+    int32_t group_base;        // first group of this launch: workgroup b walks group group_base + b % G
+    int32_t accumulate;        // 1: add the tile's votes to the stored ones (a later pass)
+    int32_t pad_job;
 };
+
+// A job whose groups run in several passes, flattened for launches where all
+// groups run concurrently (batched plans, the server): every group of every
+// pass becomes a concurrent group, votes merged with atomics.
+inline void flatten_passes(JobDesc* j) {
+    if (j->passes > 1) {
+        j->G *= j->passes;
+        j->passes = 1;
+        j->atomic_votes = j->G > 1;
+    }
+    j->group_base = 0;
+    j->accumulate = 0;
+}
 
 // One entry of the batched work list: tiles [tile_begin, tile_end) of job
 // `job`, trees of tree group `group`.
@@ -250,6 +267,15 @@ size_t default_lds_block(const DeviceProps& dp);
 int packed_occupancy(int K, int fmode, int layout, int threads, size_t lds, int* blocks_per_cu);
 int batched_occupancy(int K, int threads, size_t lds, int* blocks_per_cu);
 
+// The packer's two device operations, kept out of the host-only packer:
+// copy n bytes to device memory on `stream` and wait for it (the current
+// device's id in *dev_id), and count on the GPU the rows of X that end in
+// each leaf of a NAIVE-layout buffer (`bytes`, header h), node by node of
+// that buffer into counts[h.n_nodes] (host), synchronising `stream`.
+int device_upload(void* dev, const void* src, size_t n, void* stream, int* dev_id);
+int device_leaf_counts(const uint8_t* bytes, size_t nbytes, const Header& h, int32_t n_trees, const float* X,
+                       int64_t n_rows, int64_t ld, int32_t* counts, void* stream);
+
 int launch_fill(int32_t* p, int64_t n, int32_t v, hipStream_t s);
 // counts[i] += observations whose walk ends at node i of a NAIVE layout
 int launch_leaf_counts(const Node16* nodes, const int64_t* tree_off, int32_t n_trees, const float* X, int64_t n_rows,
@@ -261,6 +287,20 @@ int launch_batched(const JobDesc* jobs, const WorkItem* items, int32_t n_items, 
 // Zero the work counter and the votes of every job that accumulates with atomics.
 int launch_batched_prologue(const JobDesc* jobs_dev, int32_t n_jobs, int32_t* counter, hipStream_t s);
 int launch_batched_epilogue(const JobDesc* jobs_dev, int32_t n_jobs, hipStream_t s);
+
+// Launch tunes per (packed forest, batch-size bucket) and the autotuner's
+// results, in a process-wide table mirrored to the FP_TUNE_CACHE file
+// (tune.cpp).  threads / cursors 0 key the single-forest tunes fp_predict
+// uses; a plan keys its fixed workgroup size and cursor count.
+int32_t rows_bucket(int64_t n_rows);
+uint64_t forest_key(const fp_packed* p);
+bool launch_tune_get(const fp_packed* p, int64_t n_rows, int32_t threads, int32_t cursors, fp_tune* out);
+void launch_tune_put(const fp_packed* p, int64_t n_rows, int32_t threads, int32_t cursors, const fp_tune& t);
+bool autotune_cache_get(uint64_t key, fp_autotune_result* out);
+void autotune_cache_put(uint64_t key, const fp_autotune_result& r);
+// Times launch candidates of p on the first rows of X; fastest in *best.
+int search_launch(const fp_packed* p, const float* X, int64_t n_rows, int64_t ld, int32_t threads, int32_t cursors,
+                  hipStream_t stream, fp_tune* best, double* best_ms, int32_t* tried);
 
 // Work list of a batched launch (plan.cpp): chunks of row tiles per (job,
 // tree group), about `items_per_block` items per resident workgroup, largest

@@ -19,8 +19,6 @@
 // Every internal node index in a bin is larger than its parent's: children
 // always come later (level-major top, pre-order deep region), which the
 // verifier checks, so every walk terminates.
-#include <hip/hip_runtime_api.h>
-
 #include <algorithm>
 #include <cstdarg>
 #include <cstdio>
@@ -914,21 +912,33 @@ int verify_buffer(const uint8_t* bytes, size_t n, std::string* why) {
     if (h.magic != kMagic) return bad("bad magic");
     if (h.version != kFormatVersion) return bad("format version %u, expected %u", h.version, kFormatVersion);
     if (h.total_bytes != (int64_t)n) return bad("size %zu != header size %lld", n, (long long)h.total_bytes);
-    if (h.n_trees < 1 || h.n_features < 1 || h.n_classes < 1 || h.n_classes > kMaxClasses)
+    // sizes bounded by the buffer first, so that no offset arithmetic below overflows
+    if (h.n_trees < 1 || h.n_trees > (int64_t)(n / 4) || h.n_features < 1 || h.n_classes < 1 ||
+        h.n_classes > kMaxClasses || h.n_bins < 0 || h.n_bins > h.n_trees || h.n_used_features < 0 ||
+        h.n_used_features > (int64_t)(n / 4))
         return bad("bad forest dimensions");
+    if (h.n_nodes < 0 || h.n_nodes > (int64_t)n || h.nodes_offset < 0 || h.nodes_offset > (int64_t)n ||
+        h.table_offset < 0 || h.table_offset > (int64_t)n || h.roots_offset < 0 || h.roots_offset > (int64_t)n ||
+        h.fmap_offset < 0 || h.fmap_offset > (int64_t)n)
+        return bad("section offsets or node count beyond the buffer");
     if (fnv1a64(bytes + sizeof(Header), n - sizeof(Header)) != h.checksum) return bad("checksum mismatch");
     const int64_t N = h.n_nodes;
     const int64_t unit = h.layout == FP_LAYOUT_COMPACT || h.layout == FP_LAYOUT_BLOCKED || h.layout == FP_LAYOUT_CLUSTERED
                              ? 8
                              : (int64_t)sizeof(Node16);
     if (N < 0 || h.nodes_offset < (int64_t)sizeof(Header) || h.nodes_offset % 256 ||
-        h.nodes_offset + N * unit > (int64_t)n)
+        N > ((int64_t)n - h.nodes_offset) / unit)
         return bad("node section out of bounds");
     const Node16* nodes = reinterpret_cast<const Node16*>(bytes + h.nodes_offset);
     const int32_t C = h.n_classes;
     int32_t F = h.n_features;
+    // every table starts on a section boundary after the header (the packer
+    // writes them so), which also keeps the typed reads below aligned
+    auto section_ok = [&](int64_t off) {
+        return off >= (int64_t)sizeof(Header) && off % (int64_t)kSectionAlign == 0 && off <= h.nodes_offset;
+    };
     if (h.layout == FP_LAYOUT_NAIVE) {
-        if (h.table_offset + (int64_t)sizeof(int64_t) * (h.n_trees + 1) > h.nodes_offset)
+        if (!section_ok(h.table_offset) || h.table_offset + (int64_t)sizeof(int64_t) * (h.n_trees + 1) > h.nodes_offset)
             return bad("tree table out of bounds");
         const int64_t* offs = reinterpret_cast<const int64_t*>(bytes + h.table_offset);
         if (offs[0] != 0 || offs[h.n_trees] != N) return bad("tree table endpoints");
@@ -955,6 +965,8 @@ int verify_buffer(const uint8_t* bytes, size_t n, std::string* why) {
     const bool compact = h.layout == FP_LAYOUT_COMPACT;
     const bool clustered = h.layout == FP_LAYOUT_CLUSTERED;
     const bool blocked = h.layout == FP_LAYOUT_BLOCKED || clustered;
+    if (h.compact_fbits < 0 || h.compact_fbits > 32 || h.compact_cbits < 0 || h.compact_cbits > 32)
+        return bad("field widths");
     if (compact && (h.nodes_offset + 8 * N + 16 > (int64_t)n || h.compact_fbits < 1 || h.compact_fbits > 26 ||
                     h.compact_cbits < 1 || 2 * h.compact_cbits > 29 - h.compact_fbits))
         return bad("compact node section or field widths");
@@ -968,6 +980,8 @@ int verify_buffer(const uint8_t* bytes, size_t n, std::string* why) {
                       h.compact_fbits > (h.block_bytes == 48 ? fp::kCluster48FeatBits : fp::kClusterFeatBits)))
         return bad("clustered node section or field widths");
     const int64_t block_words = h.block_bytes == 48 ? 6 : 8;
+    if (!section_ok(h.table_offset) || !section_ok(h.roots_offset) || !section_ok(h.fmap_offset))
+        return bad("bin/root/feature tables misplaced");
     if (h.n_bins < 1 || h.table_offset + (int64_t)sizeof(BinEntry) * h.n_bins > h.roots_offset ||
         h.roots_offset + (int64_t)sizeof(int32_t) * h.n_trees > h.fmap_offset ||
         h.n_used_features < 1 || h.n_used_features > h.n_features ||
@@ -1348,14 +1362,9 @@ extern "C" int fp_packed_upload(fp_packed* p, void* dev, size_t cap, void* strea
     if (cap < p->bytes.size())
         return fp_set_error(FP_E2BIG, "device buffer of %zu bytes < packed size %zu", cap, p->bytes.size());
     int dev_id = -1;
-    hipError_t e = hipGetDevice(&dev_id);
-    if (e != hipSuccess) return fp_set_error(FP_EHIP, "hipGetDevice: %s", hipGetErrorString(e));
-    e = hipMemcpyAsync(dev, p->bytes.data(), p->bytes.size(), hipMemcpyHostToDevice,
-                       static_cast<hipStream_t>(stream));
-    if (e != hipSuccess) return fp_set_error(FP_EHIP, "hipMemcpyAsync: %s", hipGetErrorString(e));
-    // the host vector must outlive the copy: wait for it
-    e = hipStreamSynchronize(static_cast<hipStream_t>(stream));
-    if (e != hipSuccess) return fp_set_error(FP_EHIP, "hipStreamSynchronize: %s", hipGetErrorString(e));
+    // waits for the copy: the host vector must outlive it
+    const int rc = fp::device_upload(dev, p->bytes.data(), p->bytes.size(), stream, &dev_id);
+    if (rc) return rc;
     p->dev = dev;
     p->dev_cap = cap;
     p->dev_id = dev_id;
@@ -1369,7 +1378,6 @@ extern "C" int fp_infer_cardinality(const fp_forest_view* forest, const float* X
     if (n_rows < 0 || n_rows > INT32_MAX) return fp_set_error(FP_EINVAL, "n_rows %lld outside [0, 2^31-1]", (long long)n_rows);
     if (n_rows > 0 && !X_dev) return fp_set_error(FP_EINVAL, "X is NULL");
     if (ld < forest->n_features) return fp_set_error(FP_EINVAL, "ld %lld < n_features %d", (long long)ld, forest->n_features);
-    hipStream_t stream = static_cast<hipStream_t>(stream_v);
     try {
         std::vector<fp::TreeShape> shapes;
         int rc = fp::validate_view(forest, &shapes);
@@ -1382,25 +1390,9 @@ extern "C" int fp_infer_cardinality(const fp_forest_view* forest, const float* X
         if (rc) return rc;
         std::vector<int32_t> counts((size_t)h.n_nodes, 0);
         if (n_rows > 0) {
-            fp::DevBuf buf, cnt;
-            if ((rc = buf.ensure(bytes.size())) || (rc = cnt.ensure(sizeof(int32_t) * counts.size()))) return rc;
-            // once work is queued, every exit waits for the stream before the
-            // buffers above (and the host vectors the copies use) go away
-            struct Drain {
-                hipStream_t s;
-                ~Drain() { (void)hipStreamSynchronize(s); }
-            } drain{stream};
-            hipError_t e = hipMemcpyAsync(buf.p, bytes.data(), bytes.size(), hipMemcpyHostToDevice, stream);
-            if (e == hipSuccess) e = hipMemsetAsync(cnt.p, 0, sizeof(int32_t) * counts.size(), stream);
-            if (e != hipSuccess) return fp_set_error(FP_EHIP, "upload: %s", hipGetErrorString(e));
-            const uint8_t* base = static_cast<const uint8_t*>(buf.p);
-            rc = fp::launch_leaf_counts(reinterpret_cast<const fp::Node16*>(base + h.nodes_offset),
-                                        reinterpret_cast<const int64_t*>(base + h.table_offset), forest->n_trees,
-                                        X_dev, n_rows, ld, static_cast<int32_t*>(cnt.p), stream);
+            rc = fp::device_leaf_counts(bytes.data(), bytes.size(), h, forest->n_trees, X_dev, n_rows, ld,
+                                        counts.data(), stream_v);
             if (rc) return rc;
-            e = hipMemcpyAsync(counts.data(), cnt.p, sizeof(int32_t) * counts.size(), hipMemcpyDeviceToHost, stream);
-            if (e == hipSuccess) e = hipStreamSynchronize(stream);
-            if (e != hipSuccess) return fp_set_error(FP_EHIP, "counts: %s", hipGetErrorString(e));
         }
         // leaf counts back to the caller's node ids, summed up to the roots
         const int64_t* offs = reinterpret_cast<const int64_t*>(bytes.data() + h.table_offset);

@@ -31,6 +31,7 @@ struct fp_plan {
     int K = 2, threads = 1024, blocks = 1;
     size_t lds_bytes = 0;
     double total_cost = 0.0;
+    int32_t jobs_tuned = 0, jobs_cached = 0;
     bool use_graph = true;
     hipStream_t capture_stream = nullptr;
     hipGraph_t graph = nullptr;
@@ -112,6 +113,7 @@ extern "C" int fp_plan_create(const fp_job* jobs, int32_t n_jobs, const fp_plan_
         p->threads = opts && opts->block_threads > 0 ? opts->block_threads : 1024;
         p->K = opts && opts->cursors > 0 ? opts->cursors : 2;
         p->use_graph = opts ? opts->use_graph != 0 : true;
+        const bool autotune = opts ? opts->autotune != 0 : true;
         const int items_per_block = opts && opts->items_per_block > 0 ? opts->items_per_block : 4;
         if (p->threads % 64 || p->threads < 64 || p->threads > 1024)
             return fp_set_error(FP_EINVAL, "block_threads %d must be a multiple of 64 in [64, 1024]", p->threads);
@@ -120,6 +122,9 @@ extern "C" int fp_plan_create(const fp_job* jobs, int32_t n_jobs, const fp_plan_
         const size_t blk_max = dp.lds_per_block ? dp.lds_per_block : 65536;
         const size_t lds_block =
             opts && opts->lds_budget > 0 ? std::min((size_t)opts->lds_budget, blk_max) : fp::default_lds_block(dp);
+
+        // the plan's own stream: launch tuning at creation, then graph capture
+        HIPCHK(hipStreamCreateWithFlags(&p->capture_stream, hipStreamNonBlocking));
 
         // 1) job descriptors
         p->jobs.resize(n_jobs);
@@ -135,11 +140,34 @@ extern "C" int fp_plan_create(const fp_job* jobs, int32_t n_jobs, const fp_plan_
             if (jb.forest->dev_id != p->dev)
                 return fp_set_error(FP_ENODEV, "job %d: forest on device %d, plan on device %d", i, jb.forest->dev_id, p->dev);
             fp_tune t = jb.forest->tune;
+            if (autotune && jb.n_rows > 0 && h.layout != FP_LAYOUT_NAIVE) {
+                // the tune recorded for (forest, size bucket, threads, cursors), else time it now
+                if (fp::launch_tune_get(jb.forest, jb.n_rows, p->threads, p->K, &t)) {
+                    p->jobs_cached++;
+                } else {
+                    double ms = 0.0;
+                    int32_t tried = 0;
+                    rc = fp::search_launch(jb.forest, jb.X, jb.n_rows, jb.ld, p->threads, p->K, p->capture_stream, &t,
+                                           &ms, &tried);
+                    if (rc) {
+                        std::string msg = fp_last_error();
+                        return fp_set_error(rc, "job %d: tuning: %s", i, msg.c_str());
+                    }
+                    fp::launch_tune_put(jb.forest, jb.n_rows, p->threads, p->K, t);
+                    p->jobs_tuned++;
+                }
+                // candidates are timed with the default LDS budget: a smaller
+                // plan budget falls back to the forest's own parameters
+                if (fp::resolve_job(jb.forest, &t, jb.X, jb.n_rows, jb.ld, jb.votes, jb.cls, lds_block, &p->jobs[i]) ==
+                    FP_E2BIG)
+                    t = jb.forest->tune;
+            }
             rc = fp::resolve_job(jb.forest, &t, jb.X, jb.n_rows, jb.ld, jb.votes, jb.cls, lds_block, &p->jobs[i]);
             if (rc) {
                 std::string msg = fp_last_error();
                 return fp_set_error(rc, "job %d: %s", i, msg.c_str());
             }
+            fp::flatten_passes(&p->jobs[i]);
             p->lds_bytes = std::max(p->lds_bytes, (size_t)p->jobs[i].lds_bytes);
             depth[i] = h.expected_depth;
         }
@@ -170,7 +198,6 @@ extern "C" int fp_plan_create(const fp_job* jobs, int32_t n_jobs, const fp_plan_
 
         // 4) graph: captured on the plan's own stream, replayed on any stream
         if (p->use_graph) {
-            HIPCHK(hipStreamCreateWithFlags(&p->capture_stream, hipStreamNonBlocking));
             HIPCHK(hipStreamBeginCapture(p->capture_stream, hipStreamCaptureModeThreadLocal));
             rc = enqueue(p.get(), p->capture_stream);
             hipGraph_t g = nullptr;
@@ -217,6 +244,8 @@ extern "C" int fp_plan_info_get(const fp_plan* p, fp_plan_info* out) {
     out->graph = p->exec != nullptr;
     out->lds_bytes = (int32_t)p->lds_bytes;
     out->total_cost = p->total_cost;
+    out->jobs_tuned = p->jobs_tuned;
+    out->jobs_cached = p->jobs_cached;
     return FP_OK;
 }
 

@@ -1,80 +1,57 @@
 // Serving loop: continuous batching of prediction requests on resident
 // packed forests.
 //
-// Staging memory is two rings in HBM (observations, votes), each mirrored by
-// a pinned host ring at the same offsets; the HBM budget is their total.
-// Admission = getting ring space.  fp_serve_submit reserves space for the
-// request (in arrival order) and copies its rows straight into the pinned
-// ring; when the rings are full it keeps a heap copy instead and the request
-// waits (requests behind it wait too, so admission stays first-come
-// first-served and nothing can starve).  A scheduler thread
-//   1. retires finished launches (event query): copies each request's votes
-//      to the caller's buffer, releases its ring space, records
-//      submit -> ready time;
+// Staging memory is two rings (observations, votes) that the executor
+// keeps on the device and mirrors in host memory at the same offsets; the
+// HBM budget is their total.  Admission = getting ring space.
+// fp_serve_submit reserves space for the request (in arrival order) and
+// copies its rows straight into the host ring; when the rings are full it
+// keeps a heap copy instead and the request waits (requests behind it wait
+// too, so admission stays first-come first-served and nothing can starve).
+// A scheduler thread
+//   1. retires finished launches: copies each request's votes to the
+//      caller's buffer, releases its ring space, records submit -> ready
+//      time; a launch that failed puts its requests back at the head of the
+//      queue, in order, with their ring space kept (a request fails after
+//      max_retries such attempts);
 //   2. when a launch slot is free, takes the longest run of admitted requests
 //      at the head of the queue (up to the coalescing cap) and issues one
-//      launch for all of them on the slot's stream: H2D of their rows, the
-//      batched persistent kernel over every request, D2H of their votes.
-//      Requests admitted one after another sit next to each other in the
-//      rings, so a launch needs one or two copies each way.
+//      launch for all of them: rows to the device, the batched persistent
+//      kernel over every request, votes back.  Requests admitted one after
+//      another sit next to each other in the rings, so a launch needs one or
+//      two copies each way.
 // Up to max_inflight launches overlap.  Requests arriving while launches run
-// join the next launch: continuous batching.
-#include <hip/hip_runtime_api.h>
-
+// join the next launch: continuous batching.  The device work is behind an
+// executor interface (serve_exec.h): HIP on the GPU, or a CPU fake for tests
+// of the scheduler.
 #include <algorithm>
 #include <atomic>
 #include <chrono>
 #include <cmath>
 #include <condition_variable>
+#include <cstdlib>
 #include <cstring>
 #include <deque>
 #include <memory>
 #include <mutex>
 #include <new>
+#include <string>
 #include <system_error>
 #include <thread>
 #include <unordered_map>
 #include <vector>
 
 #include "fp_internal.h"
+#include "serve_exec.h"
 
 using Clock = std::chrono::steady_clock;
-using fp::JobDesc;
-using fp::WorkItem;
 
 namespace {
 
 constexpr size_t kAlign = 256;
 constexpr int32_t kMaxJobsPerLaunch = 4096;
-constexpr size_t kTableBytes = 4u << 20;  // per slot: job table + work items
 
 size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
-
-// Writes one byte of every 4 KiB page of a fresh host buffer (several
-// threads for large buffers), so that its pages are mapped before requests
-// stream through it: left to the first pass of requests through the rings,
-// the page faults held submits back by up to half a second.
-void touch_pages(void* p, size_t n) {
-    volatile uint8_t* b = static_cast<uint8_t*>(p);
-    auto run = [b](size_t lo, size_t hi) {
-        for (size_t i = lo; i < hi; i += 4096) b[i] = 0;
-    };
-    const size_t kSlice = size_t(256) << 20;
-    if (n <= kSlice) {
-        run(0, n);
-        return;
-    }
-    const size_t T = std::min<size_t>(8, (n + kSlice - 1) / kSlice);
-    const size_t per = (n / T + 4095) / 4096 * 4096;
-    std::vector<std::thread> th;
-    try {
-        for (size_t t = 1; t < T; t++) th.emplace_back(run, t * per, std::min(n, (t + 1) * per));
-    } catch (const std::system_error&) {
-        for (size_t t = 1 + th.size(); t < T; t++) run(t * per, std::min(n, (t + 1) * per));  // no more threads
-    }
-    run(0, std::min(n, per));
-    for (auto& t : th) t.join();
-}
 
 enum State { kStaging = 0, kWaiting, kQueued, kInflight, kDone, kFailed };
 
@@ -83,6 +60,7 @@ struct Request {
     const fp_packed* packed = nullptr;
     int64_t n_rows = 0, ld = 0;
     int32_t F = 0, C = 0;
+    int32_t attempts = 0;       // launches that failed for this request
     std::vector<float> heap;    // rows kept here while the rings are full
     int32_t* out = nullptr;     // caller's votes buffer
     Clock::time_point t_submit, t_done;
@@ -131,10 +109,6 @@ struct Ring {
 };
 
 struct Slot {
-    hipStream_t stream = nullptr;
-    hipEvent_t done = nullptr;
-    void* d_tables = nullptr;
-    void* h_tables = nullptr;
     bool busy = false;
     std::vector<Request*> reqs;
 };
@@ -146,15 +120,81 @@ double percentile(std::vector<double> v, double q) {
     return v[k];
 }
 
+// ---------------------------------------------------------------------------
+// CPU fake executor: host rings, launches that complete after a set delay,
+// an injectable failure every k-th launch, and a row checksum in place of
+// the classification (documented with FP_EXECUTOR_CPU_FAKE).
+// ---------------------------------------------------------------------------
+class FakeExecutor final : public fp::ServeExecutor {
+   public:
+    int init(const fp_server_opts& o, size_t xcap, size_t vcap, int n_slots) override {
+        opts_ = o;
+        x_.assign(xcap, 0);
+        v_.assign(vcap, 0);
+        slots_.resize(n_slots);
+        return FP_OK;
+    }
+    uint8_t* host_rows() override { return x_.data(); }
+    uint8_t* host_votes() override { return v_.data(); }
+    int device() const override { return -1; }
+    int check_forest(const fp_packed*) override { return FP_OK; }
+
+    int issue(int slot, const std::vector<fp::ServeItem>& batch) override {
+        FakeSlot& s = slots_[slot];
+        s.batch = batch;
+        s.due = Clock::now() + std::chrono::microseconds(std::max(0, opts_.fake_delay_us));
+        s.fail = opts_.fake_fail_every > 0 && ++launches_ % opts_.fake_fail_every == 0;
+        s.done = false;
+        return FP_OK;
+    }
+
+    int query(int slot) override {
+        FakeSlot& s = slots_[slot];
+        if (!s.done) {
+            if (Clock::now() < s.due) return FP_ENOTREADY;
+            if (!s.fail)
+                for (const fp::ServeItem& it : s.batch) checksum_votes(it);
+            s.done = true;
+        }
+        return s.fail ? fp_set_error(FP_EHIP, "injected launch failure") : FP_OK;
+    }
+
+    void drain(int slot) override { slots_[slot].done = true; }
+
+   private:
+    void checksum_votes(const fp::ServeItem& it) {
+        const uint8_t* rows = x_.data() + it.x_start;
+        int32_t* votes = reinterpret_cast<int32_t*>(v_.data() + it.v_start);
+        for (int64_t i = 0; i < it.n_rows; i++) {
+            uint32_t h = 2166136261u;
+            const uint8_t* b = rows + (size_t)i * it.F * sizeof(float);
+            for (size_t k = 0; k < (size_t)it.F * sizeof(float); k++) h = (h ^ b[k]) * 16777619u;
+            for (int32_t c = 0; c < it.C; c++) votes[i * it.C + c] = (int32_t)((h ^ ((uint32_t)c * 0x9E3779B9u)) & 0x7FFFFFFFu);
+        }
+    }
+
+    struct FakeSlot {
+        std::vector<fp::ServeItem> batch;
+        Clock::time_point due;
+        bool fail = false, done = true;
+    };
+    fp_server_opts opts_{};
+    std::vector<uint8_t> x_, v_;
+    std::vector<FakeSlot> slots_;
+    int64_t launches_ = 0;
+};
+
 }  // namespace
+
+namespace fp {
+std::unique_ptr<ServeExecutor> make_fake_executor() { return std::unique_ptr<ServeExecutor>(new FakeExecutor()); }
+}  // namespace fp
 
 struct fp_server {
     fp_server_opts opts{};
-    int dev = -1;
-    fp::DeviceProps dp;
-    size_t lds_block = 0;
+    std::unique_ptr<fp::ServeExecutor> exec;
     std::vector<const fp_packed*> forests;
-    uint8_t *d_x = nullptr, *h_x = nullptr, *d_v = nullptr, *h_v = nullptr;
+    uint8_t *h_x = nullptr, *h_v = nullptr;
     Ring xring, vring;
     std::vector<Slot> slots;
 
@@ -169,21 +209,13 @@ struct fp_server {
     std::thread sched;
 
     int64_t submitted = 0, completed = 0, rejected = 0, launches = 0, rows = 0;
+    int64_t failed_launches = 0, retried = 0, failed = 0;
     std::vector<double> lat_ms;
     Clock::time_point t0 = Clock::now();
     std::string thread_error;
 
     ~fp_server() {
-        for (auto& s : slots) {
-            if (s.done) (void)hipEventDestroy(s.done);
-            if (s.stream) (void)hipStreamDestroy(s.stream);
-            if (s.d_tables) (void)hipFree(s.d_tables);
-            if (s.h_tables) (void)hipHostFree(s.h_tables);
-        }
-        if (d_x) (void)hipFree(d_x);
-        if (d_v) (void)hipFree(d_v);
-        if (h_x) (void)hipHostFree(h_x);
-        if (h_v) (void)hipHostFree(h_v);
+        exec.reset();  // releases device memory before the requests' bookkeeping
         for (auto& kv : tickets) delete kv.second;
     }
 
@@ -200,70 +232,21 @@ struct fp_server {
         return true;
     }
 
-    // Issue one launch for `batch` on slot s (without the lock).
-    int issue(Slot& s, const std::vector<Request*>& batch) {
-        std::vector<JobDesc> jobs(batch.size());
-        std::vector<double> depth(batch.size());
-        size_t lds = 0;
-        for (size_t i = 0; i < batch.size(); i++) {
-            Request* r = batch[i];
-            fp_tune t = r->packed->tune;
-            int rc = fp::resolve_job(r->packed, &t, reinterpret_cast<const float*>(d_x + r->x_start), r->n_rows, r->F,
-                                     reinterpret_cast<int32_t*>(d_v + r->v_start), nullptr, lds_block, &jobs[i]);
-            if (rc) return rc;
-            lds = std::max(lds, (size_t)jobs[i].lds_bytes);
-            depth[i] = r->packed->hdr.expected_depth;
-        }
-        int occ = 1;
-        int rc = fp::batched_occupancy(opts.cursors, opts.block_threads, lds, &occ);
-        if (rc) return rc;
-        const int64_t resident = (int64_t)dp.cus * occ;
-        std::vector<WorkItem> items;
-        double cost = 0;
-        const size_t jobs_bytes = align_up(jobs.size() * sizeof(JobDesc));
-        for (int ipb = 4;; ipb /= 2) {
-            fp::build_items(jobs, depth, resident, ipb, &items, &cost);
-            if (jobs_bytes + items.size() * sizeof(WorkItem) + kAlign <= kTableBytes) break;
-            if (ipb == 1) return fp_set_error(FP_E2BIG, "launch tables exceed %zu bytes", kTableBytes);
-        }
-        memcpy(s.h_tables, jobs.data(), jobs.size() * sizeof(JobDesc));
-        memcpy(static_cast<uint8_t*>(s.h_tables) + jobs_bytes, items.data(), items.size() * sizeof(WorkItem));
-        uint8_t* dt = static_cast<uint8_t*>(s.d_tables);
-        int32_t* counter = reinterpret_cast<int32_t*>(dt + kTableBytes - kAlign);
-        hipError_t e = hipMemcpyAsync(dt, s.h_tables, jobs_bytes + items.size() * sizeof(WorkItem),
-                                      hipMemcpyHostToDevice, s.stream);
-        // rows: one copy per run of adjacent ring blocks
-        for (size_t i = 0; i < batch.size() && e == hipSuccess;) {
-            size_t j = i + 1, end = batch[i]->x_start + batch[i]->x_size;
-            while (j < batch.size() && batch[j]->x_start == end) end += batch[j++]->x_size;
-            e = hipMemcpyAsync(d_x + batch[i]->x_start, h_x + batch[i]->x_start, end - batch[i]->x_start,
-                               hipMemcpyHostToDevice, s.stream);
-            i = j;
-        }
-        if (e != hipSuccess) return fp_set_error(FP_EHIP, "hipMemcpyAsync: %s", hipGetErrorString(e));
-        const JobDesc* jobs_dev = reinterpret_cast<const JobDesc*>(dt);
-        const WorkItem* items_dev = reinterpret_cast<const WorkItem*>(dt + jobs_bytes);
-        rc = fp::launch_batched_prologue(jobs_dev, (int32_t)jobs.size(), counter, s.stream);
-        if (rc) return rc;
-        const int blocks = (int)std::max<int64_t>(1, std::min<int64_t>(resident, (int64_t)items.size()));
-        rc = fp::launch_batched(jobs_dev, items_dev, (int32_t)items.size(), counter, opts.cursors, opts.block_threads,
-                                lds, blocks, s.stream);
-        if (rc) return rc;
-        for (size_t i = 0; i < batch.size() && e == hipSuccess;) {
-            size_t j = i + 1, end = batch[i]->v_start + batch[i]->v_size;
-            while (j < batch.size() && batch[j]->v_start == end) end += batch[j++]->v_size;
-            e = hipMemcpyAsync(h_v + batch[i]->v_start, d_v + batch[i]->v_start, end - batch[i]->v_start,
-                               hipMemcpyDeviceToHost, s.stream);
-            i = j;
-        }
-        if (e == hipSuccess) e = hipEventRecord(s.done, s.stream);
-        if (e != hipSuccess) return fp_set_error(FP_EHIP, "launch copy-back: %s", hipGetErrorString(e));
-        return FP_OK;
-    }
-
+    // Retires slot s (under the lock).  ok: the votes are in the host ring.
+    // Failed: requests with attempts left go back to the head of the queue,
+    // in their order, keeping their ring space; the others fail.
     void finish_slot(Slot& s, bool ok) {
         const auto now = Clock::now();
+        if (!ok) failed_launches++;
+        std::vector<Request*> again;
         for (Request* r : s.reqs) {
+            if (!ok && (opts.max_retries < 0 || r->attempts < opts.max_retries)) {
+                r->attempts++;
+                r->state = kQueued;
+                again.push_back(r);
+                retried++;
+                continue;
+            }
             if (ok) memcpy(r->out, h_v + r->v_start, (size_t)r->n_rows * r->C * sizeof(int32_t));
             r->t_done = now;
             r->state = ok ? kDone : kFailed;
@@ -271,7 +254,9 @@ struct fp_server {
             vring.release(r->v_start);
             lat_ms.push_back(std::chrono::duration<double, std::milli>(now - r->t_submit).count());
             completed++;
+            if (!ok) failed++;
         }
+        for (auto it = again.rbegin(); it != again.rend(); ++it) queue.push_front(*it);
         s.reqs.clear();
         s.busy = false;
         completed_notify = true;
@@ -293,16 +278,23 @@ struct fp_server {
     }
 
     void run() {
-        if (hipSetDevice(dev) != hipSuccess) thread_error = "hipSetDevice failed in the scheduler";
+        exec->bind_thread();
         std::unique_lock<std::mutex> lk(mu);
         while (true) {
             bool any_busy = false;
-            for (auto& s : slots) {
+            for (size_t k = 0; k < slots.size(); k++) {
+                Slot& s = slots[k];
                 if (!s.busy) continue;
-                const hipError_t q = hipEventQuery(s.done);
-                if (q == hipSuccess) finish_slot(s, true);
-                else if (q != hipErrorNotReady) finish_slot(s, false);
-                else any_busy = true;
+                const int q = exec->query((int)k);
+                if (q == FP_OK) {
+                    finish_slot(s, true);
+                } else if (q != FP_ENOTREADY) {
+                    thread_error = fp_last_error();
+                    exec->drain((int)k);
+                    finish_slot(s, false);
+                } else {
+                    any_busy = true;
+                }
             }
             if (completed_notify) {
                 completed_notify = false;
@@ -310,14 +302,15 @@ struct fp_server {
             }
             if (stop && !any_busy) break;
             if (n_waiting) admit_waiting();
-            Slot* free_slot = nullptr;
-            for (auto& s : slots)
-                if (!s.busy) {
-                    free_slot = &s;
+            int free_slot = -1;
+            for (size_t k = 0; k < slots.size(); k++)
+                if (!slots[k].busy) {
+                    free_slot = (int)k;
                     break;
                 }
-            if (!stop && free_slot && !queue.empty() && queue.front()->state == kQueued) {
+            if (!stop && free_slot >= 0 && !queue.empty() && queue.front()->state == kQueued) {
                 std::vector<Request*> batch;
+                std::vector<fp::ServeItem> items;
                 int64_t rows_total = 0;
                 while (!queue.empty() && queue.front()->state == kQueued && (int32_t)batch.size() < kMaxJobsPerLaunch) {
                     Request* r = queue.front();
@@ -325,19 +318,21 @@ struct fp_server {
                     rows_total += r->n_rows;
                     r->state = kInflight;
                     batch.push_back(r);
+                    items.push_back(fp::ServeItem{r->packed, r->n_rows, r->F, r->C, r->x_start, r->x_size, r->v_start,
+                                                  r->v_size});
                     queue.pop_front();
                 }
-                free_slot->busy = true;
-                free_slot->reqs = batch;
+                Slot& s = slots[free_slot];
+                s.busy = true;
+                s.reqs = batch;
                 launches++;
                 rows += rows_total;
                 lk.unlock();
-                const int rc = issue(*free_slot, batch);
+                const int rc = exec->issue(free_slot, items);
                 lk.lock();
                 if (rc) {
                     thread_error = fp_last_error();
-                    (void)hipStreamSynchronize(free_slot->stream);
-                    finish_slot(*free_slot, false);
+                    finish_slot(s, false);
                 }
                 continue;
             }
@@ -346,12 +341,6 @@ struct fp_server {
         }
     }
 };
-
-#define HIPCHK(call)                                                                                  \
-    do {                                                                                              \
-        hipError_t e_ = (call);                                                                       \
-        if (e_ != hipSuccess) return fp_set_error(FP_EHIP, "%s: %s", #call, hipGetErrorString(e_));   \
-    } while (0)
 
 extern "C" int fp_server_create(const fp_server_opts* opts, fp_server** out) {
     fp_clear_error();
@@ -369,39 +358,29 @@ extern "C" int fp_server_create(const fp_server_opts* opts, fp_server** out) {
         // p99 0.9 ms at 20,000 requests/s, against 0.25 / 1.1 ms for 512 x 4)
         if (o.block_threads <= 0) o.block_threads = 1024;
         if (o.cursors <= 0) o.cursors = 2;
+        if (o.max_retries == 0) o.max_retries = 2;
+        else if (o.max_retries < 0) o.max_retries = 0;
         if (o.block_threads % 64 || o.block_threads > 1024)
             return fp_set_error(FP_EINVAL, "block_threads %d must be a multiple of 64 in [64, 1024]", o.block_threads);
         if (o.cursors != 1 && o.cursors != 2 && o.cursors != 4 && o.cursors != 8)
             return fp_set_error(FP_EINVAL, "cursors must be 1, 2, 4 or 8");
         if (o.max_inflight > 64) return fp_set_error(FP_EINVAL, "max_inflight %d exceeds 64", o.max_inflight);
         if (o.hbm_budget_bytes < (int64_t)(1 << 20)) return fp_set_error(FP_EINVAL, "hbm_budget_bytes below 1 MiB");
-        int rc = fp::current_device(&s->dev);
-        if (rc) return rc;
-        rc = fp::device_props(s->dev, &s->dp);
-        if (rc) return rc;
-        s->lds_block = fp::default_lds_block(s->dp);
+        if (o.executor != FP_EXECUTOR_HIP && o.executor != FP_EXECUTOR_CPU_FAKE)
+            return fp_set_error(FP_EINVAL, "unknown executor %d", o.executor);
+        if (o.fake_delay_us < 0 || o.fake_fail_every < 0)
+            return fp_set_error(FP_EINVAL, "fake_delay_us and fake_fail_every must be >= 0");
         // votes take 1/8 of the budget: C*4 bytes per row against F*4 for rows
         const size_t vcap = align_up((size_t)o.hbm_budget_bytes / 8);
         const size_t xcap = align_up((size_t)o.hbm_budget_bytes - vcap);
         s->xring.cap = xcap;
         s->vring.cap = vcap;
-        hipError_t e = hipMalloc((void**)&s->d_x, xcap);
-        if (e == hipSuccess) e = hipMalloc((void**)&s->d_v, vcap);
-        if (e != hipSuccess) return fp_set_error(FP_ENOMEM, "hipMalloc staging: %s", hipGetErrorString(e));
-        e = hipHostMalloc((void**)&s->h_x, xcap, hipHostMallocDefault);
-        if (e == hipSuccess) e = hipHostMalloc((void**)&s->h_v, vcap, hipHostMallocDefault);
-        if (e != hipSuccess) return fp_set_error(FP_ENOMEM, "hipHostMalloc staging: %s", hipGetErrorString(e));
-        touch_pages(s->h_x, xcap);
-        touch_pages(s->h_v, vcap);
+        s->exec = o.executor == FP_EXECUTOR_CPU_FAKE ? fp::make_fake_executor() : fp::make_hip_executor();
+        int rc = s->exec->init(o, xcap, vcap, o.max_inflight);
+        if (rc) return rc;
+        s->h_x = s->exec->host_rows();
+        s->h_v = s->exec->host_votes();
         s->slots.resize(o.max_inflight);
-        for (auto& sl : s->slots) {
-            HIPCHK(hipStreamCreateWithFlags(&sl.stream, hipStreamNonBlocking));
-            HIPCHK(hipEventCreateWithFlags(&sl.done, hipEventDisableTiming));
-            e = hipMalloc(&sl.d_tables, kTableBytes);
-            if (e != hipSuccess) return fp_set_error(FP_ENOMEM, "hipMalloc tables: %s", hipGetErrorString(e));
-            e = hipHostMalloc(&sl.h_tables, kTableBytes, hipHostMallocDefault);
-            if (e != hipSuccess) return fp_set_error(FP_ENOMEM, "hipHostMalloc tables: %s", hipGetErrorString(e));
-        }
         fp_server* raw = s.get();
         s->sched = std::thread([raw] { raw->run(); });
         *out = s.release();
@@ -418,11 +397,7 @@ extern "C" int fp_server_add_forest(fp_server* s, const fp_packed* p, int32_t* f
     if (!s || !p || !forest_id) return fp_set_error(FP_EINVAL, "NULL argument");
     if (p->hdr.layout == FP_LAYOUT_NAIVE)
         return fp_set_error(FP_EINVAL, "forest is not in a packed layout");
-    if (!p->dev) return fp_set_error(FP_ENODEV, "forest is not uploaded");
-    if (p->dev_id != s->dev) return fp_set_error(FP_ENODEV, "forest on device %d, server on device %d", p->dev_id, s->dev);
-    fp::JobDesc j;  // the forest's launch parameters must fit the server's LDS budget
-    fp_tune t = p->tune;
-    int rc = fp::resolve_job(p, &t, nullptr, 1, p->hdr.n_features, nullptr, nullptr, s->lds_block, &j);
+    int rc = s->exec->check_forest(p);
     if (rc) return rc;
     std::lock_guard<std::mutex> lk(s->mu);
     s->forests.push_back(p);
@@ -540,6 +515,9 @@ extern "C" int fp_server_stats(fp_server* s, fp_serve_stats* out) {
     }
     out->mean_rows_per_launch = s->launches ? (double)s->rows / (double)s->launches : 0.0;
     out->elapsed_s = std::chrono::duration<double>(Clock::now() - s->t0).count();
+    out->failed_launches = s->failed_launches;
+    out->retried = s->retried;
+    out->failed = s->failed;
     return FP_OK;
 }
 
@@ -548,6 +526,7 @@ extern "C" int fp_server_reset_stats(fp_server* s) {
     if (!s) return fp_set_error(FP_EINVAL, "server is NULL");
     std::lock_guard<std::mutex> lk(s->mu);
     s->submitted = s->completed = s->rejected = s->launches = s->rows = 0;
+    s->failed_launches = s->retried = s->failed = 0;
     s->lat_ms.clear();
     s->t0 = Clock::now();
     return FP_OK;

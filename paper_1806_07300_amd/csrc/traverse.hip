@@ -312,10 +312,30 @@ __device__ __forceinline__ void stage_tile(const JobDesc& j, float* xs, int32_t*
 
 // After the walks of a tile: stores its vote counters (or adds them into the
 // global votes when several tree groups share the rows), then the class of
-// each row (lowest class on ties) when this workgroup saw every tree.
+// each row (lowest class on ties) when this workgroup saw every tree.  In a
+// later pass (accumulate) each thread owns whole rows: it adds the tile's
+// counters to the stored votes and, in the last pass (cls set), takes the
+// class from the sums; no other workgroup touches these rows in the launch.
 __device__ __forceinline__ void write_tile(const JobDesc& j, const int32_t* vl, int64_t row0, int rows) {
     const int tid = threadIdx.x, bd = blockDim.x;
     __syncthreads();
+    if (j.accumulate) {
+        for (int rr = tid; rr < rows; rr += bd) {
+            int32_t* dst = j.votes + (row0 + rr) * j.C;
+            int32_t best = 0, bestv = INT_MIN;
+            for (int c = 0; c < j.C; c++) {
+                const int32_t v = dst[c] + vl[rr * j.C + c];
+                dst[c] = v;
+                if (v > bestv) {
+                    bestv = v;
+                    best = c;
+                }
+            }
+            if (j.cls) j.cls[row0 + rr] = best;
+        }
+        __syncthreads();
+        return;
+    }
     for (int i = tid; i < rows * j.C; i += bd) {
         int32_t* dst = j.votes + row0 * j.C + i;
         if (j.atomic_votes) {
@@ -931,7 +951,7 @@ struct MinWaves {
 template <int K, int FMODE, int LAYOUT>
 __global__ __launch_bounds__(1024, (MinWaves<K, LAYOUT>::value)) void packed_kernel(JobDesc j) {
     extern __shared__ __align__(16) unsigned char smem[];
-    const int group = blockIdx.x % j.G;
+    const int group = j.group_base + (int)(blockIdx.x % j.G);
     const int blocks_per_group = gridDim.x / j.G;
     const int nt = stage_group(j, group, smem);
     if (nt == 0) return;  // uniform per block
@@ -1143,7 +1163,11 @@ int resolve_job(const fp_packed* p, const fp_tune* t, const float* X, int64_t n_
     if (R > 4096) return fp_set_error(FP_EINVAL, "rows_per_block %d exceeds 4096", R);
     int G = t->tree_groups > 0 ? t->tree_groups : 1;
     if (G > h.n_bins) G = h.n_bins;
-    const int bpg = (h.n_bins + G - 1) / G;
+    int P = t->tree_passes > 0 ? t->tree_passes : 1;
+    if ((int64_t)P * G > h.n_bins) P = std::max(1, h.n_bins / G);
+    const int bpg = (h.n_bins + P * G - 1) / (P * G);
+    // passes that would hold no bin are dropped: the last pass writes the classes
+    P = ((h.n_bins + bpg - 1) / bpg + G - 1) / G;
     const int tpg = (int)std::min<int64_t>((int64_t)bpg * h.bin_size, h.n_trees);
     if ((int64_t)R * tpg >= (1 << 30)) return fp_set_error(FP_E2BIG, "rows_per_block x trees per group too large");
     const uint8_t* base = static_cast<const uint8_t*>(p->dev);
@@ -1164,6 +1188,7 @@ int resolve_job(const fp_packed* p, const fp_tune* t, const float* X, int64_t n_
     j->bin_size = h.bin_size;
     j->R = R;
     j->G = G;
+    j->passes = P;
     j->bins_per_group = bpg;
     j->trees_per_group = tpg;
     j->n_tiles = (int32_t)((n_rows + R - 1) / R);
@@ -1258,6 +1283,44 @@ int launch_leaf_counts(const Node16* nodes, const int64_t* tree_off, int32_t n_t
     hipLaunchKernelGGL(leaf_count_kernel, dim3((unsigned)blocks), dim3(256), 0, s, nodes, tree_off, n_trees, X, n_rows,
                        ld, counts);
     return check_launch("leaf_count_kernel");
+}
+
+int device_upload(void* dev, const void* src, size_t n, void* stream_v, int* dev_id) {
+    hipStream_t stream = static_cast<hipStream_t>(stream_v);
+    hipError_t e = hipGetDevice(dev_id);
+    if (e != hipSuccess) return fp_set_error(FP_EHIP, "hipGetDevice: %s", hipGetErrorString(e));
+    e = hipMemcpyAsync(dev, src, n, hipMemcpyHostToDevice, stream);
+    if (e != hipSuccess) return fp_set_error(FP_EHIP, "hipMemcpyAsync: %s", hipGetErrorString(e));
+    e = hipStreamSynchronize(stream);
+    if (e != hipSuccess) return fp_set_error(FP_EHIP, "hipStreamSynchronize: %s", hipGetErrorString(e));
+    return FP_OK;
+}
+
+int device_leaf_counts(const uint8_t* bytes, size_t nbytes, const Header& h, int32_t n_trees, const float* X,
+                       int64_t n_rows, int64_t ld, int32_t* counts, void* stream_v) {
+    hipStream_t stream = static_cast<hipStream_t>(stream_v);
+    DevBuf buf, cnt;
+    int rc = buf.ensure(nbytes);
+    if (!rc) rc = cnt.ensure(sizeof(int32_t) * (size_t)h.n_nodes);
+    if (rc) return rc;
+    // once work is queued, every exit waits for the stream before the
+    // buffers above (and the host arrays the copies use) go away
+    struct Drain {
+        hipStream_t s;
+        ~Drain() { (void)hipStreamSynchronize(s); }
+    } drain{stream};
+    hipError_t e = hipMemcpyAsync(buf.p, bytes, nbytes, hipMemcpyHostToDevice, stream);
+    if (e == hipSuccess) e = hipMemsetAsync(cnt.p, 0, sizeof(int32_t) * (size_t)h.n_nodes, stream);
+    if (e != hipSuccess) return fp_set_error(FP_EHIP, "upload: %s", hipGetErrorString(e));
+    const uint8_t* base = static_cast<const uint8_t*>(buf.p);
+    rc = launch_leaf_counts(reinterpret_cast<const Node16*>(base + h.nodes_offset),
+                            reinterpret_cast<const int64_t*>(base + h.table_offset), n_trees, X, n_rows, ld,
+                            static_cast<int32_t*>(cnt.p), stream);
+    if (rc) return rc;
+    e = hipMemcpyAsync(counts, cnt.p, sizeof(int32_t) * (size_t)h.n_nodes, hipMemcpyDeviceToHost, stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(stream);
+    if (e != hipSuccess) return fp_set_error(FP_EHIP, "counts: %s", hipGetErrorString(e));
+    return FP_OK;
 }
 
 int launch_fill(int32_t* p, int64_t n, int32_t v, hipStream_t s) {
@@ -1364,16 +1427,44 @@ static int predict_impl(const fp_packed* p, const fp_tune* tune, const float* X,
         rc = fp::launch_fill(votes, n_rows * h.n_classes, 0, stream);
         if (rc) return rc;
     }
-    rc = fp::launch_packed(j, K, threads, blocks, stream);
-    if (rc) return rc;
+    // one launch per pass; with one group per pass the first stores the votes
+    // and later ones add to them (the last also writes the classes), with
+    // several concurrent groups every pass adds with atomics
+    for (int pass = 0; pass < j.passes; pass++) {
+        fp::JobDesc jp = j;
+        jp.group_base = pass * j.G;
+        jp.accumulate = !j.atomic_votes && pass > 0;
+        jp.cls = (!j.atomic_votes && pass == j.passes - 1) ? cls : nullptr;
+        rc = fp::launch_packed(jp, K, threads, blocks, stream);
+        if (rc) return rc;
+    }
     if (j.atomic_votes && cls) return fp::launch_argmax(votes, cls, n_rows, h.n_classes, stream);
     return FP_OK;
 }
 
+// The launch parameters: the tune recorded for p's batch-size bucket
+// (fp_tune_launch, this process or the FP_TUNE_CACHE file), else p's own.
 extern "C" int fp_predict(const fp_packed* p, const float* X_dev, int64_t n_rows, int64_t ld, int32_t* votes_dev,
                           int32_t* class_dev, void* stream) {
     if (!p) return fp_set_error(FP_EINVAL, "packed forest is NULL");
+    fp_tune t;
+    if (p->hdr.layout != FP_LAYOUT_NAIVE && n_rows > 0 && fp::launch_tune_get(p, n_rows, 0, 0, &t))
+        return predict_impl(p, &t, X_dev, n_rows, ld, votes_dev, class_dev, stream);
     return predict_impl(p, &p->tune, X_dev, n_rows, ld, votes_dev, class_dev, stream);
+}
+
+extern "C" int fp_predict_tune_get(const fp_packed* p, int64_t n_rows, fp_tune* out, int32_t* source) {
+    fp_clear_error();
+    if (!p || !out) return fp_set_error(FP_EINVAL, "NULL argument");
+    int32_t src = p->has_tune ? 1 : 0;
+    *out = p->tune;
+    fp_tune t;
+    if (p->hdr.layout != FP_LAYOUT_NAIVE && n_rows > 0 && fp::launch_tune_get(p, n_rows, 0, 0, &t)) {
+        *out = t;
+        src = 2;
+    }
+    if (source) *source = src;
+    return FP_OK;
 }
 
 extern "C" int fp_predict_tuned(const fp_packed* p, const fp_tune* tune, const float* X_dev, int64_t n_rows,
