@@ -514,7 +514,7 @@ def gather_ceiling(fp, torch, working_set: int, fetch_bytes: int, chains=(1, 2, 
     """Best dependent-gather rate over chains per lane through a buffer of
     about `working_set` bytes (the probe rounds the element count down to a
     power of two)."""
-    buf = torch.empty(max(working_set, 1024 * fetch_bytes) // 4 + 16, dtype=torch.int32, device="cuda")
+    buf = torch.empty(max(working_set, 64 * fetch_bytes) // 4 + 16, dtype=torch.int32, device="cuda")
     n = 1
     while n * 2 * fetch_bytes <= buf.numel() * 4:
         n *= 2
@@ -522,6 +522,21 @@ def gather_ceiling(fp, torch, working_set: int, fetch_bytes: int, chains=(1, 2, 
     del buf
     return {"working_set_bytes": n * fetch_bytes, "fetch_bytes": fetch_bytes, "fetches_per_s": best[0],
             "gbps": best[0] * fetch_bytes / 1e9, "chains_per_lane": best[1]}
+
+
+def vmem_ceiling(fp, torch, res, fetch_bytes):
+    """The kernel's block fetches per second against the most the load path
+    returns at all: the gather probe over a 16 KB working set (every CU's L1
+    holds it) with 4 or 8 chains per lane.  The kernel's count is the
+    training-distributed fetches per walk from the packed header times the
+    walks of a step; blocks served from LDS are included, so the fraction is
+    an upper estimate."""
+    g = gather_ceiling(fp, torch, 16 << 10, fetch_bytes, chains=(4, 8))
+    walks = res["n_rows"] * res["n_trees"]
+    kernel = res["expected_fetches_per_walk"] * walks / (res["ms_per_step"] / 1e3)
+    return {"probe_block_fetches_per_s": g["fetches_per_s"], "probe_working_set_bytes": g["working_set_bytes"],
+            "probe_chains_per_lane": g["chains_per_lane"], "fetch_bytes": fetch_bytes,
+            "kernel_block_fetches_per_s": kernel, "frac": kernel / g["fetches_per_s"]}
 
 
 def probes(args, fp, synth, torch):
@@ -655,6 +670,9 @@ def main():
     torch.cuda.empty_cache()
     res["block_bytes_per_fetch"] = 64
     rl = roofline(res, "tabular")
+    vm = vmem_ceiling(fp, torch, res, 64)
+    log(f"vector-memory ceiling: {vm['probe_block_fetches_per_s'] / 1e9:.0f} G 64-byte blocks/s (L1-resident probe); "
+        f"kernel {vm['kernel_block_fetches_per_s'] / 1e9:.0f} G/s = {vm['frac']:.2f}")
     out = {
         "metric": METRIC,
         "value": res["value"],
@@ -680,6 +698,7 @@ def main():
         "speedup_vs_naive": res["speedup_vs_naive"],
         "bit_exact_vs_naive_all_rows": res["bit_exact_vs_naive_all_rows"],
         "roofline": rl,
+        "vmem_ceiling": vm,
         "wall_s_timed": res["wall_s_timed"],
         "pack_s": res["pack_s"],
     }
@@ -704,6 +723,7 @@ def main():
             r["compare"] = ("fp16: rows staged in LDS rounded toward +inf, every threshold exact in fp16 "
                             "(48-byte clustered blocks); decides every x <= t exactly as fp32")
             r["roofline"] = roofline(r, "image")
+            r["vmem_ceiling"] = vmem_ceiling(fp, torch, r, 48)
             torch.cuda.empty_cache()
         elif leg == "batched":
             r = leg_batched(args, fp, synth, torch, np, 8 if args.lite else 64)

@@ -640,7 +640,7 @@ int fp_probe_stream(const void *src_dev, void *dst_dev, uint64_t bytes, double *
  * dependent load per node or block).  buf_dev (caller-owned, 16-byte
  * aligned, `bytes` long, overwritten) is laid out as one pseudo-random cycle
  * over n elements of fetch_bytes (16, 48 or 64) bytes, n the largest power of
- * two that fits (at least 1024, at most 2^31); every lane of a full GPU
+ * two that fits (at least 64, at most 2^31); every lane of a full GPU
  * (2 x CUs workgroups of 1024) follows `chains` (1, 2, 4, 8) independent
  * chains for `steps` steps, loading each element whole.  *fetches_per_s =
  * element fetches per second (timed launch after a warm-up).

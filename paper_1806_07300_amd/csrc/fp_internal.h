@@ -307,6 +307,10 @@ int search_launch(const fp_packed* p, const float* X, int64_t n_rows, int64_t ld
 // estimated cost first.  `expected_depth[i]` is job i's forest cost model.
 void build_items(const std::vector<JobDesc>& jobs, const std::vector<double>& expected_depth, int64_t resident,
                  int items_per_block, std::vector<WorkItem>* items, double* total_cost);
+// The same into caller memory of cap items; returns the number of items
+// (sorted only when it is at most cap).  Allocates nothing.
+size_t build_items_into(const JobDesc* jobs, const double* expected_depth, size_t n, int64_t resident,
+                        int items_per_block, WorkItem* out, size_t cap, double* total_cost);
 
 }  // namespace fp
 

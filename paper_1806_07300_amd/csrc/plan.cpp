@@ -57,34 +57,51 @@ static int enqueue(fp_plan* p, hipStream_t s) {
 
 namespace fp {
 
-void build_items(const std::vector<JobDesc>& jobs, const std::vector<double>& expected_depth, int64_t resident,
-                 int items_per_block, std::vector<WorkItem>* items, double* total_cost) {
-    const size_t n = jobs.size();
-    std::vector<double> tile_cost(n, 0.0);
+size_t build_items_into(const JobDesc* jobs, const double* expected_depth, size_t n, int64_t resident,
+                        int items_per_block, WorkItem* out, size_t cap, double* total_cost) {
+    auto depth = [&](size_t i) { return std::max(1.0, expected_depth[i]); };
+    auto tile_cost = [&](size_t i) { return (double)jobs[i].R * jobs[i].trees_per_group * depth(i); };
     double total = 0.0;
     for (size_t i = 0; i < n; i++) {
         const JobDesc& j = jobs[i];
-        const double d = std::max(1.0, expected_depth[i]);
-        tile_cost[i] = (double)j.R * j.trees_per_group * d;
         const int64_t trees = std::min<int64_t>((int64_t)j.n_bins * j.bin_size, (int64_t)j.trees_per_group * j.G);
-        total += (double)j.n_rows * trees * d;
+        total += (double)j.n_rows * trees * depth(i);
     }
     const double target = total / (double)std::max<int64_t>(1, resident * std::max(1, items_per_block));
-    items->clear();
+    size_t k = 0;
     for (size_t i = 0; i < n; i++) {
         const JobDesc& j = jobs[i];
         if (j.n_rows == 0) continue;
-        const int chunk = (int)std::max(1.0, std::min((double)j.n_tiles, std::floor(target / std::max(tile_cost[i], 1.0))));
+        const int chunk =
+            (int)std::max(1.0, std::min((double)j.n_tiles, std::floor(target / std::max(tile_cost(i), 1.0))));
         for (int32_t g = 0; g < j.G; g++) {
             if (g * j.bins_per_group >= j.n_bins) break;
-            for (int32_t t = 0; t < j.n_tiles; t += chunk)
-                items->push_back(WorkItem{(int32_t)i, g, t, std::min(j.n_tiles, t + chunk)});
+            for (int32_t t = 0; t < j.n_tiles; t += chunk, k++)
+                if (k < cap) out[k] = WorkItem{(int32_t)i, g, t, std::min(j.n_tiles, t + chunk)};
         }
     }
-    std::stable_sort(items->begin(), items->end(), [&](const WorkItem& a, const WorkItem& b) {
-        return tile_cost[a.job] * (a.tile_end - a.tile_begin) > tile_cost[b.job] * (b.tile_end - b.tile_begin);
-    });
     *total_cost = total;
+    if (k > cap) return k;
+    // largest estimated cost first; equal costs keep the order of creation
+    // (job, group, first tile), so the list is the same on every call
+    std::sort(out, out + k, [&](const WorkItem& a, const WorkItem& b) {
+        const double ca = tile_cost(a.job) * (a.tile_end - a.tile_begin);
+        const double cb = tile_cost(b.job) * (b.tile_end - b.tile_begin);
+        if (ca != cb) return ca > cb;
+        if (a.job != b.job) return a.job < b.job;
+        if (a.group != b.group) return a.group < b.group;
+        return a.tile_begin < b.tile_begin;
+    });
+    return k;
+}
+
+void build_items(const std::vector<JobDesc>& jobs, const std::vector<double>& expected_depth, int64_t resident,
+                 int items_per_block, std::vector<WorkItem>* items, double* total_cost) {
+    const size_t k = build_items_into(jobs.data(), expected_depth.data(), jobs.size(), resident, items_per_block,
+                                      nullptr, 0, total_cost);
+    items->resize(k);
+    build_items_into(jobs.data(), expected_depth.data(), jobs.size(), resident, items_per_block, items->data(), k,
+                     total_cost);
 }
 
 }  // namespace fp

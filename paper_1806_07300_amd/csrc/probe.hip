@@ -9,7 +9,10 @@
 //                       next index from its first word.  The rate of such
 //                       fetches against the working-set size is the ceiling
 //                       of a walk whose every step needs the previous one,
-//                       as a tree walk does.
+//                       as a tree walk does.  With a working set that fits
+//                       every CU's L1 (16 KB, say) and 8 chains per lane it
+//                       is the vector-memory ceiling: the most block fetches
+//                       per second the load path returns at all.
 //
 // The cycle: element i points to (a i + c) mod n with n a power of two, a = 1
 // mod 4 and c odd, which visits all n elements once per period (Hull-Dobell),
@@ -133,7 +136,7 @@ extern "C" int fp_probe_gather(void* buf_dev, uint64_t bytes, int32_t fetch_byte
     // the largest power-of-two element count that fits, at most 2^31 elements
     uint64_t n = 1;
     while (n * 2 * (uint64_t)fetch_bytes <= bytes && n < (1ull << 31)) n *= 2;
-    if (n * (uint64_t)fetch_bytes > bytes || n < 1024) return fp_set_error(FP_EINVAL, "buffer holds fewer than 1024 elements");
+    if (n * (uint64_t)fetch_bytes > bytes || n < 64) return fp_set_error(FP_EINVAL, "buffer holds fewer than 64 elements");
     hipStream_t s = static_cast<hipStream_t>(stream_v);
     int dev = 0, cus = 0;
     if (hipGetDevice(&dev) != hipSuccess || hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)

@@ -161,7 +161,7 @@ def test_batched_fp16_tile(threads, cursors):
 
 
 @pytest.mark.timeout(900)  # trains 64 forests on the host first (about a minute on 16 threads)
-def test_batched_workload_64_forests():
+def test_batched_workload_64_forests(say):
     """The 64-forest workload (16-2048 trees, 4-784 features, 2-10 classes,
     1-200,000 rows each), every forest autotuned, one persistent graph launch.
     Every row of every forest equals the checker on two graph replays, and
@@ -174,8 +174,8 @@ def test_batched_workload_64_forests():
         X, _ = w.predict_rows()
         Xd = torch.from_numpy(X).cuda()
         res = fp.fp_autotune(f, Xd, block_threads=threads, cursors=cursors, sample_rows=16384)
-        if i % 8 == 7:
-            print(f"[batched] {i + 1} forests trained and tuned", flush=True)
+        if i % 4 == 3:
+            say(f"[batched] {i + 1} forests trained and tuned")
         p = fp.fp_pack_forest(f, **res["pack"])
         fp.fp_packed_upload(p)
         fp.fp_packed_set_tune(p, res["tune"])
@@ -210,14 +210,14 @@ def test_batched_workload_64_forests():
     torch.cuda.synchronize()
     ms_naive = t0.elapsed_time(t1)
     layouts = [fp.fp_packed_info_get(j["packed"])["layout"] for j in jobs]
-    print(f"\n[batched] 64 forests, {rows} rows: one graph launch {ms:.3f} ms = {rows / ms / 1e3:.2f} M obs/s; "
+    say(f"\n[batched] 64 forests, {rows} rows: one graph launch {ms:.3f} ms = {rows / ms / 1e3:.2f} M obs/s; "
           f"naive layout, 64 launches {ms_naive:.3f} ms = {rows / ms_naive / 1e3:.2f} M obs/s "
-          f"({ms_naive / ms:.2f}x); layouts chosen {np.bincount(layouts, minlength=4).tolist()}", flush=True)
+        f"({ms_naive / ms:.2f}x); layouts chosen {np.bincount(layouts, minlength=5).tolist()}")
     for i, j in enumerate(jobs):
         if len(j["X"]):
             assert torch.equal(nv[i], j["votes"]), f"forest {i}: naive votes differ"
     want = [oracle.predict(j["forest"], j["X"]) for j in jobs]  # every row of every forest
-    print(f"[batched] checker done for {rows} rows", flush=True)
+    say(f"[batched] checker done for {rows} rows")
     for replay in range(2):
         for j in jobs:
             j["votes"].fill_(-1)

@@ -19,9 +19,9 @@ def test_stream_probe():
     assert torch.equal(a, b)
 
 
+@pytest.mark.parametrize("n", [4096, 256])  # 256 x 64 B: the L1-resident ceiling's working set
 @pytest.mark.parametrize("fetch_bytes", [16, 48, 64])
-def test_gather_buffer_is_one_cycle(fetch_bytes):
-    n = 4096
+def test_gather_buffer_is_one_cycle(fetch_bytes, n):
     buf = torch.zeros(n * fetch_bytes // 4 + 7, dtype=torch.int32, device="cuda")
     rate = fp.fp_probe_gather(buf, fetch_bytes, chains=2, steps=16)
     assert rate > 0
@@ -44,4 +44,4 @@ def test_probe_arguments_refused():
             fp.fp_probe_gather(buf, **{"fetch_bytes": 16, "chains": 1, "steps": 4, **kw})
         assert e.value.code == fp.FP_EINVAL
     with pytest.raises(fp.FPError):
-        fp.fp_probe_gather(torch.zeros(100, dtype=torch.int32, device="cuda"), 16, 1, 4)  # fewer than 1024 elements
+        fp.fp_probe_gather(torch.zeros(100, dtype=torch.int32, device="cuda"), 16, 1, 4)  # fewer than 64 elements

@@ -1,0 +1,76 @@
+"""The batched entry point that allocates nothing (fp_predict_batched_noalloc)
+against the plan path (fp_plan_create + fp_predict_batched) on the same jobs,
+bit for bit, on two calls in a row -- the second with fewer jobs and fewer
+rows, so that stale tables or counters in the static scratch would show --
+and against the CPU checker."""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import paper_1806_07300_amd as fp
+import synth
+
+pytestmark = pytest.mark.gpu
+
+SPECS = [  # trees, features, classes, rows, layout, bin, depth, tune
+    (40, 12, 3, 5000, fp.FP_LAYOUT_CLUSTERED, 8, 3, {"rows_per_block": 32}),
+    (24, 30, 5, 1777, fp.FP_LAYOUT_PACKED, 4, 2, {"rows_per_block": 16, "tree_groups": 2}),
+    (33, 9, 2, 3001, fp.FP_LAYOUT_BLOCKED, 33, 3, {"rows_per_block": 64}),
+    (50, 16, 4, 2500, fp.FP_LAYOUT_CLUSTERED, 5, 3, {"rows_per_block": 24, "tree_passes": 4}),
+    (18, 7, 6, 1, fp.FP_LAYOUT_COMPACT, 6, 2, {}),
+]
+
+
+def make_jobs(n_rows_scale=1.0, which=None):
+    jobs = []
+    for i, (T, F, C, N, layout, B, D, tune) in enumerate(SPECS):
+        if which is not None and i not in which:
+            continue
+        Xt, yt = synth.gaussian_mixture(2000, F, C, seed=300 + i)
+        f = synth.train_forest(Xt, yt, n_trees=T, n_classes=C, mtry=max(1, int(np.sqrt(F))), max_depth=11,
+                               seed=310 + i)
+        n = max(1, int(N * n_rows_scale))
+        X, _ = synth.gaussian_mixture(n, F, C, seed=320 + i)
+        p = fp.fp_pack_forest(f, layout=layout, bin_size=B, interleave_depth=D)
+        fp.fp_packed_upload(p)
+        if tune:
+            fp.fp_packed_set_tune(p, tune)
+        jobs.append({"forest": f, "X": X, "packed": p, "Xd": torch.from_numpy(X).cuda(), "C": C})
+    return jobs
+
+
+def outputs(jobs):
+    return [(torch.full((len(j["X"]), j["C"]), -1, dtype=torch.int32, device="cuda"),
+             torch.full((len(j["X"]),), -1, dtype=torch.int32, device="cuda")) for j in jobs]
+
+
+@pytest.mark.parametrize("threads,cursors", [(1024, 2), (512, 4)])
+def test_noalloc_matches_the_plan_twice(threads, cursors):
+    for call, (scale, which) in enumerate(((1.0, None), (0.3, [0, 3, 4]))):
+        jobs = make_jobs(scale, which)
+        mine, ref = outputs(jobs), outputs(jobs)
+        print(f"[noalloc] call {call + 1}: {len(jobs)} jobs, {sum(len(j['X']) for j in jobs)} rows", flush=True)
+        fp.fp_predict_batched_noalloc([(j["packed"], j["Xd"], v, c) for j, (v, c) in zip(jobs, mine)],
+                                      block_threads=threads, cursors=cursors)
+        plan = fp.fp_plan_create([(j["packed"], j["Xd"], v, c) for j, (v, c) in zip(jobs, ref)],
+                                 block_threads=threads, cursors=cursors)
+        fp.fp_predict_batched(plan)
+        torch.cuda.synchronize()
+        for j, (v, c), (rv, rc) in zip(jobs, mine, ref):
+            assert torch.equal(v, rv) and torch.equal(c, rc), f"call {call + 1}: differs from the plan"
+            wv, wc = oracle.predict(j["forest"], j["X"])
+            assert np.array_equal(v.cpu().numpy(), wv) and np.array_equal(c.cpu().numpy(), wc)
+
+
+def test_noalloc_rejects():
+    jobs = make_jobs(0.1, [0])
+    (v, c), = outputs(jobs)
+    j = jobs[0]
+    L = fp.lib()
+    arr = (fp.fp_job * 1)(fp.fp_job(j["packed"].handle.value, j["Xd"].data_ptr(), len(j["X"]), j["X"].shape[1],
+                                    v.data_ptr(), c.data_ptr()))
+    opts = fp.fp_plan_opts(1024, 2, 0, 0, 0, 1, 0)  # autotune would time candidates: refused
+    assert L.fp_predict_batched_noalloc(arr, 1, opts, None) == fp.FP_EINVAL
+    assert L.fp_predict_batched_noalloc(arr, 0, None, None) == fp.FP_EINVAL
+    assert L.fp_predict_batched_noalloc(arr, 5000, None, None) == fp.FP_E2BIG
