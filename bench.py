@@ -614,55 +614,11 @@ def only(args, fp, synth, torch):
         log(f"{args.only} launch {i + 1}/{args.steps} done")
 
 
-def main():
-    ap = argparse.ArgumentParser()
-    ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=10)
-    ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--rows", type=int, default=0, help="rows per step for --only/--ladder/--probes (0: the workload's)")
-    ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--only", choices=["packed", "naive", "copy"], default=None)
-    ap.add_argument("--workload", choices=["tabular", "image", "small"], default="tabular")
-    ap.add_argument("--cache", default=os.environ.get("FP_BENCH_CACHE", "/tmp/forestpack_cache"))
-    ap.add_argument("--legs", default="small,image,batched,serve",
-                    help="extra workloads after the headline, comma-separated (or 'none')")
-    ap.add_argument("--budget-s", type=float, default=480.0,
-                    help="start no extra leg after this many seconds of the run")
-    ap.add_argument("--serve-seconds", type=float, default=10.0)
-    ap.add_argument("--serve-rate", type=float, default=20000.0)
-    ap.add_argument("--ladder", choices=["image", "tabular", "tabular_imb"], default=None)
-    ap.add_argument("--probes", action="store_true")
-    ap.add_argument("--lite", action="store_true",
-                    help="small sizes for every leg, to check the code paths quickly (not a measurement)")
-    args = ap.parse_args()
-    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
-        print(f"bench.py measures one GPU only (asked for {args.gpus}); rows shard across GPUs with the "
-              "forest replicated and no exchange, which is not run here.", file=sys.stderr)
-        sys.exit(2)
-
-    import numpy as np
-    import torch
-    import paper_1806_07300_amd as fp
-    from paper_1806_07300_amd import presets
-    import synth
-
-    if not torch.cuda.is_available():
-        print("bench.py needs a GPU", file=sys.stderr)
-        sys.exit(1)
-    torch.cuda.set_device(0)
-    if args.only:
-        only(args, fp, synth, torch)
-        return
-    if args.ladder:
-        ladder(args, fp, synth, torch)
-        return
-    if args.probes:
-        probes(args, fp, synth, torch)
-        return
-
-    # headline: the tabular workload, 10M rows through 1,024 trees in bins of 16
-    tab_w = synth.tabular(n_train=20_000, n_trees=32, n_predict=200_000) if args.lite else synth.tabular()
-    img_w = synth.image(n_train=6000, n_trees=16, n_predict=100_000) if args.lite else synth.image()
+def headline(args, fp, torch, np, presets, tab_w):
+    """The benchmark's line: the tabular workload, 10M rows through 1,024
+    trees in bins of 16, packed (the preset's launch) against naive, with the
+    CPU checker's baseline and bit-exact check, the HBM roofline and the
+    vector-memory ceiling."""
     res = single_forest_leg("tabular", tab_w, presets.TABULAR, args, fp, torch, np, args.steps,
                             args.warmup, 3, with_cpu=True)
     forest, packed, naive, Xd, votes, cls = res.pop("_keep")
@@ -705,6 +661,63 @@ def main():
     for k in ("cpu_baseline", "oracle_check", "node_visits_per_row", "node_visits_per_s"):
         if k in res:
             out[k] = res[k]
+    return out, packed
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--rows", type=int, default=0, help="rows per step for --only/--ladder/--probes (0: the workload's)")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--only", choices=["packed", "naive", "copy"], default=None)
+    ap.add_argument("--workload", choices=["tabular", "image", "small"], default="tabular")
+    ap.add_argument("--cache", default=os.environ.get("FP_BENCH_CACHE", "/tmp/forestpack_cache"))
+    ap.add_argument("--headline", choices=["tabular", "none"], default="tabular",
+                    help="none: only the extra workloads (profiling sessions; no benchmark line)")
+    ap.add_argument("--legs", default="small,image,batched,serve",
+                    help="extra workloads after the headline, comma-separated (or 'none')")
+    ap.add_argument("--budget-s", type=float, default=480.0,
+                    help="start no extra leg after this many seconds of the run")
+    ap.add_argument("--serve-seconds", type=float, default=10.0)
+    ap.add_argument("--serve-rate", type=float, default=20000.0)
+    ap.add_argument("--ladder", choices=["image", "tabular", "tabular_imb"], default=None)
+    ap.add_argument("--probes", action="store_true")
+    ap.add_argument("--lite", action="store_true",
+                    help="small sizes for every leg, to check the code paths quickly (not a measurement)")
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print(f"bench.py measures one GPU only (asked for {args.gpus}); rows shard across GPUs with the "
+              "forest replicated and no exchange, which is not run here.", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+    import paper_1806_07300_amd as fp
+    from paper_1806_07300_amd import presets
+    import synth
+
+    if not torch.cuda.is_available():
+        print("bench.py needs a GPU", file=sys.stderr)
+        sys.exit(1)
+    torch.cuda.set_device(0)
+    if args.only:
+        only(args, fp, synth, torch)
+        return
+    if args.ladder:
+        ladder(args, fp, synth, torch)
+        return
+    if args.probes:
+        probes(args, fp, synth, torch)
+        return
+
+    tab_w = synth.tabular(n_train=20_000, n_trees=32, n_predict=200_000) if args.lite else synth.tabular()
+    img_w = synth.image(n_train=6000, n_trees=16, n_predict=100_000) if args.lite else synth.image()
+    if args.headline == "none":  # the extra workloads alone (profiling sessions); not the benchmark's line
+        out, packed = {"headline": None}, None
+    else:
+        out, packed = headline(args, fp, torch, np, presets, tab_w)
     legs = [x for x in args.legs.split(",") if x and x != "none"]
     extra = {}
     image_forest = None
@@ -730,6 +743,9 @@ def main():
         elif leg == "serve":
             if image_forest is None:
                 image_forest = img_w.forest(cache_dir=args.cache)
+            if packed is None:
+                tf = tab_w.forest(cache_dir=args.cache, progress=Progress("tabular"))
+                packed, _ = pack(fp, tf, **presets.TABULAR["pack"])
             r = leg_serve(args, fp, synth, torch, np, img_w, image_forest, tab_w, packed,
                           2.0 if args.lite else args.serve_seconds, 1.0,
                           2000.0 if args.lite else args.serve_rate, pool_rows=100_000 if args.lite else 1_000_000)
