@@ -504,6 +504,26 @@ int fp_plan_info_get(const fp_plan *plan, fp_plan_info *out);
 
 void fp_plan_free(fp_plan *plan);
 
+/*
+ * For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): one batched
+ * run of `jobs` -- what fp_plan_create followed by fp_predict_batched computes,
+ * with the same kernels -- that allocates nothing.  The job table, the work
+ * list and the work counter go to a fixed device array of 1 MiB inside the
+ * library (one per GPU, held until the process ends), filled by a copy from
+ * a static host area that HIP performs synchronously; no hipMalloc, hipFree
+ * or other allocating call is made.  Limits: at most 4,096 jobs and as many
+ * work items as fit the array after the job table (about 50,000 for a few
+ * jobs); larger requests return FP_E2BIG.  Each job uses the tune recorded
+ * for its forest, size bucket, block_threads and cursors, else its forest's
+ * own tune; opts->autotune must be 0 (FP_EINVAL), use_graph is ignored.
+ * Calls on one GPU share its array: a call waits for earlier work on
+ * `stream` before overwriting it, but calls that overlap on different
+ * streams of one GPU race.  Arguments, ownership and other errors are those
+ * of fp_plan_create and fp_predict_batched.
+ */
+int fp_predict_batched_noalloc(const fp_job *jobs, int32_t n_jobs, const fp_plan_opts *opts, void *stream);
+
 /* ------------------------------------------------------------------------ */
 /* Serving: continuous batching of prediction requests                       */
 /* ------------------------------------------------------------------------ */

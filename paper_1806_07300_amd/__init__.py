@@ -150,6 +150,8 @@ def lib():
             "fp_plan_create": ([ctypes.POINTER(fp_job), _i32, ctypes.POINTER(fp_plan_opts), ctypes.POINTER(_vp)],
                                ctypes.c_int),
             "fp_predict_batched": ([_vp, _vp], ctypes.c_int),
+            "fp_predict_batched_noalloc": ([ctypes.POINTER(fp_job), _i32, ctypes.POINTER(fp_plan_opts), _vp],
+                                           ctypes.c_int),
             "fp_plan_info_get": ([_vp, ctypes.POINTER(fp_plan_info)], ctypes.c_int),
             "fp_plan_free": ([_vp], None),
             "fp_server_create": ([ctypes.POINTER(fp_server_opts), ctypes.POINTER(_vp)], ctypes.c_int),
@@ -478,6 +480,20 @@ def fp_plan_create(jobs, block_threads: int = 0, cursors: int = 0, use_graph: bo
     _check(lib().fp_plan_create(arr, len(jobs), None if default_opts else ctypes.byref(opts), ctypes.byref(out)),
            "fp_plan_create")
     return Plan(out.value, keep)
+
+
+def fp_predict_batched_noalloc(jobs, block_threads: int = 0, cursors: int = 0, items_per_block: int = 0,
+                               lds_budget: int = 0, stream=None) -> None:
+    """One batched run of jobs [(Packed, X, votes, cls-or-None)] that
+    allocates no device memory (tables in the library's static scratch)."""
+    arr = (fp_job * len(jobs))()
+    for i, (p, X, votes, cls) in enumerate(jobs):
+        n, ld = _check_rows(X, fp_packed_info_get(p)["n_features"])
+        arr[i] = fp_job(p.handle.value, X.data_ptr(), n, ld, votes.data_ptr(),
+                        cls.data_ptr() if cls is not None else None)
+    opts = fp_plan_opts(block_threads, cursors, 0, items_per_block, lds_budget, 0, 0)
+    _check(lib().fp_predict_batched_noalloc(arr, len(jobs), ctypes.byref(opts), _stream_ptr(stream)),
+           "fp_predict_batched_noalloc")
 
 
 def fp_predict_batched(plan: Plan, stream=None) -> None:
