@@ -81,9 +81,10 @@ def traffic_file(workload: str) -> str:
 
 
 def read_traffic(workload: str):
-    """HBM bytes per launch of the workload's packed kernel measured by
-    rocprofv3 --pmc (FETCH_SIZE, WRITE_SIZE, scaled by a copy-kernel
-    calibration); None when missing or taken on a different kernel source."""
+    """HBM bytes per step of the workload's packed kernel (all the step's
+    launches: one per tree pass) measured by rocprofv3 --pmc (FETCH_SIZE,
+    WRITE_SIZE, scaled by a copy-kernel calibration); None when missing or
+    taken on a different kernel source."""
     path = traffic_file(workload)
     if not os.path.exists(path):
         return None
@@ -95,6 +96,8 @@ def read_traffic(workload: str):
     if vals.get("kernel_source_sha256") != kernel_source_hash():
         return None
     try:
+        if "fetch_bytes_per_step" in vals:
+            return float(vals["fetch_bytes_per_step"]) + float(vals["write_bytes_per_step"])
         return float(vals["fetch_bytes_per_launch"]) + float(vals["write_bytes_per_launch"])
     except (KeyError, ValueError):
         return None
