@@ -136,13 +136,21 @@ class Forest:
 def train_forest(X: np.ndarray, y: np.ndarray, *, n_trees: int, n_classes: int, mtry: int,
                  max_depth: int = -1, bootstrap: bool = True, seed: int = 0,
                  min_samples_split: int = 2, n_threads: int = 0, tree_offset: int = 0,
-                 progress=None) -> Forest:
+                 progress=None, checkpoint: str | None = None) -> Forest:
     """Train a seeded CART random forest (see the header of cart.c).
 
     Tree t depends only on (seed, tree_offset + t), so a forest can be trained
     in chunks; with ``progress`` set, trees are trained in chunks of that many
-    and ``progress(done, total)`` is called after each chunk."""
+    (default 64) and ``progress(done, total)`` is called after each chunk.
+    With ``checkpoint`` (a path prefix) set, each finished chunk is saved as
+    ``<prefix>.trees<first>-<end>.npz`` and a later call with the same
+    prefix loads the chunks it finds instead of training them again, so an
+    interrupted training resumes where it stopped and yields the same forest.
+    The prefix must name one (data, parameters) pair; the caller removes the
+    chunk files once the forest is kept elsewhere."""
     chunk = max(1, int(getattr(progress, "chunk", 64))) if progress is not None else n_trees
+    if checkpoint is not None and progress is None:
+        chunk = 64
     lib = _load()
     X = np.ascontiguousarray(X, dtype=np.float32)
     y = np.ascontiguousarray(y, dtype=np.int32)
@@ -155,6 +163,17 @@ def train_forest(X: np.ndarray, y: np.ndarray, *, n_trees: int, n_classes: int, 
         parts = []
         for t0 in range(0, n_trees, chunk):
             k = min(chunk, n_trees - t0)
+            part = f"{checkpoint}.trees{tree_offset + t0}-{tree_offset + t0 + k}.npz" if checkpoint else None
+            if part and os.path.exists(part):
+                try:
+                    f = Forest.load(part)
+                except Exception:  # an unreadable chunk file is trained again
+                    f = None
+                if f is not None and f.n_trees == k and f.n_features == F and f.n_classes == n_classes:
+                    parts.append(f)
+                    if progress is not None:
+                        progress(t0 + k, n_trees)
+                    continue
             p = _Params(k, F, n_classes, mtry, max_depth, min_samples_split, int(bool(bootstrap)),
                         n_threads, tree_offset + t0, 0, seed & 0xFFFFFFFFFFFFFFFF)
             h = ctypes.c_void_p()
@@ -165,6 +184,8 @@ def train_forest(X: np.ndarray, y: np.ndarray, *, n_trees: int, n_classes: int, 
                 parts.append(_export(lib, h, k, F, n_classes))
             finally:
                 lib.cart_free(h)
+            if part:
+                _save_atomic(parts[-1], part)
             if progress is not None:
                 progress(t0 + k, n_trees)
     finally:
@@ -378,16 +399,31 @@ class Workload:
         X, y = self.train_rows()
         f = train_forest(X, y, n_trees=self.n_trees, n_classes=self.n_classes, mtry=self.mtry,
                          max_depth=self.max_depth, bootstrap=True, seed=self.forest_seed,
-                         n_threads=n_threads, progress=progress)
-        if path:
-            try:  # np.savez appends .npz only when missing: save to a temporary name, then rename
-                f.save(path + ".tmp.npz")
-                os.replace(path + ".tmp.npz", path)
-            except OSError as e:  # a full disk only costs the cache
-                print(f"[synth] forest cache not written ({e})", flush=True)
-                if os.path.exists(path + ".tmp.npz"):
-                    os.remove(path + ".tmp.npz")
+                         n_threads=n_threads, progress=progress,
+                         checkpoint=path[:-len(".npz")] if path else None)
+        if path and _save_atomic(f, path):
+            for name in os.listdir(cache_dir):  # the chunk files of this forest
+                if name.startswith(f"forest_{self.name}.trees") and name.endswith(".npz"):
+                    try:
+                        os.remove(os.path.join(cache_dir, name))
+                    except OSError:
+                        pass
         return f
+
+
+def _save_atomic(f: Forest, path: str) -> bool:
+    """Save to a temporary name, then rename (np.savez appends .npz only when
+    missing), so a reader never sees half a file.  A failure (a full disk)
+    only costs the cache: it is reported and False returned."""
+    try:
+        f.save(path + ".tmp.npz")
+        os.replace(path + ".tmp.npz", path)
+        return True
+    except OSError as e:
+        print(f"[synth] forest cache not written ({e})", flush=True)
+        if os.path.exists(path + ".tmp.npz"):
+            os.remove(path + ".tmp.npz")
+        return False
 
 
 def small() -> Workload:

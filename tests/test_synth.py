@@ -8,6 +8,7 @@ thread-count independence) and a partition cross-check against scikit-learn's
 CART on tie-free data.
 """
 from fractions import Fraction
+import os
 import itertools
 
 import numpy as np
@@ -325,3 +326,56 @@ def test_training_rejects_nan():
     y = np.arange(10, dtype=np.int32) % 2
     with pytest.raises(RuntimeError):
         synth.train_forest(X, y, n_trees=1, n_classes=2, mtry=2, bootstrap=False, seed=0)
+
+
+class _StopAfter:
+    """A progress callback that interrupts training after `n` chunks."""
+    chunk = 8
+
+    def __init__(self, n):
+        self.n, self.calls = n, []
+
+    def __call__(self, done, total):
+        self.calls.append(done)
+        if len(self.calls) == self.n:
+            raise KeyboardInterrupt
+
+
+def test_interrupted_training_resumes_to_the_same_forest(tmp_path):
+    """Chunks of finished trees are kept while a forest trains; a second call
+    after an interruption loads them, trains only the rest, and the forest is
+    the one an uninterrupted training gives (tree t depends on (seed, t) only)."""
+    w = synth.small()
+    X, y = w.train_rows()
+    kw = dict(n_trees=w.n_trees, n_classes=w.n_classes, mtry=w.mtry, max_depth=w.max_depth, seed=w.forest_seed)
+    whole = synth.train_forest(X, y, **kw)
+    prefix = str(tmp_path / "f")
+    stop = _StopAfter(2)
+    with pytest.raises(KeyboardInterrupt):
+        synth.train_forest(X, y, progress=stop, checkpoint=prefix, **kw)
+    assert sorted(os.listdir(tmp_path)) == ["f.trees0-8.npz", "f.trees8-16.npz"]
+    seen = []
+
+    class Count:
+        chunk = 8
+
+        def __call__(self, done, total):
+            seen.append(done)
+
+    # a chunk file that cannot be read is trained again
+    with open(tmp_path / "f.trees8-16.npz", "wb") as fh:
+        fh.write(b"not a forest")
+    resumed = synth.train_forest(X, y, progress=Count(), checkpoint=prefix, **kw)
+    assert seen == [8, 16, 24, 32]
+    assert sorted(os.listdir(tmp_path)) == ["f.trees0-8.npz", "f.trees16-24.npz", "f.trees24-32.npz",
+                                            "f.trees8-16.npz"]
+    for k in ("tree_node_offset", "feature", "threshold", "left", "right", "leaf_class", "cardinality", "depth"):
+        assert np.array_equal(getattr(resumed, k), getattr(whole, k)), k
+
+
+def test_workload_cache_removes_its_chunks(tmp_path):
+    w = synth.small()
+    f = w.forest(cache_dir=str(tmp_path))
+    assert os.listdir(tmp_path) == ["forest_small.npz"]
+    g = w.forest(cache_dir=str(tmp_path))
+    assert np.array_equal(f.threshold, g.threshold) and np.array_equal(f.tree_node_offset, g.tree_node_offset)
