@@ -80,11 +80,12 @@ def traffic_file(workload: str) -> str:
     return os.path.join(ROOT, "profiles", f"packed_kernel_{workload}_traffic.txt")
 
 
-def read_traffic(workload: str):
+def read_traffic(workload: str, tune: dict | None = None):
     """HBM bytes per step of the workload's packed kernel (all the step's
     launches: one per tree pass) measured by rocprofv3 --pmc (FETCH_SIZE,
-    WRITE_SIZE, scaled by a copy-kernel calibration); None when missing or
-    taken on a different kernel source."""
+    WRITE_SIZE, scaled by a copy-kernel calibration); None when missing,
+    taken on a different kernel source, or (when the record names its
+    launch) with a launch other than `tune`."""
     path = traffic_file(workload)
     if not os.path.exists(path):
         return None
@@ -95,6 +96,12 @@ def read_traffic(workload: str):
             vals[k.strip()] = v.strip()
     if vals.get("kernel_source_sha256") != kernel_source_hash():
         return None
+    if tune is not None and "launch" in vals:
+        try:
+            if json.loads(vals["launch"]) != tune:
+                return None
+        except ValueError:
+            return None
     try:
         if "fetch_bytes_per_step" in vals:
             return float(vals["fetch_bytes_per_step"]) + float(vals["write_bytes_per_step"])
@@ -224,7 +231,7 @@ def roofline(res, workload):
     algo = n * (F * 4 + C * 4 + 4) + res["packed_bytes"]
     achieved = algo / (res["ms_per_step"] / 1e3) / 1e9
     return {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-            "frac": achieved / HBM_PEAK_GBS, "traffic": read_traffic(workload),
+            "frac": achieved / HBM_PEAK_GBS, "traffic": read_traffic(workload, res.get("tune")),
             "algorithmic_bytes_per_launch": algo}
 
 

@@ -252,6 +252,24 @@ int search_launch(const fp_packed* p, const float* X, int64_t n_rows, int64_t ld
         t.tree_groups = g;
         if ((rc = time_one(t))) return rc;
     }
+    // pass 4 (single-forest searches, whose workgroup size is free, with
+    // 1024-thread workgroups): one workgroup per CU holding all of the CU's
+    // LDS, so that its bin tops are not duplicated across two workgroups, at
+    // the same tile and a tile half as large again.  A plan's workgroups
+    // share one LDS budget, so plans (threads fixed) skip it.
+    const fp_tune p3 = best_t;
+    int dev = 0;
+    DeviceProps dp;
+    if (threads <= 0 && p3.block_threads == 1024 && current_device(&dev) == FP_OK && device_props(dev, &dp) == FP_OK &&
+        dp.lds_per_block > (size_t)default_lds_block(dp)) {
+        for (int grow = 0; grow < 2; grow++) {
+            fp_tune t = p3;
+            t.lds_bytes = (int32_t)dp.lds_per_block;
+            if (grow) t.rows_per_block = std::min(4096, t.rows_per_block + t.rows_per_block / 2);
+            if (t.rows_per_block > 2 * n) break;
+            if ((rc = time_one(t))) return rc;
+        }
+    }
     *best_out = best_t;
     *best_ms_out = best;
     *tried_out = tried;

@@ -17,16 +17,20 @@ IMAGE = {
 }
 
 # Gaussian thresholds are not exact in fp16, so the clustered blocks take
-# their 64-byte form with fp32 thresholds; 512 rows of 28 fp32 features per
-# tile.  The 2.8 GB forest does not fit any cache: the 64 bins are walked in
-# 32 passes of two bins (32 trees, about 88 MB), one launch each over all
-# rows, so that a pass's blocks stay in the last-level cache while every row
-# walks them (408 ms in one pass; 391, 379, 353, 345, 350 ms in 4, 8, 16,
-# 32, 64 passes)
+# their 64-byte form with fp32 thresholds.  The 2.8 GB forest does not fit
+# any cache: the 64 bins are walked in 16 passes of four bins (64 trees,
+# about 177 MB), one launch each over all rows, so that a pass's blocks stay
+# in the last-level cache while every row walks them.  One 1024-thread
+# workgroup per CU takes the CU's whole LDS (lds_bytes 160 KB): a 768-row
+# tile of 28 fp32 features and, in the rest, the first blocks of the pass's
+# bins, which two workgroups per CU would each have to hold a copy of; with
+# half the wavefronts, lanes are refilled once 24 of a wavefront's are idle.
+# Measured on 10M rows: one pass 408 ms; 32 passes of 512-row tiles, two
+# workgroups per CU 345 ms; this launch 269 ms
 TABULAR = {
     "pack": {"layout": 4, "bin_size": 16, "interleave_depth": 3, "line_align": 0},
-    "tune": {"rows_per_block": 512, "cursors": 1, "tree_groups": 1, "block_threads": 1024, "refill_lanes": 32,
-             "feature_lds": 1, "tree_passes": 32},
+    "tune": {"rows_per_block": 768, "cursors": 1, "tree_groups": 1, "block_threads": 1024, "refill_lanes": 24,
+             "feature_lds": 1, "tree_passes": 16, "lds_bytes": 163840},
     "naive_tune": {"block_threads": 256},
 }
 
