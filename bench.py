@@ -224,15 +224,19 @@ def single_forest_leg(name, w, preset, args, fp, torch, np, steps, warmup, naive
 
 
 def roofline(res, workload):
-    """The compulsory HBM bytes of one launch (rows in, votes and classes out,
-    the packed forest read once) over the packed kernel's time per launch
-    (the step is that one kernel: one tree group, no argmax pass)."""
+    """The compulsory HBM bytes of one step (rows in, votes and classes out,
+    the packed forest read once) over the step's time.  A step is the packed
+    kernel alone (one tree group, no argmax pass), launched once per tree
+    pass: per launch, the bytes and the time are both the step's divided by
+    the number of passes, the same ratio."""
     n, F, C = res["n_rows"], res["n_features"], res["n_classes"]
     algo = n * (F * 4 + C * 4 + 4) + res["packed_bytes"]
     achieved = algo / (res["ms_per_step"] / 1e3) / 1e9
+    traffic = read_traffic(workload, res.get("tune"))
     return {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-            "frac": achieved / HBM_PEAK_GBS, "traffic": read_traffic(workload, res.get("tune")),
-            "algorithmic_bytes_per_launch": algo}
+            "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
+            "algorithmic_bytes_per_launch": algo,
+            "traffic_over_algorithmic": traffic / algo if traffic else None}
 
 
 def leg_batched(args, fp, synth, torch, np, n_forests=64):

@@ -265,7 +265,15 @@ int resolve_job(const fp_packed* p, const fp_tune* t, const float* X, int64_t n_
 size_t default_lds_block(const DeviceProps& dp);
 
 int packed_occupancy(int K, int fmode, int layout, int threads, size_t lds, int* blocks_per_cu);
-int batched_occupancy(int K, int threads, size_t lds, int* blocks_per_cu);
+// Batched launches: `lds` is the largest job layout; the launch adds a
+// 16-byte slot after it (the workgroup's item number), so jobs are resolved
+// against batched_job_budget(lds_block).
+constexpr size_t kItemSlotBytes = 16;
+size_t batched_job_budget(size_t lds_block);
+// blocks_only: every job of the launch is in a block layout (BLOCKED or
+// CLUSTERED): the launch takes the kernel variant without node-layout walks.
+int batched_occupancy(int K, bool blocks_only, int threads, size_t lds, int* blocks_per_cu);
+bool jobs_blocks_only(const JobDesc* jobs, int32_t n_jobs);
 
 // The packer's two device operations, kept out of the host-only packer:
 // copy n bytes to device memory on `stream` and wait for it (the current
@@ -283,7 +291,7 @@ int launch_leaf_counts(const Node16* nodes, const int64_t* tree_off, int32_t n_t
 int launch_argmax(const int32_t* votes, int32_t* cls, int64_t n, int32_t C, hipStream_t s);
 int launch_packed(const JobDesc& j, int K, int threads, int blocks, hipStream_t s);
 int launch_batched(const JobDesc* jobs, const WorkItem* items, int32_t n_items, int32_t* counter, int K,
-                   int threads, size_t lds_bytes, int blocks, hipStream_t s);
+                   bool blocks_only, int threads, size_t lds_bytes, int blocks, hipStream_t s);
 // Zero the work counter and the votes of every job that accumulates with atomics.
 int launch_batched_prologue(const JobDesc* jobs_dev, int32_t n_jobs, int32_t* counter, hipStream_t s);
 int launch_batched_epilogue(const JobDesc* jobs_dev, int32_t n_jobs, hipStream_t s);

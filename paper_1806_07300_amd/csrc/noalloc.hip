@@ -64,8 +64,8 @@ extern "C" int fp_predict_batched_noalloc(const fp_job* jobs, int32_t n_jobs, co
         return fp_set_error(FP_EINVAL, "block_threads %d must be a multiple of 64 in [64, 1024]", threads);
     if (K != 1 && K != 2 && K != 4 && K != 8) return fp_set_error(FP_EINVAL, "cursors must be 1, 2, 4 or 8");
     const size_t blk_max = dp.lds_per_block ? dp.lds_per_block : 65536;
-    const size_t lds_block =
-        opts && opts->lds_budget > 0 ? std::min((size_t)opts->lds_budget, blk_max) : fp::default_lds_block(dp);
+    const size_t lds_block = fp::batched_job_budget(
+        opts && opts->lds_budget > 0 ? std::min((size_t)opts->lds_budget, blk_max) : fp::default_lds_block(dp));
     const size_t jobs_bytes = align256(sizeof(fp::JobDesc) * (size_t)n_jobs);
     if (jobs_bytes + 512 > kScratchBytes)
         return fp_set_error(FP_E2BIG, "%d jobs need %zu bytes of tables; the scratch holds %zu", n_jobs, jobs_bytes,
@@ -97,7 +97,8 @@ extern "C" int fp_predict_batched_noalloc(const fp_job* jobs, int32_t n_jobs, co
         lds = std::max(lds, (size_t)jd[i].lds_bytes);
     }
     int occ = 1;
-    rc = fp::batched_occupancy(K, threads, lds, &occ);
+    const bool blocks_only = fp::jobs_blocks_only(jd, n_jobs);
+    rc = fp::batched_occupancy(K, blocks_only, threads, lds, &occ);
     if (rc) return rc;
     const int64_t resident = (int64_t)dp.cus * occ;
     // the plan's work list, written straight after the job table
@@ -123,7 +124,7 @@ extern "C" int fp_predict_batched_noalloc(const fp_job* jobs, int32_t n_jobs, co
     rc = fp::launch_batched_prologue(jobs_dev, n_jobs, counter, stream);
     if (rc) return rc;
     const int blocks = (int)std::max<int64_t>(1, std::min<int64_t>(resident, (int64_t)n_items));
-    rc = fp::launch_batched(jobs_dev, items_dev, (int32_t)n_items, counter, K, threads, lds, blocks, stream);
+    rc = fp::launch_batched(jobs_dev, items_dev, (int32_t)n_items, counter, K, blocks_only, threads, lds, blocks, stream);
     if (rc) return rc;
     return fp::launch_batched_epilogue(jobs_dev, n_jobs, stream);
 }

@@ -29,6 +29,7 @@ struct fp_plan {
     WorkItem* items_dev = nullptr;
     int32_t* counter_dev = nullptr;
     int K = 2, threads = 1024, blocks = 1;
+    bool blocks_only = false;  // every job in a block layout: the lean kernel variant
     size_t lds_bytes = 0;
     double total_cost = 0.0;
     int32_t jobs_tuned = 0, jobs_cached = 0;
@@ -49,8 +50,8 @@ static int enqueue(fp_plan* p, hipStream_t s) {
     const int32_t n_jobs = (int32_t)p->jobs.size();
     int rc = fp::launch_batched_prologue(p->jobs_dev, n_jobs, p->counter_dev, s);
     if (rc) return rc;
-    rc = fp::launch_batched(p->jobs_dev, p->items_dev, (int32_t)p->items.size(), p->counter_dev, p->K, p->threads,
-                            p->lds_bytes, p->blocks, s);
+    rc = fp::launch_batched(p->jobs_dev, p->items_dev, (int32_t)p->items.size(), p->counter_dev, p->K,
+                            p->blocks_only, p->threads, p->lds_bytes, p->blocks, s);
     if (rc) return rc;
     return fp::launch_batched_epilogue(p->jobs_dev, n_jobs, s);
 }
@@ -137,8 +138,9 @@ extern "C" int fp_plan_create(const fp_job* jobs, int32_t n_jobs, const fp_plan_
         if (p->K != 1 && p->K != 2 && p->K != 4 && p->K != 8)
             return fp_set_error(FP_EINVAL, "cursors must be 1, 2, 4 or 8");
         const size_t blk_max = dp.lds_per_block ? dp.lds_per_block : 65536;
-        const size_t lds_block =
-            opts && opts->lds_budget > 0 ? std::min((size_t)opts->lds_budget, blk_max) : fp::default_lds_block(dp);
+        // the jobs' share of the workgroup's LDS (the launch adds the item slot)
+        const size_t lds_block = fp::batched_job_budget(
+            opts && opts->lds_budget > 0 ? std::min((size_t)opts->lds_budget, blk_max) : fp::default_lds_block(dp));
 
         // the plan's own stream: launch tuning at creation, then graph capture
         HIPCHK(hipStreamCreateWithFlags(&p->capture_stream, hipStreamNonBlocking));
@@ -191,7 +193,8 @@ extern "C" int fp_plan_create(const fp_job* jobs, int32_t n_jobs, const fp_plan_
 
         // 2) persistent grid and work items
         int occ = 1;
-        rc = fp::batched_occupancy(p->K, p->threads, p->lds_bytes, &occ);
+        p->blocks_only = fp::jobs_blocks_only(p->jobs.data(), (int32_t)p->jobs.size());
+        rc = fp::batched_occupancy(p->K, p->blocks_only, p->threads, p->lds_bytes, &occ);
         if (rc) return rc;
         const int64_t resident = (int64_t)dp.cus * occ;
         fp::build_items(p->jobs, depth, resident, items_per_block, &p->items, &p->total_cost);

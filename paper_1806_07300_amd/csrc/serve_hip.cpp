@@ -75,7 +75,7 @@ class HipExecutor final : public fp::ServeExecutor {
         if (rc) return rc;
         rc = fp::device_props(dev_, &dp_);
         if (rc) return rc;
-        lds_block_ = fp::default_lds_block(dp_);
+        lds_block_ = fp::batched_job_budget(fp::default_lds_block(dp_));
         hipError_t e = hipMalloc((void**)&d_x_, xcap);
         if (e == hipSuccess) e = hipMalloc((void**)&d_v_, vcap);
         if (e != hipSuccess) return fp_set_error(FP_ENOMEM, "hipMalloc staging: %s", hipGetErrorString(e));
@@ -126,7 +126,8 @@ class HipExecutor final : public fp::ServeExecutor {
             depth[i] = r.packed->hdr.expected_depth;
         }
         int occ = 1;
-        int rc = fp::batched_occupancy(opts_.cursors, opts_.block_threads, lds, &occ);
+        const bool blocks_only = fp::jobs_blocks_only(jobs.data(), (int32_t)jobs.size());
+        int rc = fp::batched_occupancy(opts_.cursors, blocks_only, opts_.block_threads, lds, &occ);
         if (rc) return rc;
         const int64_t resident = (int64_t)dp_.cus * occ;
         std::vector<fp::WorkItem> items;
@@ -160,7 +161,7 @@ class HipExecutor final : public fp::ServeExecutor {
         rc = fp::launch_batched_prologue(jobs_dev, (int32_t)jobs.size(), counter, s.stream);
         const int blocks = (int)std::max<int64_t>(1, std::min<int64_t>(resident, (int64_t)items.size()));
         if (!rc)
-            rc = fp::launch_batched(jobs_dev, items_dev, (int32_t)items.size(), counter, opts_.cursors,
+            rc = fp::launch_batched(jobs_dev, items_dev, (int32_t)items.size(), counter, opts_.cursors, blocks_only,
                                     opts_.block_threads, lds, blocks, s.stream);
         if (rc) {
             (void)hipStreamSynchronize(s.stream);

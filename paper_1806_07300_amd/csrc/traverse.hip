@@ -974,17 +974,53 @@ __global__ __launch_bounds__(1024, (MinWaves<K, LAYOUT>::value)) void packed_ker
 // Many forests: persistent workgroups pull work items from a global counter
 // (items are ordered largest first) and restage LDS when the (job, group)
 // changes.  Every workgroup exits once the counter passes n_items.
-template <int K>
+// Tiles [tile_begin, tile_end) of one work item, features in LDS (FM 1) or
+// read from memory (FM 0).  Block layouts walk one block per lane.
+// BLOCKS: every job of the launch is in a block layout (the host picks this
+// variant only then), so the node-layout walks are not compiled in and do
+// not set the kernel's register budget.
+template <int K, int FM, bool BLOCKS>
+__device__ __forceinline__ void item_tiles(const JobDesc& j, const WorkItem& w, int nt, unsigned char* smem) {
+    for (int tile = w.tile_begin; tile < w.tile_end; tile++) {
+        if (!BLOCKS && j.layout == FP_LAYOUT_COMPACT) {
+            run_tile_compact<K, FM>(j, nt, tile, smem);
+        } else if (j.layout == FP_LAYOUT_CLUSTERED && j.block_bytes == 48) {
+            if constexpr (FM == 1) {
+                if (j.x16) {
+                    run_tile_blocked<1, 1, 4>(j, nt, tile, smem);
+                    continue;
+                }
+            }
+            run_tile_blocked<1, FM, 3>(j, nt, tile, smem);
+        } else if (j.layout == FP_LAYOUT_CLUSTERED) {
+            run_tile_blocked<1, FM, 2>(j, nt, tile, smem);
+        } else if (j.layout == FP_LAYOUT_BLOCKED) {
+            if (j.block_bytes == 48) run_tile_blocked<1, FM, 0>(j, nt, tile, smem);
+            else run_tile_blocked<1, FM, 1>(j, nt, tile, smem);
+        } else if constexpr (!BLOCKS) {
+            run_tile<K, FM>(j, nt, tile, smem);
+        }
+    }
+}
+
+// The item number is broadcast through a slot at the end of the dynamic LDS
+// (item_slot bytes in), not a static __shared__ variable: static LDS would
+// add to every job's budget and leave two workgroups no longer fitting a CU.
+template <int K, bool BLOCKS>
 __global__ __launch_bounds__(1024, (K <= 2 ? 8 : 4)) void batched_kernel(const JobDesc* __restrict__ jobs,
                                                                          const WorkItem* __restrict__ items,
-                                                                         int32_t n_items, int32_t* counter) {
+                                                                         int32_t n_items, int32_t* counter,
+                                                                         int32_t item_slot) {
     extern __shared__ __align__(16) unsigned char smem[];
-    __shared__ int32_t s_item;
+    int32_t* s_item = reinterpret_cast<int32_t*>(smem + item_slot);
     int staged_job = -1, staged_group = -1, nt = 0;
     while (true) {
-        if (threadIdx.x == 0) s_item = atomicAdd(counter, 1);
+        if (threadIdx.x == 0) *s_item = atomicAdd(counter, 1);
         __syncthreads();
-        const int it = s_item;
+        // the item is the workgroup's: readfirstlane makes that visible to the
+        // compiler, so the item and its job descriptor are loaded into scalar
+        // registers instead of occupying vector registers in every lane
+        const int it = __builtin_amdgcn_readfirstlane(*s_item);
         __syncthreads();
         if (it >= n_items) break;
         const WorkItem w = items[it];
@@ -995,18 +1031,9 @@ __global__ __launch_bounds__(1024, (K <= 2 ? 8 : 4)) void batched_kernel(const J
             staged_group = w.group;
         }
         if (nt == 0) continue;
-        if (j.layout == FP_LAYOUT_COMPACT)
-            for (int tile = w.tile_begin; tile < w.tile_end; tile++) run_tile_compact<K, 2>(j, nt, tile, smem);
-        else if (j.layout >= FP_LAYOUT_BLOCKED)
-            for (int tile = w.tile_begin; tile < w.tile_end; tile++) {
-                if (j.layout == FP_LAYOUT_CLUSTERED && j.block_bytes == 48 && j.x16) run_tile_blocked<1, 2, 4>(j, nt, tile, smem);
-                else if (j.layout == FP_LAYOUT_CLUSTERED && j.block_bytes == 48) run_tile_blocked<1, 2, 3>(j, nt, tile, smem);
-                else if (j.layout == FP_LAYOUT_CLUSTERED) run_tile_blocked<1, 2, 2>(j, nt, tile, smem);
-                else if (j.block_bytes == 48) run_tile_blocked<1, 2, 0>(j, nt, tile, smem);
-                else run_tile_blocked<1, 2, 1>(j, nt, tile, smem);
-            }
-        else
-            for (int tile = w.tile_begin; tile < w.tile_end; tile++) run_tile<K, 2>(j, nt, tile, smem);
+        // the feature source is fixed per job: walk with it compiled in
+        if (j.feat_lds) item_tiles<K, 1, BLOCKS>(j, w, nt, smem);
+        else item_tiles<K, 0, BLOCKS>(j, w, nt, smem);
     }
 }
 
@@ -1083,13 +1110,16 @@ const void* pick_packed(int K, int fmode, int layout) {
     return nullptr;
 }
 
-const void* pick_batched(int K) {
+// blocks_only: every job is in a block layout, which walks one block per
+// lane whatever K is.
+const void* pick_batched(int K, bool blocks_only) {
+    if (K != 1 && K != 2 && K != 4 && K != 8) return nullptr;
+    if (blocks_only) return reinterpret_cast<const void*>(&batched_kernel<1, true>);
     switch (K) {
-        case 1: return reinterpret_cast<const void*>(&batched_kernel<1>);
-        case 2: return reinterpret_cast<const void*>(&batched_kernel<2>);
-        case 4: return reinterpret_cast<const void*>(&batched_kernel<4>);
-        case 8: return reinterpret_cast<const void*>(&batched_kernel<8>);
-        default: return nullptr;
+        case 1: return reinterpret_cast<const void*>(&batched_kernel<1, false>);
+        case 2: return reinterpret_cast<const void*>(&batched_kernel<2, false>);
+        case 4: return reinterpret_cast<const void*>(&batched_kernel<4, false>);
+        default: return reinterpret_cast<const void*>(&batched_kernel<8, false>);
     }
 }
 
@@ -1267,11 +1297,19 @@ int packed_occupancy(int K, int fmode, int layout, int threads, size_t lds, int*
     return FP_OK;
 }
 
-int batched_occupancy(int K, int threads, size_t lds, int* blocks_per_cu) {
-    const void* fn = pick_batched(K);
+bool jobs_blocks_only(const JobDesc* jobs, int32_t n_jobs) {
+    for (int32_t i = 0; i < n_jobs; i++)
+        if (jobs[i].layout < FP_LAYOUT_BLOCKED) return false;
+    return true;
+}
+
+size_t batched_job_budget(size_t lds_block) { return lds_block > kItemSlotBytes ? lds_block - kItemSlotBytes : 0; }
+
+int batched_occupancy(int K, bool blocks_only, int threads, size_t lds, int* blocks_per_cu) {
+    const void* fn = pick_batched(K, blocks_only);
     if (!fn) return fp_set_error(FP_EINVAL, "cursors must be 1, 2, 4 or 8");
     int occ = 0;
-    hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, fn, threads, lds);
+    hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, fn, threads, round16(lds) + kItemSlotBytes);
     *blocks_per_cu = (e == hipSuccess && occ > 0) ? occ : 1;
     return FP_OK;
 }
@@ -1346,12 +1384,13 @@ int launch_packed(const JobDesc& j, int K, int threads, int blocks, hipStream_t 
     return FP_OK;
 }
 
-int launch_batched(const JobDesc* jobs, const WorkItem* items, int32_t n_items, int32_t* counter, int K, int threads,
-                   size_t lds_bytes, int blocks, hipStream_t s) {
-    const void* fn = pick_batched(K);
+int launch_batched(const JobDesc* jobs, const WorkItem* items, int32_t n_items, int32_t* counter, int K,
+                   bool blocks_only, int threads, size_t lds_bytes, int blocks, hipStream_t s) {
+    const void* fn = pick_batched(K, blocks_only);
     if (!fn) return fp_set_error(FP_EINVAL, "cursors must be 1, 2, 4 or 8");
-    void* args[] = {&jobs, &items, &n_items, &counter};
-    hipError_t e = hipLaunchKernel(fn, dim3(blocks), dim3(threads), args, lds_bytes, s);
+    int32_t item_slot = (int32_t)round16(lds_bytes);
+    void* args[] = {&jobs, &items, &n_items, &counter, &item_slot};
+    hipError_t e = hipLaunchKernel(fn, dim3(blocks), dim3(threads), args, (size_t)item_slot + kItemSlotBytes, s);
     if (e != hipSuccess) return fp_set_error(FP_EHIP, "batched_kernel launch: %s", hipGetErrorString(e));
     return FP_OK;
 }
