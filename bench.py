@@ -259,8 +259,13 @@ def leg_batched(args, fp, synth, torch, np, n_forests=64):
         cls = torch.empty((len(X),), dtype=torch.int32, device="cuda")
         jobs.append({"forest": f, "Xd": Xd, "packed": p, "votes": votes, "cls": cls, "tried": res["n_tried"]})
     log(f"batched: {n_forests} forests trained and tuned in {time.perf_counter() - t0:.1f} s")
+    # the plan searches each job's launch on its whole batch (the autotuner
+    # timed packings on a 16,384-row sample); tunes are kept per forest and
+    # batch-size bucket
+    t1 = time.perf_counter()
     plan = fp.fp_plan_create([(j["packed"], j["Xd"], j["votes"], j["cls"]) for j in jobs],
-                             block_threads=threads, cursors=cursors)
+                             block_threads=threads, cursors=cursors, autotune=True)
+    plan_s = time.perf_counter() - t1
     rows = sum(int(j["Xd"].shape[0]) for j in jobs)
     ms, _ = time_steps(lambda: fp.fp_predict_batched(plan), 10, 2, torch)
     naive = []
@@ -285,7 +290,8 @@ def leg_batched(args, fp, synth, torch, np, n_forests=64):
            "naive": {"ms_per_step": ms_naive, "value": rows / (ms_naive / 1e3), "launches": n_forests},
            "speedup_vs_naive": ms_naive / ms, "bit_exact_vs_naive_all_rows": bool(exact),
            "layouts_chosen": {LAYOUT_NAMES[k]: int(c) for k, c in enumerate(np.bincount(layouts, minlength=5)) if c},
-           "autotune_candidates_timed": int(sum(j["tried"] for j in jobs))}
+           "autotune_candidates_timed": int(sum(j["tried"] for j in jobs)), "plan_create_s": plan_s,
+           "plan": fp.fp_plan_info_get(plan)}
     log(f"batched: graph replay {ms:.3f} ms = {rows / ms / 1e3:.2f} M obs/s; naive {n_forests} launches {ms_naive:.3f} ms "
         f"({ms_naive / ms:.2f}x), exact={exact}")
     return out

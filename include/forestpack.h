@@ -469,7 +469,7 @@ typedef struct fp_plan_opts {
     int32_t cursors;        /* 0: 2 (two walks per lane in node layouts; block
                                layouts walk one block per lane) */
     int32_t use_graph;      /* 1 (default when opts is NULL): capture a hipGraph; 0: plain launches */
-    int32_t items_per_block;/* work items per persistent workgroup to aim for (0: 4) */
+    int32_t items_per_block;/* work items per persistent workgroup to aim for (0: 16) */
     int64_t lds_budget;     /* LDS bytes per workgroup (0: half of a CU's LDS) */
     int32_t autotune;       /* 1 (default when opts is NULL): each job with rows
                                uses the tune recorded for (its forest, its size

@@ -59,7 +59,7 @@ extern "C" int fp_predict_batched_noalloc(const fp_job* jobs, int32_t n_jobs, co
     if (rc) return rc;
     const int threads = opts && opts->block_threads > 0 ? opts->block_threads : 1024;
     const int K = opts && opts->cursors > 0 ? opts->cursors : 2;
-    const int ipb = opts && opts->items_per_block > 0 ? opts->items_per_block : 4;
+    const int ipb = opts && opts->items_per_block > 0 ? opts->items_per_block : fp::kDefaultItemsPerBlock;
     if (threads % 64 || threads < 64 || threads > 1024)
         return fp_set_error(FP_EINVAL, "block_threads %d must be a multiple of 64 in [64, 1024]", threads);
     if (K != 1 && K != 2 && K != 4 && K != 8) return fp_set_error(FP_EINVAL, "cursors must be 1, 2, 4 or 8");

@@ -132,7 +132,7 @@ extern "C" int fp_plan_create(const fp_job* jobs, int32_t n_jobs, const fp_plan_
         p->K = opts && opts->cursors > 0 ? opts->cursors : 2;
         p->use_graph = opts ? opts->use_graph != 0 : true;
         const bool autotune = opts ? opts->autotune != 0 : true;
-        const int items_per_block = opts && opts->items_per_block > 0 ? opts->items_per_block : 4;
+        const int items_per_block = opts && opts->items_per_block > 0 ? opts->items_per_block : fp::kDefaultItemsPerBlock;
         if (p->threads % 64 || p->threads < 64 || p->threads > 1024)
             return fp_set_error(FP_EINVAL, "block_threads %d must be a multiple of 64 in [64, 1024]", p->threads);
         if (p->K != 1 && p->K != 2 && p->K != 4 && p->K != 8)
