@@ -441,7 +441,7 @@ def tabular(n_train: int = 1_000_000, n_trees: int = 1024, n_predict: int = 10_0
             imbalanced: bool = False) -> Workload:
     """28-feature binary tabular rows; 1024 trees, mtry 5, min leaf 1; 1M train, 10M predict.
     imbalanced: about 10% positives (label logit shifted by 3.35), where the
-    splits are more lopsided and Stat has more to gain (Sec. IV-A)."""
+    splits are more lopsided and Stat has more to gain (Sec. IV-C)."""
     name = "tabular" if (n_train, n_trees) == (1_000_000, 1024) else f"tabular_{n_train}_{n_trees}"
     if imbalanced:
         name += "_imb"
