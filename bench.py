@@ -80,12 +80,10 @@ def traffic_file(workload: str) -> str:
     return os.path.join(ROOT, "profiles", f"packed_kernel_{workload}_traffic.txt")
 
 
-def read_traffic(workload: str, tune: dict | None = None):
-    """HBM bytes per step of the workload's packed kernel (all the step's
-    launches: one per tree pass) measured by rocprofv3 --pmc (FETCH_SIZE,
-    WRITE_SIZE, scaled by a copy-kernel calibration); None when missing,
-    taken on a different kernel source, or (when the record names its
-    launch) with a launch other than `tune`."""
+def read_traffic_record(workload: str, tune: dict | None = None) -> dict | None:
+    """The workload's counter record (profiles/packed_kernel_<workload>_traffic.txt)
+    as a dict, or None when missing, taken on a different kernel source, or
+    (when the record names its launch) with a launch other than `tune`."""
     path = traffic_file(workload)
     if not os.path.exists(path):
         return None
@@ -102,6 +100,17 @@ def read_traffic(workload: str, tune: dict | None = None):
                 return None
         except ValueError:
             return None
+    return vals
+
+
+def read_traffic(workload: str, tune: dict | None = None):
+    """HBM bytes per step of the workload's packed kernel (all the step's
+    launches: one per tree pass) measured by rocprofv3 --pmc (FETCH_SIZE,
+    WRITE_SIZE, scaled by a copy-kernel calibration); None when the record
+    is missing or does not match (read_traffic_record)."""
+    vals = read_traffic_record(workload, tune)
+    if vals is None:
+        return None
     try:
         if "fetch_bytes_per_step" in vals:
             return float(vals["fetch_bytes_per_step"]) + float(vals["write_bytes_per_step"])
@@ -233,10 +242,16 @@ def roofline(res, workload):
     algo = n * (F * 4 + C * 4 + 4) + res["packed_bytes"]
     achieved = algo / (res["ms_per_step"] / 1e3) / 1e9
     traffic = read_traffic(workload, res.get("tune"))
+    rec = read_traffic_record(workload, res.get("tune")) or {}
+    try:
+        l2 = float(rec["l2_hit_rate"])
+    except (KeyError, ValueError):
+        l2 = None
     return {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
             "algorithmic_bytes_per_launch": algo,
-            "traffic_over_algorithmic": traffic / algo if traffic else None}
+            "traffic_over_algorithmic": traffic / algo if traffic else None,
+            "l2_hit_rate": l2}
 
 
 def leg_batched(args, fp, synth, torch, np, n_forests=64):
@@ -672,6 +687,11 @@ def headline(args, fp, torch, np, presets, tab_w):
         },
         "naive": res["naive"],
         "speedup_vs_naive": res["speedup_vs_naive"],
+        # context, not a target: the paper's own measurements, on CPUs
+        "paper_reported": {"speedup_over_ranger_cpp": 4, "speedup_over_r_rerf": 50,
+                           "hardware": "4 x Intel Xeon E7-4860 v2, 2.6 GHz (single-core experiments); "
+                                       "AWS t2.xlarge nodes (multi-node)",
+                           "where": "Sec. I (speedups), Sec. IV-A (hardware)"},
         "bit_exact_vs_naive_all_rows": res["bit_exact_vs_naive_all_rows"],
         "roofline": rl,
         "vmem_ceiling": vm,
