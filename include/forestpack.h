@@ -595,8 +595,11 @@ int fp_server_create(const fp_server_opts *opts, fp_server **out);
  * server's device (the CPU fake executor needs no upload); *forest_id
  * receives its id.  Its fp_tune (rows_per_block, tree_groups, tree_passes,
  * lds_top_nodes, feature_lds, refill_lanes) is used for its requests; its
- * tables must fit the server's LDS budget.  Errors: FP_EINVAL (NULL, naive
- * layout), FP_ENODEV (not uploaded, other device), FP_E2BIG (LDS). */
+ * tables must fit the server's LDS budget.  Requests are small, so small
+ * tiles (16-32 rows) and, for a forest of many bins, tree groups spread a
+ * request over more workgroups and cut its latency (tree passes run as
+ * concurrent groups here).  Errors: FP_EINVAL (NULL, naive layout),
+ * FP_ENODEV (not uploaded, other device), FP_E2BIG (LDS). */
 int fp_server_add_forest(fp_server *s, const fp_packed *forest, int32_t *forest_id);
 
 /* Queue a request: rows X_host [n_rows][ld] (host fp32, copied before return).
