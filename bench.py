@@ -538,9 +538,14 @@ def ladder(args, fp, synth, torch):
         r["eu_model_ms"] = miss * (r["expected_fetches"] - r["well_used_nodes"]) / r["eu"]  # Eq. 2
         log(f"{r['name']:9s} measured {r['ms']:9.3f} ms, Eq. 2 estimate {r['eu_model_ms']:9.3f} ms")
     # the autotuner's cost-model prior (Eq. 2 with EU) on the same forest: the
-    # score of every candidate packing beside the time of the ones it timed
+    # score of every candidate packing beside the time of the ones it timed.
+    # It packs every candidate, so a forest of more than 128 trees is tuned
+    # on its first 128 (packing the 1,024-tree forest 66 times takes half an
+    # hour of host time)
     sample = min(n, 65536)
-    tuned = fp.fp_autotune(forest, Xd[:sample], block_threads=1024, sample_rows=sample)
+    tuned_forest = forest if forest.n_trees <= 128 else forest.subset(range(128))
+    log(f"autotune on {tuned_forest.n_trees} trees, {sample} rows: packing and scoring every candidate")
+    tuned = fp.fp_autotune(tuned_forest, Xd[:sample], block_threads=1024, sample_rows=sample)
     for t in sorted(tuned["trials"], key=lambda t: (t["pack"]["layout"], t["model_cost"])):
         pk = t["pack"]
         log(f"autotune {LAYOUT_NAMES[pk['layout']]:9s} B={pk['bin_size']:5d} D={pk['interleave_depth']}  "
@@ -549,7 +554,7 @@ def ladder(args, fp, synth, torch):
         f"{LAYOUT_NAMES[tuned['pack']['layout']]} B={tuned['pack']['bin_size']} D={tuned['pack']['interleave_depth']} "
         f"{tuned['tune']} at {tuned['best_ms']:.3f} ms per {sample} rows")
     print(json.dumps({"ladder": args.ladder, "n_rows": n, "n_trees": forest.n_trees, "steps": args.steps,
-                      "rungs": rungs, "autotune": tuned}), flush=True)
+                      "rungs": rungs, "autotune_trees": tuned_forest.n_trees, "autotune": tuned}), flush=True)
 
 
 def gather_ceiling(fp, torch, working_set: int, fetch_bytes: int, chains=(1, 2, 4)) -> dict:
