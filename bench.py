@@ -540,10 +540,10 @@ def ladder(args, fp, synth, torch):
     # the autotuner's cost-model prior (Eq. 2 with EU) on the same forest: the
     # score of every candidate packing beside the time of the ones it timed.
     # It packs every candidate, so a forest of more than 128 trees is tuned
-    # on its first 128 (packing the 1,024-tree forest 66 times takes half an
+    # on its first 32 (packing the 1,024-tree forest 66 times takes half an
     # hour of host time)
     sample = min(n, 65536)
-    tuned_forest = forest if forest.n_trees <= 128 else forest.subset(range(128))
+    tuned_forest = forest if forest.n_trees <= 128 else forest.subset(range(32))
     log(f"autotune on {tuned_forest.n_trees} trees, {sample} rows: packing and scoring every candidate")
     tuned = fp.fp_autotune(tuned_forest, Xd[:sample], block_threads=1024, sample_rows=sample)
     for t in sorted(tuned["trials"], key=lambda t: (t["pack"]["layout"], t["model_cost"])):
