@@ -79,7 +79,8 @@ class HipExecutor final : public fp::ServeExecutor {
         // one workgroup holds a CU: serving launches are small, and a launch
         // spread over more workgroups than CUs measured higher latency on
         // the 8-forest Poisson stream (p50 0.64 ms against 0.55 ms)
-        lds_block_ = fp::default_lds_block(dp_);
+        lds_block_ = std::min(fp::default_lds_block(dp_),
+                              fp::batched_job_budget(dp_.lds_per_block ? dp_.lds_per_block : 65536));
         hipError_t e = hipMalloc((void**)&d_x_, xcap);
         if (e == hipSuccess) e = hipMalloc((void**)&d_v_, vcap);
         if (e != hipSuccess) return fp_set_error(FP_ENOMEM, "hipMalloc staging: %s", hipGetErrorString(e));
