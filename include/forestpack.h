@@ -281,7 +281,11 @@ int fp_infer_cardinality(const fp_forest_view *forest, const float *X_dev, int64
  *                   refills and leave lanes idle longer
  *   lds_bytes       LDS one workgroup may use (0: half of a CU's, so that two
  *                   workgroups share a CU; capped at the device's per-block
- *                   limit); more LDS fits more observations per tile
+ *                   limit); more LDS fits more observations per tile.  A
+ *                   forest far larger than the caches walked in tree passes
+ *                   runs faster with a CU's whole LDS in one 1024-thread
+ *                   workgroup, which keeps one copy of the pass's first
+ *                   blocks per CU instead of two
  *   tree_passes     the bins are split into this many consecutive groups
  *                   that run one after the other, each group walked by every
  *                   workgroup over all rows in a launch of its own, the
