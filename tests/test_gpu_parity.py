@@ -89,6 +89,10 @@ TUNES = [
     {"rows_per_block": 40, "cursors": 1, "tree_passes": 4, "block_threads": 1024},
     {"rows_per_block": 8, "cursors": 4, "tree_passes": 2, "tree_groups": 2},
     {"rows_per_block": 24, "cursors": 1, "tree_passes": 9, "lds_top_nodes": -1},
+    # one workgroup per CU with the CU's whole LDS (the large-forest launch shape)
+    {"rows_per_block": 768, "cursors": 1, "block_threads": 1024, "refill_lanes": 24, "feature_lds": 1,
+     "tree_passes": 3, "lds_bytes": 163840},
+    {"rows_per_block": 200, "cursors": 2, "block_threads": 1024, "lds_bytes": 163840, "tree_groups": 2},
 ]
 
 
