@@ -353,8 +353,10 @@ int fp_predict_tuned(const fp_packed *p, const fp_tune *tune, const float *X_dev
 /*
  * The design experiment of Sec. III-A (Fig. 2) for a forest already packed:
  * times candidate launch parameters of p (rows per workgroup, workgroup
- * size, cursors, refill threshold, tree groups) on the first min(n_rows,
- * 2^18) rows of X_dev, records the fastest for p's bytes and the size bucket
+ * size, cursors, refill threshold, tree groups; with block_threads 0 also a
+ * CU's whole LDS for one 1024-thread workgroup and, for a forest larger than
+ * the last-level cache, tree passes) on the first min(n_rows, 2^18) rows of
+ * X_dev, records the fastest for p's bytes and the size bucket
  * ceil(log2(n_rows)) in the process-wide tune table (fp_predict then uses it
  * for batches of that bucket; fp_plan_create for jobs of that bucket when
  * block_threads and cursors match) and, when the FP_TUNE_CACHE environment

@@ -3,7 +3,8 @@
 // Sec. III-A settles the stripe width and interleave depth with a design
 // experiment on the target machine (Fig. 2); on the GPU the launch mapping
 // (rows per workgroup, workgroup size, cursors per lane, refill threshold,
-// tree groups) matters as much and depends on the batch size as well.
+// tree groups, LDS per workgroup, tree passes) matters as much and depends
+// on the batch size as well.
 // fp_tune_launch times candidate mappings of one packed forest on the
 // caller's rows and records the fastest for the batch's size bucket
 // (ceil(log2(n_rows))).  Records live in a process-wide table keyed by the
@@ -115,6 +116,9 @@ void append_line(const char* line) {
 
 namespace fp {
 
+// Forest bytes per tree pass that the launch search starts from.
+constexpr int64_t kPassBytes = int64_t(176) << 20;
+
 int32_t rows_bucket(int64_t n_rows) {
     int32_t b = 0;
     while (b < 62 && (int64_t(1) << b) < n_rows) b++;
@@ -174,7 +178,11 @@ void autotune_cache_put(uint64_t key, const fp_autotune_result& r) {
 // 2^18) and returns the fastest.  threads / cursors > 0 are kept fixed.
 int search_launch(const fp_packed* p, const float* X, int64_t n_rows, int64_t ld, int32_t threads, int32_t cursors,
                   hipStream_t stream, fp_tune* best_out, double* best_ms_out, int32_t* tried_out) {
-    const int64_t n = std::min<int64_t>(n_rows, int64_t(1) << 18);
+    // a forest larger than the last-level cache is timed on more rows: the
+    // launch shapes that suit it (tree passes, a CU's whole LDS) amortise
+    // per-pass costs over many tiles
+    const bool big = p->hdr.total_bytes > kPassBytes;
+    const int64_t n = std::min<int64_t>(n_rows, int64_t(1) << (big ? 20 : 18));
     const int C = p->hdr.n_classes;
     DevBuf votes;
     int rc = votes.ensure((size_t)std::max<int64_t>(n, 1) * C * sizeof(int32_t));
@@ -252,23 +260,48 @@ int search_launch(const fp_packed* p, const float* X, int64_t n_rows, int64_t ld
         t.tree_groups = g;
         if ((rc = time_one(t))) return rc;
     }
-    // pass 4 (single-forest searches, whose workgroup size is free, with
-    // 1024-thread workgroups): one workgroup per CU holding all of the CU's
-    // LDS, so that its bin tops are not duplicated across two workgroups, at
-    // the same tile and a tile half as large again.  A plan's workgroups
-    // share one LDS budget, so plans (threads fixed) skip it.
-    const fp_tune p3 = best_t;
+    // pass 4 (single-forest searches, forests larger than the last-level
+    // cache): tree passes, so that each pass's bins (about kPassBytes of
+    // forest, a share of MI355X's 256 MB MALL) stay cached while every row
+    // walks them; around that count, half and twice it
+    if (threads <= 0 && big && p->hdr.n_bins >= 2) {
+        const fp_tune p3 = best_t;
+        const int64_t base = std::min<int64_t>(p->hdr.n_bins, (p->hdr.total_bytes + kPassBytes - 1) / kPassBytes);
+        for (int64_t P : {base / 2, base, 2 * base}) {
+            if (P < 2 || P > p->hdr.n_bins) continue;
+            fp_tune t = p3;
+            t.tree_passes = (int32_t)P;
+            t.tree_groups = 1;
+            if ((rc = time_one(t))) return rc;
+        }
+    }
+    // pass 5 (single-forest searches, whose workgroup size is free): one
+    // 1024-thread workgroup per CU holding all of the CU's LDS, so that its
+    // bin tops are not duplicated across workgroups, at the tile found so
+    // far and at one 1.5 and 3 times as large (what does not fit is skipped).
+    // A plan's workgroups share one LDS budget, so plans (threads fixed)
+    // skip it.
     int dev = 0;
     DeviceProps dp;
-    if (threads <= 0 && p3.block_threads == 1024 && current_device(&dev) == FP_OK && device_props(dev, &dp) == FP_OK &&
+    if (threads <= 0 && current_device(&dev) == FP_OK && device_props(dev, &dp) == FP_OK &&
         dp.lds_per_block > (size_t)default_lds_block(dp)) {
-        for (int grow = 0; grow < 2; grow++) {
-            fp_tune t = p3;
+        const fp_tune p4 = best_t;
+        for (int grow : {2, 3, 6}) {
+            fp_tune t = p4;
+            t.block_threads = 1024;
             t.lds_bytes = (int32_t)dp.lds_per_block;
-            if (grow) t.rows_per_block = std::min(4096, t.rows_per_block + t.rows_per_block / 2);
+            t.rows_per_block = std::min(4096, t.rows_per_block * grow / 2);
             if (t.rows_per_block > 2 * n) break;
             if ((rc = time_one(t))) return rc;
         }
+        const fp_tune p5 = best_t;
+        if (p5.lds_bytes > 0)
+            for (int rl : {16, 24}) {
+                if (rl == p5.refill_lanes) continue;
+                fp_tune t = p5;
+                t.refill_lanes = rl;
+                if ((rc = time_one(t))) return rc;
+            }
     }
     *best_out = best_t;
     *best_ms_out = best;
